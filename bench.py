@@ -1,0 +1,276 @@
+"""Benchmark: temporal edges traversed per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--mode batch|single] [--no-cpu] [--serve]
+
+A step answers every query of the workload once: the earliest-arrival
+queries of the R-MAT scale-20 graph (2^25 edges, 64 sources, t_alpha in the
+first half of the span, t_omega = max) by default.  The graph and the
+queries are synthetic and resident in HBM before timing starts.
+
+value = sum over queries of the temporal edges each traverses (edges whose
+tail is reached, departing no earlier than the tail's earliest arrival and
+t_alpha, arriving by t_omega; counted on the GPU from the result) times
+steps, divided by the wall time of the timed steps.
+
+Printed as one JSON line, with the dominant kernel's roofline figures
+measured with HIP events over the timed steps, and the CPU oracle timed on
+a bounded sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20-32m")
+    ap.add_argument("--mode", choices=["batch", "single"], default="batch")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve", action="store_true", help="also run the serving sweep")
+    ap.add_argument("--extras", action="store_true", help="also time LD/F and one-at-a-time EA")
+    ap.add_argument("--tune", action="store_true", help="autotune before timing")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2401_02563_amd as K
+    from workloads import CONFIGS, make_graph, make_queries
+
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[args.workload]
+    t0 = time.time()
+    g = make_graph(args.workload)
+    srcs, ta, tw = make_queries(args.workload, g)
+    log(f"generated {args.workload}: n={g.n} m={g.m} q={len(srcs)} in {time.time() - t0:.1f}s")
+    dev = [K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)]
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    G = K.kairos_graph_build(*dev, g.n)
+    build_s = time.perf_counter() - tb
+    del dev
+    log(f"index built in {build_s * 1e3:.1f} ms")
+    q = len(srcs)
+    out = torch.empty(q * g.n, dtype=torch.int32, device="cuda")
+    one = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    if args.tune:
+        best = K.kairos_autotune(G, srcs[: min(q, 16)], ta[: min(q, 16)], tw[: min(q, 16)])
+        log(f"autotuned: {best}")
+
+    def step():
+        if args.mode == "batch":
+            K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        else:
+            for i in range(q):
+                K.kairos_earliest_arrival(G, int(srcs[i]), int(ta[i]), int(tw[i]), out[i * g.n:(i + 1) * g.n])
+
+    # traversed edges per query, from the GPU result (not timed)
+    step()
+    torch.cuda.synchronize()
+    etrav = [K.kairos_traversed_edges(G, int(ta[i]), int(tw[i]), out[i * g.n:(i + 1) * g.n]) for i in range(q)]
+    etrav_total = int(sum(etrav))
+    log(f"traversed edges per step: {etrav_total}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K.kairos_profile_enable(G, True)
+    K.kairos_profile_read(G)  # reset
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = K.kairos_profile_read(G)
+    K.kairos_profile_enable(G, False)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = etrav_total * args.steps / elapsed
+
+    # dominant kernel: push (frontier expansion) or chunk (split adjacencies)
+    push_bytes = 8 * prof["edges_scanned"] + 16 * prof["items"] + 8 * prof["relaxations"]
+    chunk_bytes = 8 * prof["chunk_edges"]
+    kern = "push" if prof["ms_push"] >= prof["ms_chunk"] else "chunk"
+    kb = push_bytes if kern == "push" else chunk_bytes
+    launches = max(1, prof[f"launches_{kern}"])
+    avg_ms = prof[f"ms_{kern}"] / launches
+    achieved = (kb / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "kernel": f"{kern}_kernel", "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": launches,
+        "alg_bytes_per_launch": int(kb / launches),
+        "push_ms": round(prof["ms_push"], 3), "chunk_ms": round(prof["ms_chunk"], 3),
+        "push_gbs": round(push_bytes / max(prof["ms_push"], 1e-9) / 1e6, 1),
+        "chunk_gbs": round(chunk_bytes / max(prof["ms_chunk"], 1e-9) / 1e6, 1),
+    }
+
+    extra = {}
+    if args.extras:
+        extra.update(time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav))
+    if args.serve:
+        extra["serving"] = serve_sweep(K, torch, G, g, args.workload)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(g, srcs, ta, tw, etrav, args.cpu_seconds)
+
+    line = {
+        "metric": "temporal edges traversed/s", "value": value, "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "queries_per_step": q,
+                   "mode": args.mode, "window": cfg["window"]},
+        "queries_per_s": q * args.steps / elapsed,
+        "build_ms": round(build_s * 1e3, 2), "build_edges_per_s": g.m / build_s,
+        "traversed_edges_per_step": etrav_total,
+        "rounds_per_step": prof["rounds"] / args.steps,
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(line), flush=True)
+    G.free()
+
+
+def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
+    res = {}
+    q = len(srcs)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(q):
+        K.kairos_earliest_arrival(G, int(srcs[i]), int(ta[i]), int(tw[i]), one)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    res["single_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt, "ms_per_query": dt / q * 1e3}
+    t = time.perf_counter()
+    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    res["batch_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt}
+    k = min(8, q)
+    for kind, fn in (("latest_departure", K.kairos_latest_departure), ("fastest", K.kairos_fastest)):
+        t = time.perf_counter()
+        for i in range(k):
+            fn(G, int(srcs[i]), int(ta[i]), int(tw[i]), one)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        res[kind] = {"ms_per_query": dt / k * 1e3, "queries": k}
+    return res
+
+
+def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=2000):
+    """Open-loop Poisson arrivals: continuous-batching server versus a FIFO
+    server answering one query at a time, on the same trace."""
+    from workloads import poisson_arrivals
+    from workloads.configs import make_kinds
+    srcs, ta, tw = make_queries_log(name, g, count)
+    kinds = make_kinds("serve-rmat20", count)
+    outs = torch.empty((count, g.n), dtype=torch.int32, device="cuda")
+    res = []
+    for rate in rates:
+        arr = poisson_arrivals(rate, count, 105 + rate)
+        srv = K.kairos_server_create(G, max_slots=64, queue_capacity=1 << 20)
+        lat = {}
+        done = 0
+        start = time.perf_counter()
+        i = 0
+        t_sub = {}
+        while done < count:
+            now = time.perf_counter() - start
+            while i < count and arr[i] <= now:
+                tk = K.kairos_server_submit(srv, int(kinds[i]), int(srcs[i]), int(ta[i]), int(tw[i]), outs[i])
+                t_sub[tk] = arr[i]
+                i += 1
+            for c in K.kairos_server_poll(srv, 4096):
+                lat[c["ticket"]] = (c["t_done_ns"] - c["t_submit_ns"]) * 1e-9
+                done += 1
+            time.sleep(0.0001)
+        wall = time.perf_counter() - start
+        K.kairos_server_free(srv)
+        lv = np.array(list(lat.values()))
+        # FIFO one-at-a-time on the same trace (virtual clock)
+        fifo_lat = []
+        clock = 0.0
+        fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
+        n_fifo = min(count, 400)
+        for j in range(n_fifo):
+            clock = max(clock, arr[j])
+            t = time.perf_counter()
+            fns[kinds[j]](G, int(srcs[j]), int(ta[j]), int(tw[j]), outs[j])
+            clock += time.perf_counter() - t
+            fifo_lat.append(clock - arr[j])
+        fl = np.array(fifo_lat)
+        res.append({"rate": rate, "served_qps": count / wall, "p50_ms": float(np.percentile(lv, 50) * 1e3),
+                    "p99_ms": float(np.percentile(lv, 99) * 1e3),
+                    "fifo_qps": n_fifo / clock if clock > 0 else None,
+                    "fifo_p50_ms": float(np.percentile(fl, 50) * 1e3),
+                    "fifo_p99_ms": float(np.percentile(fl, 99) * 1e3), "fifo_queries": n_fifo})
+        log(f"serve rate={rate}: {res[-1]}")
+    return res
+
+
+def make_queries_log(name, g, count):
+    from workloads.gen import log_uniform_windows, sample_sources
+    from workloads import CONFIGS
+    c = CONFIGS["serve-rmat20"]
+    ss = np.random.SeedSequence(c["qseed"]).spawn(2)
+    src = sample_sources(g, count, int(ss[0].generate_state(1)[0]))
+    ta, tw = log_uniform_windows(count, c["t_lo"], c["t_hi"], int(ss[1].generate_state(1)[0]))
+    return src, ta, tw
+
+
+def cpu_baseline(g, srcs, ta, tw, etrav, seconds):
+    """The CPU oracle (one-pass scan over edges sorted by departure time),
+    one query per host thread, on as many of the workload's queries as fit
+    in about `seconds` of wall time."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t = time.perf_counter()
+    se = oracle.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    sort_s = time.perf_counter() - t
+    # probe one query to size the sample
+    t = time.perf_counter()
+    oracle.earliest_arrival(se, srcs[0], ta[0], tw[0])
+    per = max(time.perf_counter() - t, 1e-4)
+    k = int(min(len(srcs), max(cores, seconds * cores / per)))
+    k = max(1, min(k, len(srcs)))
+    t = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda i: oracle.earliest_arrival(se, srcs[i], ta[i], tw[i]), range(k)))
+    dt = time.perf_counter() - t
+    edges = float(sum(etrav[:k]))
+    return {"value": edges / dt, "unit": "edges/s", "cores": cores, "kind": "oracle",
+            "queries_per_s": k / dt,
+            "sample": f"first {k} of {len(srcs)} queries of the workload, one per thread; "
+                      f"edges pre-sorted by departure once ({sort_s:.1f} s, not counted)"}
+
+
+if __name__ == "__main__":
+    main()

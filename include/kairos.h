@@ -1,0 +1,241 @@
+/*
+ * kairos.h -- C interface of libkairos, temporal minimal-path queries on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Model (paper §2.1): vertices 0..n-1; a temporal edge (u, v, t, lambda)
+ * departs u at time t and arrives at v at time a = t + lambda.  Times are
+ * uint32; 0xFFFFFFFF (KAIROS_INF) is reserved for "unreachable", so every
+ * finite time is <= 0xFFFFFFFE (KAIROS_TMAX).  lambda >= 1.
+ *
+ * A path from src is time-respecting when each edge departs no earlier than
+ * the previous one arrives (the non-strict "Succeeds" predicate of §2.2, as
+ * tested by the Update function of Alg. 2).  A query (src, [t_alpha,
+ * t_omega]) only uses edges with t >= t_alpha and a <= t_omega (the closed
+ * query interval of Alg. 2).  Outputs, per vertex v:
+ *   earliest arrival  EA[v] = min arrival at v            EA[src] = t_alpha
+ *   latest departure  LD[v] = max departure from src       LD[src] = t_omega
+ *   fastest           F[v]  = min (arrival - departure)    F[src]  = 0
+ * (the minimal temporal paths of §2.3 and Table 4); unreachable vertices
+ * get KAIROS_INF.  These values are unique, so results do not depend on
+ * scheduling.
+ *
+ * Conventions
+ *  - Pointers named "device" must point to device memory of the current HIP
+ *    device (for example a torch tensor's data_ptr()); "host" pointers to
+ *    host memory.  uint32 data may be stored in int32 tensors.
+ *  - Every call returns a kairos_status.  On an argument error nothing is
+ *    written to any output.
+ *  - The library owns every handle and the device memory behind it; the
+ *    caller owns the buffers it passes in.
+ *  - Query calls are synchronous: on return the output is complete.
+ *  - A graph is immutable after build and may be queried from several host
+ *    threads at once; each concurrent query takes its own scratch state.
+ */
+#ifndef KAIROS_H
+#define KAIROS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KAIROS_INF 0xFFFFFFFFu
+#define KAIROS_TMAX 0xFFFFFFFEu
+
+typedef enum kairos_status {
+    KAIROS_OK = 0,
+    KAIROS_ERR_INVALID = 1, /* null pointer, n == 0, unknown kind or option  */
+    KAIROS_ERR_RANGE = 2,   /* id >= n, lambda == 0, t + lambda > TMAX,
+                               t_alpha > t_omega, t_omega > TMAX, m >= 2^32 */
+    KAIROS_ERR_NOMEM = 3,   /* device or host allocation failed             */
+    KAIROS_ERR_DEVICE = 4,  /* a HIP call or kernel failed                  */
+    KAIROS_ERR_BUSY = 5     /* a server queue is full                       */
+} kairos_status;
+
+typedef struct kairos_graph kairos_graph;
+
+/* ---------------------------------------------------------------- build --
+ * Temporal CSR index (§4.2), built on the device.  Out-edges are grouped by
+ * tail and sorted by (tail, t, a, head); in-edges grouped by head and sorted
+ * by (head, a, t, tail).  Sorting each adjacency by time is what lets a
+ * traversal skip every edge that departs before the tail's arrival (the job
+ * the paper gives its interval index, §3.1 and §4.3) by binary search.
+ *
+ *   src, dst, t, lambda  device, m entries each, read only; the library
+ *                        copies what it needs, so they may be freed on return.
+ *   m                    number of edges (0 allowed, < 2^32).
+ *   n                    number of vertices (>= 1).
+ *   hip_stream           hipStream_t for all work on this graph, or NULL for
+ *                        library-owned streams.
+ *   out                  host; receives the handle.
+ * Errors: INVALID (null pointer with m > 0, null out, n == 0), RANGE (an id
+ * >= n, lambda == 0, t + lambda > TMAX; checked on the device), NOMEM,
+ * DEVICE.  On error *out is left unchanged.
+ */
+int kairos_graph_build(const uint32_t *src, const uint32_t *dst, const uint32_t *t,
+                       const uint32_t *lambda, uint64_t m, uint32_t n, void *hip_stream,
+                       kairos_graph **out);
+
+/* Releases the graph and all device memory it holds.  NULL is ignored. */
+void kairos_graph_free(kairos_graph *g);
+
+/* n, m and the device bytes held by the index (any pointer may be NULL). */
+int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t *device_bytes);
+
+/* Device pointers of the index, for inspection (read only, owned by g):
+ *   off_out[n+1]  first out-edge of each tail;  out-edge e has
+ *   t_out[e], and dst_a_out[2e], dst_a_out[2e+1] = head, arrival;
+ *   off_in[n+1]   first in-edge of each head;   in-edge e has
+ *   a_in[e], and src_t_in[2e], src_t_in[2e+1] = tail, departure. */
+typedef struct kairos_index_view {
+    const uint32_t *off_out, *t_out, *dst_a_out;
+    const uint32_t *off_in, *a_in, *src_t_in;
+} kairos_index_view;
+int kairos_graph_index(const kairos_graph *g, kairos_index_view *view);
+
+/* -------------------------------------------------------------- queries --
+ * Single-source queries (Alg. 2 for earliest arrival; latest departure and
+ * fastest as named in §2.3 and Table 4).
+ *   src             vertex id < n.
+ *   t_alpha,t_omega query interval, t_alpha <= t_omega <= TMAX.
+ *   out             device, n uint32, written in full.
+ * Errors: INVALID (g or out null), RANGE, NOMEM, DEVICE.
+ */
+int kairos_earliest_arrival(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                            uint32_t *out);
+int kairos_latest_departure(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                            uint32_t *out);
+int kairos_fastest(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                   uint32_t *out);
+
+/* q earliest-arrival queries answered together.
+ *   src, t_alpha, t_omega  host, q entries each.
+ *   out                    device, q*n uint32, query-major (row i = query i).
+ * Row i equals kairos_earliest_arrival for query i.  q == 0 is a no-op. */
+int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *src,
+                                  const uint32_t *t_alpha, const uint32_t *t_omega,
+                                  uint32_t *out);
+
+/* Temporal edges traversed by an earliest-arrival result: the number of
+ * edges (u, v, t, a) with ea[u] finite, t >= max(ea[u], t_alpha) and
+ * a <= t_omega.  ea: device, n entries (a result of the calls above);
+ * count: host.  This is the numerator of the traversal rate. */
+int kairos_traversed_edges(kairos_graph *g, uint32_t t_alpha, uint32_t t_omega,
+                           const uint32_t *ea, uint64_t *count);
+
+/* --------------------------------------------------------------- tuning --
+ * Run-time parameters; they change speed, never results.  The paper derives
+ * its equivalents (cost constants, selectivity threshold, index cut-off,
+ * parallel grain; §5.1, §6.1) by experiment; kairos_autotune measures them
+ * on a sample of the caller's own queries. */
+typedef struct kairos_tuning {
+    uint32_t block;          /* threads per workgroup of the push kernel: 256 or 512 */
+    uint32_t chunk;          /* edges per chunk when a long adjacency is split     */
+    uint32_t split;          /* adjacency ranges at least this long are split      */
+    uint32_t pull_alpha;     /* pull when frontier out-edges > m / pull_alpha;
+                                0 disables the pull kernel                          */
+    uint32_t pull_beta;      /* back to push when frontier < n / pull_beta          */
+    uint32_t rounds_per_sync;/* push rounds queued before the host checks the
+                                frontier (1 = check every round)                    */
+    uint32_t batch_persistent; /* 1: batched queries run in one persistent launch  */
+    uint32_t sweep_group;    /* departure times handled together by the
+                                latest-departure / fastest sweep                     */
+} kairos_tuning;
+
+int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);
+int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in);
+
+/* Grid search over the tuning space on q sample queries (host arrays, as in
+ * the batch call); keeps the fastest setting in g and copies it to *best
+ * (may be NULL).  Results never change; only time does. */
+int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
+                    const uint32_t *t_omega, kairos_tuning *best);
+
+/* ------------------------------------------------------------ profiling --
+ * When enabled, every kernel launch on g is bracketed by HIP events on the
+ * stream it runs on and its algorithmic work is counted on the device.
+ * Reading resolves the events (it synchronises g's streams) and resets. */
+typedef enum kairos_kernel_class {
+    KAIROS_K_PUSH = 0,  /* push temporal edge map: frontier expansion       */
+    KAIROS_K_PULL = 1,  /* pull temporal edge map                           */
+    KAIROS_K_INIT = 2,  /* per-query state initialisation and outputs       */
+    KAIROS_K_SORT = 3,  /* index build                                      */
+    KAIROS_K_CHUNK = 4, /* push temporal edge map: split long adjacencies   */
+    KAIROS_K_COUNT = 5
+} kairos_kernel_class;
+
+typedef struct kairos_profile {
+    uint64_t launches[KAIROS_K_COUNT];
+    double ms[KAIROS_K_COUNT];   /* summed event time                          */
+    uint64_t edges_scanned;      /* out-edges read by the push kernel (8 B each) */
+    uint64_t chunk_edges;        /* out-edges read by the chunk kernel (8 B each) */
+    uint64_t items;              /* frontier entries expanded by push          */
+    uint64_t relaxations;        /* successful atomic minimum updates          */
+    uint64_t pull_edges;         /* in-edges read by pull (12 B each)          */
+    uint64_t pull_vertices;      /* vertices examined by pull                  */
+    uint64_t rounds;             /* frontier rounds                            */
+} kairos_profile;
+
+int kairos_profile_enable(kairos_graph *g, int on);
+int kairos_profile_read(kairos_graph *g, kairos_profile *out);
+
+/* -------------------------------------------------------------- serving --
+ * Continuous batching: queries are admitted into slots as they arrive while
+ * others are on the device; each scheduler iteration runs one frontier round
+ * for every active slot in one launch, then retires finished slots.  A slot
+ * is admitted only when one is free and the device reports at least the
+ * slot's state size plus mem_reserve_bytes free.  The graph stays resident.
+ */
+typedef struct kairos_server kairos_server;
+
+typedef struct kairos_server_opts {
+    uint32_t max_slots;         /* concurrent queries on the device (>= 1)     */
+    uint32_t queue_capacity;    /* waiting queries before submit returns BUSY  */
+    uint64_t mem_reserve_bytes; /* device memory left free by admission        */
+    void *hip_stream;           /* stream for server work, NULL = own stream   */
+} kairos_server_opts;
+
+typedef struct kairos_completion {
+    uint64_t ticket;
+    int32_t status;             /* kairos_status of the query                  */
+    int32_t kind;               /* 0 EA, 1 LD, 2 F                             */
+    uint64_t t_submit_ns;       /* CLOCK_MONOTONIC at submit                   */
+    uint64_t t_done_ns;         /* CLOCK_MONOTONIC when the result was ready   */
+} kairos_completion;
+
+/* g must outlive the server. */
+int kairos_server_create(kairos_graph *g, const kairos_server_opts *opts, kairos_server **out);
+
+/* Never blocks.  kind: 0 earliest arrival, 1 latest departure, 2 fastest.
+ * out: device, n uint32; must stay valid until the completion is polled.
+ * Returns BUSY when the waiting queue is full, RANGE/INVALID for bad
+ * arguments (then no ticket is issued). */
+int kairos_server_submit(kairos_server *s, int kind, uint32_t src, uint32_t t_alpha,
+                         uint32_t t_omega, uint32_t *out, uint64_t *ticket);
+
+/* Copies up to cap finished queries into done (host) and their number into
+ * *n_done; never blocks. */
+int kairos_server_poll(kairos_server *s, kairos_completion *done, uint32_t cap, uint32_t *n_done);
+
+/* Waits for all submitted queries, stops the scheduler, frees the server. */
+void kairos_server_free(kairos_server *s);
+
+typedef struct kairos_server_stats {
+    uint64_t submitted, completed, iterations, admitted_waits_mem;
+    uint32_t active_slots, waiting, max_slots_seen;
+} kairos_server_stats;
+int kairos_server_stats_read(kairos_server *s, kairos_server_stats *out);
+
+/* Test hook: the server admits as if the device reported this many free
+ * bytes (UINT64_MAX restores the real query). */
+int kairos_server_set_free_bytes_override(kairos_server *s, uint64_t bytes);
+
+/* Static description of a status code. */
+const char *kairos_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KAIROS_H */

@@ -1,0 +1,290 @@
+// C entry points of libkairos: argument checks, handle lifetime, dispatch.
+#include "internal.h"
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+namespace kairos {
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line)
+{
+    static int verbose = -1;
+    if (verbose < 0) {
+        const char *s = std::getenv("KAIROS_LOG");
+        verbose = (s && *s && *s != '0') ? 1 : 0;
+    }
+    if (verbose) std::fprintf(stderr, "kairos: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+}
+
+void *dev_alloc(size_t bytes, uint64_t *account)
+{
+    void *p = nullptr;
+    if (bytes == 0) bytes = 4;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (account) *account += bytes;
+    return p;
+}
+
+void dev_free(void *p)
+{
+    if (p) hipFree(p);
+}
+
+}  // namespace kairos
+
+using namespace kairos;
+
+extern "C" {
+
+const char *kairos_status_string(int status)
+{
+    switch (status) {
+    case KAIROS_OK: return "ok";
+    case KAIROS_ERR_INVALID: return "invalid argument";
+    case KAIROS_ERR_RANGE: return "value out of range";
+    case KAIROS_ERR_NOMEM: return "out of memory";
+    case KAIROS_ERR_DEVICE: return "device error";
+    case KAIROS_ERR_BUSY: return "queue full";
+    default: return "unknown status";
+    }
+}
+
+static void graph_release(kairos_graph *g)
+{
+    if (!g) return;
+    for (Slot *s : g->free_slots) slot_destroy(s);
+    for (Slot *s : g->batch_slots) slot_destroy(s);
+    g->free_slots.clear();
+    g->batch_slots.clear();
+    {
+        std::lock_guard<std::mutex> lk(g->prof.mu);
+        for (auto &p : g->prof.pending) {
+            hipEventDestroy(p.second.first);
+            hipEventDestroy(p.second.second);
+        }
+        for (hipEvent_t e : g->prof.free_events) hipEventDestroy(e);
+        g->prof.pending.clear();
+        g->prof.free_events.clear();
+    }
+    dev_free(g->off_out);
+    dev_free(g->t_out);
+    dev_free(g->da_out);
+    dev_free(g->off_in);
+    dev_free(g->a_in);
+    dev_free(g->st_in);
+    delete g;
+}
+
+int kairos_graph_build(const uint32_t *src, const uint32_t *dst, const uint32_t *t, const uint32_t *lambda,
+                       uint64_t m, uint32_t n, void *hip_stream, kairos_graph **out)
+{
+    if (!out || n == 0) return KAIROS_ERR_INVALID;
+    if (m > 0 && (!src || !dst || !t || !lambda)) return KAIROS_ERR_INVALID;
+    if (m >= (1ull << 32)) return KAIROS_ERR_RANGE;
+    kairos_graph *g = new (std::nothrow) kairos_graph();
+    if (!g) return KAIROS_ERR_NOMEM;
+    g->n = n;
+    g->m = m;
+    g->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return KAIROS_ERR_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g->device) == hipSuccess && prop.multiProcessorCount > 0)
+        g->num_cus = prop.multiProcessorCount;
+    g->tuning = default_tuning(g);
+    hipStream_t st = g->stream;
+    bool own = false;
+    if (!st) {
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            delete g;
+            return KAIROS_ERR_DEVICE;
+        }
+        own = true;
+    }
+    int rc = build_index(g, src, dst, t, lambda, st);
+    hipStreamSynchronize(st);
+    if (own) hipStreamDestroy(st);
+    if (rc != KAIROS_OK) {
+        graph_release(g);
+        return rc;
+    }
+    *out = g;
+    return KAIROS_OK;
+}
+
+void kairos_graph_free(kairos_graph *g)
+{
+    graph_release(g);
+}
+
+int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t *device_bytes)
+{
+    if (!g) return KAIROS_ERR_INVALID;
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (device_bytes) *device_bytes = g->index_bytes;
+    return KAIROS_OK;
+}
+
+int kairos_graph_index(const kairos_graph *g, kairos_index_view *view)
+{
+    if (!g || !view) return KAIROS_ERR_INVALID;
+    view->off_out = g->off_out;
+    view->t_out = g->t_out;
+    view->dst_a_out = (const uint32_t *)g->da_out;
+    view->off_in = g->off_in;
+    view->a_in = g->a_in;
+    view->src_t_in = (const uint32_t *)g->st_in;
+    return KAIROS_OK;
+}
+
+static int check_query(const kairos_graph *g, uint32_t src, uint32_t ta, uint32_t tw)
+{
+    if (src >= g->n || ta > tw || tw > KAIROS_TMAX) return KAIROS_ERR_RANGE;
+    return KAIROS_OK;
+}
+
+static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+{
+    if (!g || !out) return KAIROS_ERR_INVALID;
+    int rc = check_query(g, src, ta, tw);
+    if (rc) return rc;
+    Slot *s = nullptr;
+    if ((rc = slot_acquire(g, 1, kind != 0, &s))) return rc;
+    rc = kind == 0 ? run_earliest_arrival(g, s, src, ta, tw, out) : run_sweep(g, s, kind, src, ta, tw, out);
+    if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    if (rc == KAIROS_OK) {
+        slot_release(g, s);
+    } else {
+        hipStreamSynchronize(s->stream);
+        slot_destroy(s);
+    }
+    return rc;
+}
+
+int kairos_earliest_arrival(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out)
+{
+    return single_query(g, 0, src, t_alpha, t_omega, out);
+}
+
+int kairos_latest_departure(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out)
+{
+    return single_query(g, 1, src, t_alpha, t_omega, out);
+}
+
+int kairos_fastest(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out)
+{
+    return single_query(g, 2, src, t_alpha, t_omega, out);
+}
+
+int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
+                                  const uint32_t *t_omega, uint32_t *out)
+{
+    if (!g) return KAIROS_ERR_INVALID;
+    if (q == 0) return KAIROS_OK;
+    if (!src || !t_alpha || !t_omega || !out) return KAIROS_ERR_INVALID;
+    for (uint32_t i = 0; i < q; ++i) {
+        int rc = check_query(g, src[i], t_alpha[i], t_omega[i]);
+        if (rc) return rc;
+    }
+    // queries per launch: q*n must fit the 32-bit frontier item encoding
+    const uint64_t per = std::max<uint64_t>(1, std::min<uint64_t>(q, 0xFFFFFFFEull / g->n));
+    for (uint64_t b = 0; b < q; b += per) {
+        const uint32_t k = (uint32_t)std::min<uint64_t>(per, q - b);
+        Slot *s = nullptr;
+        int rc = slot_acquire(g, k, false, &s);
+        if (rc) return rc;
+        rc = run_batch(g, s, k, src + b, t_alpha + b, t_omega + b, out + b * g->n);
+        if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+        if (rc == KAIROS_OK) {
+            slot_release(g, s);
+        } else {
+            hipStreamSynchronize(s->stream);
+            slot_destroy(s);
+            return rc;
+        }
+    }
+    return KAIROS_OK;
+}
+
+int kairos_traversed_edges(kairos_graph *g, uint32_t t_alpha, uint32_t t_omega, const uint32_t *ea,
+                           uint64_t *count)
+{
+    if (!g || !ea || !count) return KAIROS_ERR_INVALID;
+    if (t_alpha > t_omega || t_omega > KAIROS_TMAX) return KAIROS_ERR_RANGE;
+    return count_traversed(g, t_alpha, t_omega, ea, count);
+}
+
+int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out)
+{
+    if (!g || !out) return KAIROS_ERR_INVALID;
+    *out = g->tuning;
+    return KAIROS_OK;
+}
+
+int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
+{
+    if (!g || !in) return KAIROS_ERR_INVALID;
+    if ((in->block != 256 && in->block != 512) || in->chunk < 64 || in->split < 64 ||
+        in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64)
+        return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split;
+    g->tuning = *in;
+    if (resize) {
+        // chunk lists are sized from these values: drop cached scratch
+        for (Slot *s : g->free_slots) slot_destroy(s);
+        for (Slot *s : g->batch_slots) slot_destroy(s);
+        g->free_slots.clear();
+        g->batch_slots.clear();
+    }
+    return KAIROS_OK;
+}
+
+int kairos_profile_enable(kairos_graph *g, int on)
+{
+    if (!g) return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    g->prof.on = on != 0;
+    return KAIROS_OK;
+}
+
+int kairos_profile_read(kairos_graph *g, kairos_profile *out)
+{
+    if (!g || !out) return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    std::memset(out, 0, sizeof(*out));
+    for (auto &p : g->prof.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess)
+            g->prof.ms[p.first] += ms;
+        g->prof.free_events.push_back(p.second.first);
+        g->prof.free_events.push_back(p.second.second);
+    }
+    g->prof.pending.clear();
+    for (int k = 0; k < KAIROS_K_COUNT; ++k) {
+        out->launches[k] = g->prof.launches[k];
+        out->ms[k] = g->prof.ms[k];
+        g->prof.launches[k] = 0;
+        g->prof.ms[k] = 0;
+    }
+    out->edges_scanned = g->prof.edges;
+    out->chunk_edges = g->prof.chunk_edges;
+    out->items = g->prof.items;
+    out->relaxations = g->prof.relax;
+    out->pull_edges = g->prof.pull_edges;
+    out->pull_vertices = g->prof.pull_verts;
+    out->rounds = g->prof.rounds;
+    g->prof.edges = g->prof.chunk_edges = g->prof.items = g->prof.relax = g->prof.pull_edges = g->prof.pull_verts = 0;
+    g->prof.rounds = 0;
+    return KAIROS_OK;
+}
+
+}  // extern "C"

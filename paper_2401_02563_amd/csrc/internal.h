@@ -1,0 +1,159 @@
+// Internal declarations of libkairos (not part of the C interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/kairos.h"
+
+namespace kairos {
+
+constexpr uint32_t INF = 0xFFFFFFFFu;
+constexpr uint32_t TMAX = 0xFFFFFFFEu;
+
+// Return-on-error helpers for host code.
+#define KAIROS_HIP(call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) {                            \
+            kairos::note_hip_error(e_, #call, __FILE__, __LINE__); \
+            return KAIROS_ERR_DEVICE;                      \
+        }                                                  \
+    } while (0)
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+// Device allocation with byte accounting; returns nullptr on failure.
+void *dev_alloc(size_t bytes, uint64_t *account);
+void dev_free(void *p);
+
+// ---------------------------------------------------------------------------
+// Per-query (or per-batch) device state.  One slot holds room for qcap
+// queries over n vertices; the arrays are query-major (query i owns
+// [i*n, (i+1)*n)).
+struct Slot {
+    uint32_t qcap = 0;
+    uint32_t n = 0;
+    uint32_t *done = nullptr;    // qcap*n: lowest claimed out-edge per vertex, INF = unvisited
+    uint32_t *stamp = nullptr;   // qcap*n: round stamp used to enqueue a vertex once per round
+    uint32_t *queue[2] = {nullptr, nullptr}; // qcap*n each: frontier items q*n+u
+    uint4 *chunks = nullptr;     // split adjacency ranges {q, start, len, _}
+    uint64_t chunk_cap = 0;
+    uint4 *qp = nullptr;         // qcap: {src, t_alpha, t_omega, sweep departure}
+    uint32_t *arr = nullptr;     // n: arrival scratch for the sweep queries
+    uint32_t *fa = nullptr;      // n: fastest duration (sweep)
+    uint32_t *l1 = nullptr;      // n: latest departure + 1 (sweep), 0 = none
+    uint32_t *cnt = nullptr;     // device counters, see CNT_* below
+    unsigned long long *stats = nullptr; // device work counters, see ST_*
+    uint32_t *h_pin = nullptr;   // pinned host mirror for counter read-back
+    uint32_t stamp_next = 1;     // next round stamp value
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t bytes = 0;
+};
+
+// Counter layout (uint32 words) in Slot::cnt.
+enum : int {
+    CNT_FRONT = 0,   // [0..2] rotating frontier sizes
+    CNT_CHUNK = 3,   // [3..5] rotating chunk-list sizes
+    CNT_ERR = 6,     // sticky error bits
+    CNT_PULLVOL = 7, // [7..9] rotating: out-edges of the next frontier (saturating)
+    CNT_WORDS = 16
+};
+enum : int {
+    ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5,
+    ST_WORDS = 8
+};
+
+struct ProfileAcc {
+    bool on = false;
+    uint64_t launches[KAIROS_K_COUNT] = {};
+    double ms[KAIROS_K_COUNT] = {};
+    uint64_t edges = 0, chunk_edges = 0, items = 0, relax = 0, pull_edges = 0, pull_verts = 0, rounds = 0;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> free_events;
+    std::mutex mu;
+};
+
+}  // namespace kairos
+
+struct kairos_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    // out-index: edges grouped by tail, sorted by (tail, t, a, head)
+    uint32_t *off_out = nullptr;  // n+1
+    uint32_t *t_out = nullptr;    // m
+    uint2 *da_out = nullptr;      // m: {head, arrival}
+    // in-index: edges grouped by head, sorted by (head, a, t, tail)
+    uint32_t *off_in = nullptr;   // n+1
+    uint32_t *a_in = nullptr;     // m
+    uint2 *st_in = nullptr;       // m: {tail, departure}
+    uint32_t max_out_degree = 0;
+    uint64_t index_bytes = 0;
+    hipStream_t stream = nullptr; // caller's stream, or nullptr
+    int device = 0;
+    int num_cus = 256;
+    kairos_tuning tuning{};
+    std::mutex pool_mu;
+    std::vector<kairos::Slot *> free_slots;   // single-query slots
+    std::vector<kairos::Slot *> batch_slots;  // batch slots (any qcap)
+    kairos::ProfileAcc prof;
+};
+
+namespace kairos {
+
+// build.hip
+int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const uint32_t *t,
+                const uint32_t *lam, hipStream_t st);
+
+// traverse.hip
+int slot_acquire(kairos_graph *g, uint32_t qcap, bool sweep, Slot **out);
+void slot_release(kairos_graph *g, Slot *s);
+void slot_destroy(Slot *s);
+int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw,
+                         uint32_t *out);
+int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uint32_t tw,
+              uint32_t *out);
+int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
+              const uint32_t *tw, uint32_t *out);
+int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);
+
+// Device state of a multi-slot round loop driven by the server (query
+// slots q in [0, qcap), query-major arrays of qcap*n words).
+struct MultiState {
+    uint32_t qcap = 0, n = 0;
+    uint32_t *arr = nullptr, *done = nullptr, *stamp = nullptr, *fa = nullptr, *l1 = nullptr;
+    uint32_t *queue[2] = {nullptr, nullptr};  // queue[0] feeds the next round
+    uint32_t *cnt = nullptr;                  // CNT_WORDS counters, then qcap activity flags
+    uint4 *chunks = nullptr, *qp = nullptr;
+    uint64_t chunk_cap = 0;
+    unsigned long long *stats = nullptr;
+    uint32_t round = 0, stamp_next = 1;
+    hipStream_t stream = nullptr;
+};
+// One slot start or sweep step: qp[q] = {src, ta, tw, sdep}; the source
+// starts at sdep (ta when sdep == INF, a plain earliest-arrival query).
+struct Inject {
+    uint32_t q, src, ta, tw, sdep, pad0, pad1, pad2;
+};
+int multi_push_round(kairos_graph *g, MultiState *ms);
+int multi_inject(kairos_graph *g, MultiState *ms, const Inject *host_pinned, uint32_t count);
+int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count);
+int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32_t src, uint32_t tw,
+                   uint32_t *out);
+
+// profiling (traverse.hip)
+void prof_begin(kairos_graph *g, hipStream_t st, hipEvent_t *ev0);
+void prof_end(kairos_graph *g, hipStream_t st, int cls, hipEvent_t ev0);
+void prof_add_stats(kairos_graph *g, const unsigned long long *h);
+
+kairos_tuning default_tuning(const kairos_graph *g);
+
+}  // namespace kairos

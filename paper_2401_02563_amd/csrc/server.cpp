@@ -1,0 +1,480 @@
+// Continuous-batching query server.
+//
+// A scheduler thread owns a pool of query slots on the device.  Each
+// iteration it (1) admits waiting queries into free slots, growing the slot
+// pool when the device reports enough free memory, (2) starts them (slot
+// state reset, source injected into the shared frontier), (3) runs ONE push
+// round for every active slot in a single launch, and (4) reads back the
+// frontier size and per-slot activity flags.  A slot whose frontier emptied
+// either moves to its next departure time (latest departure / fastest sweep)
+// or is finished: its result is written to the caller's buffer and a
+// completion with timestamps is queued for polling.  Queries that arrive
+// while others run join at the next iteration, so their rounds overlap on
+// the device with everyone else's.
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+using namespace kairos;
+
+namespace {
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Query {
+    uint64_t ticket;
+    int kind;
+    uint32_t src, ta, tw;
+    uint32_t *out;
+    uint64_t t_submit;
+};
+
+struct SlotRun {
+    bool busy = false;
+    bool started = false;
+    Query q{};
+    std::vector<uint32_t> steps;  // sweep departure times, descending
+    size_t next_step = 0;
+};
+
+}  // namespace
+
+struct kairos_server {
+    kairos_graph *g = nullptr;
+    kairos_server_opts opts{};
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Query> waiting;
+    std::deque<kairos_completion> done;
+    std::thread th;
+    bool stop = false;
+    bool failed = false;
+    uint64_t next_ticket = 1;
+    kairos_server_stats stats{};
+    uint64_t free_override = UINT64_MAX;
+    // device side (scheduler thread only)
+    MultiState ms;
+    bool own_stream = false;
+    uint32_t cap = 0;
+    std::vector<SlotRun> slots;
+    uint32_t *h_pin = nullptr;  // pinned: counters+flags | inject list | init list
+    uint64_t per_slot_chunks = 0;
+};
+
+namespace {
+
+size_t pin_words(uint32_t max_slots)
+{
+    return CNT_WORDS + (size_t)max_slots + 8 * (size_t)max_slots + (size_t)max_slots + 64;
+}
+
+uint64_t slot_bytes(kairos_server *s)
+{
+    return (uint64_t)s->g->n * 4 * 7 + s->per_slot_chunks * sizeof(uint4) + sizeof(uint4) + 4;
+}
+
+bool free_bytes_ok(kairos_server *s, uint64_t need)
+{
+    uint64_t fr = s->free_override;
+    if (fr == UINT64_MAX) {
+        size_t f = 0, t = 0;
+        if (hipMemGetInfo(&f, &t) != hipSuccess) return false;
+        fr = f;
+    }
+    return fr >= need + s->opts.mem_reserve_bytes;
+}
+
+void free_state(MultiState &m)
+{
+    dev_free(m.arr);
+    dev_free(m.done);
+    dev_free(m.stamp);
+    dev_free(m.fa);
+    dev_free(m.l1);
+    dev_free(m.queue[0]);
+    dev_free(m.queue[1]);
+    dev_free(m.cnt);
+    dev_free(m.chunks);
+    dev_free(m.qp);
+    dev_free(m.stats);
+    m = MultiState{};
+}
+
+// Grow the slot pool to `ncap` slots, keeping the state of existing slots.
+// Called between rounds only.  Returns false if memory is short.
+bool grow(kairos_server *s, uint32_t ncap)
+{
+    if (ncap <= s->cap) return true;
+    const uint64_t need = slot_bytes(s) * (ncap - s->cap);
+    if (!free_bytes_ok(s, need)) return false;
+    const size_t n = s->g->n;
+    const size_t qn = (size_t)ncap * n, on = (size_t)s->cap * n;
+    MultiState nm;
+    nm.qcap = ncap;
+    nm.n = (uint32_t)n;
+    nm.round = s->ms.round;
+    nm.stamp_next = s->ms.stamp_next;
+    nm.stream = s->ms.stream;
+    nm.chunk_cap = s->per_slot_chunks * ncap;
+    nm.arr = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.done = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.stamp = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.fa = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.l1 = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.queue[0] = (uint32_t *)dev_alloc(qn * 4 + 64, nullptr);
+    nm.queue[1] = (uint32_t *)dev_alloc(qn * 4 + 64, nullptr);
+    nm.cnt = (uint32_t *)dev_alloc((CNT_WORDS + (size_t)ncap) * 4, nullptr);
+    nm.chunks = (uint4 *)dev_alloc(nm.chunk_cap * sizeof(uint4), nullptr);
+    nm.qp = (uint4 *)dev_alloc((size_t)ncap * sizeof(uint4), nullptr);
+    nm.stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, nullptr);
+    hipStream_t st = s->ms.stream;
+    bool ok = nm.arr && nm.done && nm.stamp && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
+              nm.chunks && nm.qp && nm.stats;
+    ok = ok && hipMemsetAsync(nm.stamp, 0, qn * 4, st) == hipSuccess &&
+         hipMemsetAsync(nm.cnt, 0, (CNT_WORDS + (size_t)ncap) * 4, st) == hipSuccess &&
+         hipMemsetAsync(nm.stats, 0, ST_WORDS * 8, st) == hipSuccess;
+    if (ok && s->cap) {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        ok = hipMemcpyAsync(nm.arr, s->ms.arr, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.done, s->ms.done, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.stamp, s->ms.stamp, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.fa, s->ms.fa, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.l1, s->ms.l1, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.queue[0], s->ms.queue[0], on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.cnt, s->ms.cnt, (CNT_WORDS + (size_t)s->cap) * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.qp, s->ms.qp, (size_t)s->cap * sizeof(uint4), k, st) == hipSuccess;
+    }
+    ok = ok && hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        hipStreamSynchronize(st);
+        free_state(nm);
+        (void)hipGetLastError();
+        return false;
+    }
+    free_state(s->ms);
+    s->ms = nm;
+    s->cap = ncap;
+    s->slots.resize(ncap);
+    return true;
+}
+
+void complete(kairos_server *s, const Query &q, int status, uint64_t t_done)
+{
+    kairos_completion c{};
+    c.ticket = q.ticket;
+    c.status = status;
+    c.kind = q.kind;
+    c.t_submit_ns = q.t_submit;
+    c.t_done_ns = t_done;
+    s->done.push_back(c);
+    s->stats.completed += 1;
+}
+
+int sweep_steps(kairos_server *s, const Query &q, std::vector<uint32_t> &steps)
+{
+    kairos_graph *g = s->g;
+    hipStream_t st = s->ms.stream;
+    uint32_t off[2];
+    KAIROS_HIP(hipMemcpyAsync(s->h_pin, g->off_out + q.src, 8, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    off[0] = s->h_pin[0];
+    off[1] = s->h_pin[1];
+    const uint32_t deg = off[1] - off[0];
+    steps.clear();
+    if (!deg) return KAIROS_OK;
+    std::vector<uint32_t> t(deg);
+    std::vector<uint2> da(deg);
+    KAIROS_HIP(hipMemcpyAsync(t.data(), g->t_out + off[0], deg * 4ull, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipMemcpyAsync(da.data(), g->da_out + off[0], deg * 8ull, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    for (uint32_t i = 0; i < deg; ++i)
+        if (t[i] >= q.ta && da[i].y <= q.tw) steps.push_back(t[i]);
+    std::sort(steps.begin(), steps.end());
+    steps.erase(std::unique(steps.begin(), steps.end()), steps.end());
+    std::reverse(steps.begin(), steps.end());
+    return KAIROS_OK;
+}
+
+// Fail everything in flight and waiting (after a device error).
+void fail_all(kairos_server *s)
+{
+    const uint64_t t = now_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->failed = true;
+    for (auto &sl : s->slots)
+        if (sl.busy) {
+            complete(s, sl.q, KAIROS_ERR_DEVICE, t);
+            sl = SlotRun{};
+        }
+    while (!s->waiting.empty()) {
+        complete(s, s->waiting.front(), KAIROS_ERR_DEVICE, t);
+        s->waiting.pop_front();
+    }
+    s->stats.active_slots = 0;
+    s->stats.waiting = 0;
+}
+
+int iterate(kairos_server *s, std::vector<Inject> &pending, uint32_t &front)
+{
+    kairos_graph *g = s->g;
+    hipStream_t st = s->ms.stream;
+    std::vector<uint32_t> admitted;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        uint32_t active = 0;
+        for (auto &sl : s->slots) active += sl.busy;
+        if (active == 0 && s->waiting.empty() && pending.empty()) {
+            if (s->stop) return 1;
+            s->cv.wait_for(lk, std::chrono::milliseconds(5));
+            return 0;
+        }
+        while (!s->waiting.empty()) {
+            int slot = -1;
+            for (uint32_t i = 0; i < s->cap; ++i)
+                if (!s->slots[i].busy) {
+                    slot = (int)i;
+                    break;
+                }
+            if (slot < 0) {
+                if (s->cap >= s->opts.max_slots) break;
+                const uint32_t ncap = std::min<uint32_t>(s->opts.max_slots, std::max<uint32_t>(4, s->cap * 2));
+                lk.unlock();
+                const bool ok = grow(s, ncap);
+                lk.lock();
+                if (!ok) {
+                    s->stats.admitted_waits_mem += 1;
+                    break;
+                }
+                continue;
+            }
+            SlotRun &sl = s->slots[slot];
+            sl = SlotRun{};
+            sl.busy = true;
+            sl.q = s->waiting.front();
+            s->waiting.pop_front();
+            admitted.push_back((uint32_t)slot);
+        }
+        uint32_t act = 0;
+        for (auto &sl : s->slots) act += sl.busy;
+        s->stats.active_slots = act;
+        s->stats.waiting = (uint32_t)s->waiting.size();
+        s->stats.max_slots_seen = std::max(s->stats.max_slots_seen, act);
+        if (act == 0 && pending.empty()) {
+            // nothing can run: queries wait for memory
+            if (s->stop) {
+                // shutting down and nothing will ever free memory for them
+                while (!s->waiting.empty()) {
+                    complete(s, s->waiting.front(), KAIROS_ERR_NOMEM, now_ns());
+                    s->waiting.pop_front();
+                }
+                return 1;
+            }
+            s->cv.wait_for(lk, std::chrono::milliseconds(1));
+            return 0;
+        }
+    }
+    std::vector<uint32_t> finish_now;
+    for (uint32_t slot : admitted) {
+        SlotRun &sl = s->slots[slot];
+        if (sl.q.kind == 0) {
+            pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, INF, 0, 0, 0});
+        } else {
+            int rc = sweep_steps(s, sl.q, sl.steps);
+            if (rc) return rc;
+            if (sl.steps.empty()) {
+                finish_now.push_back(slot);
+            } else {
+                pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, sl.steps[0], 0, 0, 0});
+                sl.next_step = 1;
+            }
+        }
+        sl.started = true;
+    }
+    // pinned layout: [0, CNT_WORDS + max_slots) read-back | inject list | init list
+    Inject *h_inj = (Inject *)(s->h_pin + CNT_WORDS + s->opts.max_slots);
+    uint32_t *h_init = s->h_pin + CNT_WORDS + s->opts.max_slots + 8 * (size_t)s->opts.max_slots;
+    for (size_t i = 0; i < admitted.size(); ++i) h_init[i] = admitted[i];
+    int rc = multi_init_slots(g, &s->ms, h_init, (uint32_t)admitted.size());
+    if (rc) return rc;
+    for (size_t i = 0; i < pending.size(); ++i) h_inj[i] = pending[i];
+    if ((rc = multi_inject(g, &s->ms, h_inj, (uint32_t)pending.size()))) return rc;
+    front += (uint32_t)pending.size();
+    pending.clear();
+    if (front > 0) {
+        if ((rc = multi_push_round(g, &s->ms))) return rc;
+    }
+    // finishing: slots with an empty frontier after this round
+    const size_t rb = CNT_WORDS + s->cap;
+    KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->ms.cnt, rb * 4, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    front = s->h_pin[CNT_FRONT + s->ms.round % 3u];
+    const uint32_t *flags = s->h_pin + CNT_WORDS;
+    std::vector<uint32_t> finished = finish_now;
+    for (uint32_t slot = 0; slot < s->cap; ++slot) {
+        SlotRun &sl = s->slots[slot];
+        if (!sl.busy || !sl.started) continue;
+        if (std::find(finish_now.begin(), finish_now.end(), slot) != finish_now.end()) continue;
+        if (flags[slot] == s->ms.round) continue;  // still has frontier work
+        if (sl.q.kind != 0 && sl.next_step < sl.steps.size()) {
+            pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, sl.steps[sl.next_step++], 0, 0, 0});
+            continue;
+        }
+        finished.push_back(slot);
+    }
+    if (!finished.empty()) {
+        for (uint32_t slot : finished) {
+            const Query &q = s->slots[slot].q;
+            if ((rc = multi_finalize(g, &s->ms, slot, q.kind, q.src, q.tw, q.out))) return rc;
+        }
+        KAIROS_HIP(hipStreamSynchronize(st));
+        const uint64_t t = now_ns();
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (uint32_t slot : finished) {
+            complete(s, s->slots[slot].q, KAIROS_OK, t);
+            s->slots[slot] = SlotRun{};
+        }
+        uint32_t act = 0;
+        for (auto &sl : s->slots) act += sl.busy;
+        s->stats.active_slots = act;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.iterations += 1;
+    }
+    return 0;
+}
+
+void scheduler(kairos_server *s)
+{
+    std::vector<Inject> pending;
+    uint32_t front = 0;
+    for (;;) {
+        int rc = iterate(s, pending, front);
+        if (rc == 1) break;
+        if (rc != 0) {
+            fail_all(s);
+            pending.clear();
+            front = 0;
+            std::unique_lock<std::mutex> lk(s->mu);
+            while (!s->stop) {
+                while (!s->waiting.empty()) {
+                    complete(s, s->waiting.front(), KAIROS_ERR_DEVICE, now_ns());
+                    s->waiting.pop_front();
+                }
+                s->cv.wait_for(lk, std::chrono::milliseconds(5));
+            }
+            while (!s->waiting.empty()) {
+                complete(s, s->waiting.front(), KAIROS_ERR_DEVICE, now_ns());
+                s->waiting.pop_front();
+            }
+            break;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int kairos_server_create(kairos_graph *g, const kairos_server_opts *opts, kairos_server **out)
+{
+    if (!g || !opts || !out || opts->max_slots == 0 || opts->queue_capacity == 0) return KAIROS_ERR_INVALID;
+    if ((uint64_t)opts->max_slots * g->n >= 0xFFFFFFF0ull) return KAIROS_ERR_RANGE;
+    kairos_server *s = new (std::nothrow) kairos_server();
+    if (!s) return KAIROS_ERR_NOMEM;
+    s->g = g;
+    s->opts = *opts;
+    s->per_slot_chunks = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
+                         g->m / std::max<uint32_t>(g->tuning.split, 64) + 1;
+    if (opts->hip_stream) {
+        s->ms.stream = (hipStream_t)opts->hip_stream;
+    } else if (hipStreamCreateWithFlags(&s->ms.stream, hipStreamNonBlocking) == hipSuccess) {
+        s->own_stream = true;
+    } else {
+        delete s;
+        return KAIROS_ERR_DEVICE;
+    }
+    if (hipHostMalloc((void **)&s->h_pin, pin_words(opts->max_slots) * 4, hipHostMallocDefault) != hipSuccess) {
+        if (s->own_stream) hipStreamDestroy(s->ms.stream);
+        delete s;
+        return KAIROS_ERR_NOMEM;
+    }
+    s->ms.n = g->n;
+    s->th = std::thread(scheduler, s);
+    *out = s;
+    return KAIROS_OK;
+}
+
+int kairos_server_submit(kairos_server *s, int kind, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                         uint32_t *out, uint64_t *ticket)
+{
+    if (!s || !out || !ticket || kind < 0 || kind > 2) return KAIROS_ERR_INVALID;
+    if (src >= s->g->n || t_alpha > t_omega || t_omega > KAIROS_TMAX) return KAIROS_ERR_RANGE;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->waiting.size() >= s->opts.queue_capacity) return KAIROS_ERR_BUSY;
+    Query q{s->next_ticket++, kind, src, t_alpha, t_omega, out, now_ns()};
+    *ticket = q.ticket;
+    s->stats.submitted += 1;
+    if (s->failed) {
+        complete(s, q, KAIROS_ERR_DEVICE, now_ns());
+        return KAIROS_OK;
+    }
+    s->waiting.push_back(q);
+    s->stats.waiting = (uint32_t)s->waiting.size();
+    s->cv.notify_one();
+    return KAIROS_OK;
+}
+
+int kairos_server_poll(kairos_server *s, kairos_completion *done, uint32_t cap, uint32_t *n_done)
+{
+    if (!s || !n_done || (cap && !done)) return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    uint32_t k = 0;
+    while (k < cap && !s->done.empty()) {
+        done[k++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_done = k;
+    return KAIROS_OK;
+}
+
+int kairos_server_stats_read(kairos_server *s, kairos_server_stats *out)
+{
+    if (!s || !out) return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return KAIROS_OK;
+}
+
+int kairos_server_set_free_bytes_override(kairos_server *s, uint64_t bytes)
+{
+    if (!s) return KAIROS_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->free_override = bytes;
+    return KAIROS_OK;
+}
+
+void kairos_server_free(kairos_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    hipStreamSynchronize(s->ms.stream);
+    free_state(s->ms);
+    if (s->h_pin) hipHostFree(s->h_pin);
+    if (s->own_stream) hipStreamDestroy(s->ms.stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,971 @@
+// Frontier traversal over the time-sorted temporal CSR: earliest arrival
+// (Alg. 2), and latest departure / fastest by a sweep over departure times.
+//
+// Differences from the paper's Alg. 2, and why:
+//  * A vertex re-enters the frontier whenever its arrival improves (the
+//    visit-once flag of Alg. 2 can keep a late arrival found in an early
+//    round).  The source starts at t_alpha; edges are usable iff
+//    t >= t_alpha and a <= t_omega; succession is non-strict (t >= arrival).
+//  * TemporalEdgeMap's per-vertex choice between a T-CSR scan and an interval
+//    index (§4.4, §5) becomes two binary searches into the vertex's
+//    time-sorted adjacency: the first edge departing at or after the vertex's
+//    arrival, and the first departing at or after t_omega (any such edge
+//    arrives after t_omega).  Only the edges in between are read.
+//  * done[u] remembers the lowest adjacency position already claimed for u.
+//    When u comes back with an earlier arrival only the newly usable prefix
+//    [lo, done[u]) is read: whether an edge relaxes its head does not depend
+//    on the tail's arrival once it is usable, so every out-edge is read at
+//    most once per query.  Claims are made with atomicMin, so concurrent
+//    claims never overlap.
+//  * writeMin is a device-scope atomicMin on uint32 arrival times.  Arrivals
+//    only decrease, so a stale plain read of arr[v] can only cause a
+//    redundant atomic, never a missed update; the tail's own arrival is read
+//    with an atomic load.
+//  * Each frontier vertex is enqueued at most once per round through a round
+//    stamp; enqueueing is aggregated per wave with a ballot.
+//  * Work is balanced inside a block by a prefix sum over the claimed range
+//    lengths; ranges of at least `split` edges are cut into chunks of `chunk`
+//    edges that a second kernel spreads over the whole GPU.
+
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace kairos {
+
+namespace {
+
+constexpr int TB = 256;  // threads per traversal block
+
+struct TravArgs {
+    const uint32_t *off;     // out-index offsets
+    const uint32_t *tt;      // out-edge departure
+    const uint2 *da;         // out-edge {head, arrival}
+    const uint32_t *off_in;  // in-index offsets
+    const uint32_t *a_in;    // in-edge arrival
+    const uint2 *st_in;      // in-edge {tail, departure}
+    const uint4 *qp;         // per query {src, t_alpha, t_omega, sweep departure}
+    uint32_t n;
+    uint32_t *arr;
+    uint32_t *done;
+    uint32_t *stamp;
+    uint32_t *fa;
+    uint32_t *l1;
+    const uint32_t *cur;
+    uint32_t *next;
+    uint32_t *cnt;
+    uint4 *chunks;
+    uint32_t chunk_cap;
+    unsigned long long *stats;
+    uint32_t round;
+    uint32_t stamp_val;
+    uint32_t split;
+    uint32_t chunk;
+    uint32_t nq;             // queries (dense pull covers nq*n vertices)
+    uint32_t track_volume;   // accumulate out-degree of enqueued vertices
+    uint32_t *qflag;         // per query: round+1 when it enqueued something (or null)
+};
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t lo,
+                                                    uint32_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Wave-aggregated append of `item` for the lanes with `push` set.
+__device__ __forceinline__ void enqueue(const TravArgs &A, bool push, uint32_t item, uint32_t v,
+                                        uint32_t *next_cnt, uint32_t *vol_cnt)
+{
+    if (push && A.qflag) A.qflag[item / A.n] = A.round + 1u;
+    const uint64_t bal = __ballot(push);
+    if (bal == 0) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    uint32_t base = 0;
+    if ((int)lane == leader) base = atomicAdd(next_cnt, (uint32_t)__popcll(bal));
+    base = __shfl(base, leader);
+    if (push) {
+        A.next[base + __popcll(bal & lanemask_lt())] = item;
+        if (A.track_volume) {
+            const uint32_t deg = A.off[v + 1] - A.off[v];
+            if (deg) atomicAdd(vol_cnt, deg);
+        }
+    }
+}
+
+// Relax out-edge e of query q: returns true when the head must be enqueued.
+template <bool SWEEP>
+__device__ __forceinline__ bool relax(const TravArgs &A, uint32_t q, uint32_t e, uint32_t tw,
+                                      uint32_t sdep, uint32_t &item, uint32_t &vout,
+                                      unsigned long long &nrelax)
+{
+    const uint2 dv = A.da[e];
+    const uint32_t v = dv.x, a = dv.y;
+    vout = v;
+    if (a > tw) return false;
+    const size_t sv = (size_t)q * A.n + v;
+    item = (uint32_t)sv;
+    if (!(a < A.arr[sv])) return false;
+    const uint32_t old = atomicMin(&A.arr[sv], a);
+    if (!(a < old)) return false;
+    ++nrelax;
+    if (SWEEP && sdep != INF) {
+        atomicMin(&A.fa[sv], a - sdep);
+        atomicMax(&A.l1[sv], sdep + 1u);
+    }
+    return atomicExch(&A.stamp[sv], A.stamp_val) != A.stamp_val;
+}
+
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
+{
+    __shared__ unsigned long long s_pref[TB + 1];
+    __shared__ uint32_t s_lo[TB];
+    __shared__ uint32_t s_q[TB];
+    __shared__ uint32_t s_tw[TB];
+    __shared__ uint32_t s_sd[TB];
+    __shared__ unsigned long long s_wsum[TB / 64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t F = A.cnt[CNT_FRONT + r3];
+    if (blockIdx.x == 0 && tid == 0) {
+        A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_PULLVOL + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
+    }
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
+    uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+
+    for (uint32_t base = blockIdx.x * TB; base < F; base += gridDim.x * TB) {
+        const uint32_t i = base + tid;
+        uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0;
+        if (i < F) {
+            ++n_items;
+            const uint32_t item = A.cur[i];
+            q = item / A.n;
+            const uint32_t u = item - q * A.n;
+            const uint4 p = A.qp[q];
+            tw = p.z;
+            sd = p.w;
+            const size_t su = (size_t)q * A.n + u;
+            const uint32_t r = __hip_atomic_load(&A.arr[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t b = A.off[u], e = A.off[u + 1];
+            lo = lower_bound_u32(A.tt, b, e, r);
+            const uint32_t old = atomicMin(&A.done[su], lo);
+            uint32_t end = old;
+            if (old == INF) end = lower_bound_u32(A.tt, lo, e, tw);
+            if (lo < end) len = end - lo;
+            if (len >= A.split) {
+                const uint32_t nch = (len + A.chunk - 1) / A.chunk;
+                const uint32_t cb = atomicAdd(chunk_cnt, nch);
+                const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
+                for (uint32_t k = 0; k < fit; ++k) {
+                    const uint32_t s0 = lo + k * A.chunk;
+                    A.chunks[cb + k] = make_uint4(q, s0, min(A.chunk, len - k * A.chunk), 0u);
+                }
+                const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
+                lo += covered;
+                len -= covered;
+            }
+        }
+        // exclusive prefix sum of len over the block
+        unsigned long long x = len;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[w] = x;
+        s_lo[tid] = lo;
+        s_q[tid] = q;
+        s_tw[tid] = tw;
+        s_sd[tid] = sd;
+        __syncthreads();
+        unsigned long long woff = 0, total = 0;
+        for (int w2 = 0; w2 < TB / 64; ++w2) {
+            if (w2 < w) woff += s_wsum[w2];
+            total += s_wsum[w2];
+        }
+        s_pref[tid] = woff + x - len;
+        if (tid == 0) s_pref[TB] = total;
+        __syncthreads();
+        n_edges += total;
+        for (unsigned long long j = tid; j < total; j += TB) {
+            // owner: the last k with s_pref[k] <= j
+            int lo_k = 0, hi_k = TB;
+            while (hi_k - lo_k > 1) {
+                const int mid = (lo_k + hi_k) >> 1;
+                if (s_pref[mid] <= j)
+                    lo_k = mid;
+                else
+                    hi_k = mid;
+            }
+            const uint32_t e = s_lo[lo_k] + (uint32_t)(j - s_pref[lo_k]);
+            uint32_t item = 0, v = 0;
+            const bool push = relax<SWEEP>(A, s_q[lo_k], e, s_tw[lo_k], s_sd[lo_k], item, v, n_relax);
+            enqueue(A, push, item, v, next_cnt, vol_cnt);
+        }
+        __syncthreads();
+    }
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_relax += __shfl_xor(n_relax, o);
+            n_items += __shfl_xor(n_items, o);
+        }
+        if (lane == 0) {
+            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
+        }
+        if (tid == 0 && n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
+    }
+}
+
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
+{
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
+    unsigned long long n_edges = 0, n_relax = 0;
+    for (uint32_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const uint4 ch = A.chunks[c];
+        const uint4 p = A.qp[ch.x];
+        n_edges += ch.z;
+        for (uint32_t k = threadIdx.x; k < ch.z; k += TB) {
+            uint32_t item = 0, v = 0;
+            const bool push = relax<SWEEP>(A, ch.x, ch.y + k, p.z, p.w, item, v, n_relax);
+            enqueue(A, push, item, v, next_cnt, vol_cnt);
+        }
+    }
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
+        if ((threadIdx.x & 63) == 0 && n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+        if (threadIdx.x == 0 && n_edges) atomicAdd(&A.stats[ST_CHUNK_EDGES], n_edges);
+    }
+}
+
+// Dense pull round: every vertex v of every query looks at its in-edges in
+// ascending arrival (only those arriving before its current value and within
+// the window); the first whose tail has arrived by its departure is the new
+// minimum.  One writer per vertex, no atomics.
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
+{
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_PULLVOL + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + A.round % 3u] = 0u;
+    }
+    unsigned long long n_edges = 0, n_verts = 0, n_relax = 0;
+    const uint64_t total = (uint64_t)A.nq * A.n;
+    const uint64_t stride = (uint64_t)gridDim.x * TB;
+    const uint64_t rounds = (total + stride - 1) / stride;
+    for (uint64_t it = 0; it < rounds; ++it) {
+        const uint64_t idx = it * stride + (uint64_t)blockIdx.x * TB + threadIdx.x;
+        bool push = false;
+        uint32_t item = 0, v = 0;
+        if (idx < total) {
+            const uint32_t q = (uint32_t)(idx / A.n);
+            v = (uint32_t)(idx - (uint64_t)q * A.n);
+            const uint4 p = A.qp[q];
+            if (v != p.x) {
+                ++n_verts;
+                const size_t sv = (size_t)q * A.n + v;
+                const uint32_t rv = A.arr[sv];
+                const uint32_t lim = min(rv, p.z + 1u);
+                const uint32_t b = A.off_in[v], e = A.off_in[v + 1];
+                const uint32_t ub = lower_bound_u32(A.a_in, b, e, lim);
+                for (uint32_t k = b; k < ub; ++k) {
+                    ++n_edges;
+                    const uint2 st = A.st_in[k];
+                    if (st.y >= p.y && A.arr[(size_t)q * A.n + st.x] <= st.y) {
+                        const uint32_t a = A.a_in[k];
+                        A.arr[sv] = a;
+                        ++n_relax;
+                        if (SWEEP && p.w != INF) {
+                            A.fa[sv] = min(A.fa[sv], a - p.w);
+                            A.l1[sv] = max(A.l1[sv], p.w + 1u);
+                        }
+                        push = true;
+                        item = (uint32_t)sv;
+                        break;
+                    }
+                }
+            }
+        }
+        enqueue(A, push, item, v, next_cnt, vol_cnt);
+    }
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_edges += __shfl_xor(n_edges, o);
+            n_verts += __shfl_xor(n_verts, o);
+            n_relax += __shfl_xor(n_relax, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (n_edges) atomicAdd(&A.stats[ST_PULL_EDGES], n_edges);
+            if (n_verts) atomicAdd(&A.stats[ST_PULL_VERTS], n_verts);
+            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+        }
+    }
+}
+
+// Query start: parameters, source arrival, first frontier, counters.
+__global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_qp, uint32_t nq,
+                                    uint32_t src_arrival_from_w)
+{
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+        const uint4 p = host_qp[q];
+        ((uint4 *)A.qp)[q] = p;
+        const size_t ss = (size_t)q * A.n + p.x;
+        A.arr[ss] = src_arrival_from_w ? p.w : p.y;
+        A.next[q] = (uint32_t)ss;  // `next` names the buffer read by the first round here
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.cnt[CNT_FRONT + A.round % 3u] = nq;
+        A.cnt[CNT_FRONT + (A.round + 1u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + A.round % 3u] = 0u;
+        A.cnt[CNT_PULLVOL + A.round % 3u] = 0u;
+        A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u] = 0u;
+    }
+}
+
+__global__ void finalize_sweep_kernel(uint32_t *out, const uint32_t *l1, const uint32_t *fa, uint32_t n,
+                                      int kind, uint32_t src, uint32_t tw)
+{
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint32_t r;
+        if (v == src)
+            r = kind == 1 ? tw : 0u;
+        else if (kind == 1)
+            r = l1[v] ? l1[v] - 1u : INF;
+        else
+            r = fa[v];
+        out[v] = r;
+    }
+}
+
+__global__ void count_traversed_kernel(const uint32_t *__restrict__ a_in, const uint2 *__restrict__ st_in,
+                                       uint64_t m, const uint32_t *__restrict__ ea, uint32_t ta, uint32_t tw,
+                                       unsigned long long *out)
+{
+    unsigned long long c = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint2 st = st_in[e];
+        const uint32_t r = ea[st.x];
+        if (r != INF && st.y >= max(r, ta) && a_in[e] <= tw) ++c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+int grid_cap(uint64_t work, int per_block, int cap)
+{
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)cap) g = cap;
+    return (int)g;
+}
+
+int fill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t value)
+{
+    if (!count) return KAIROS_OK;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_cap(count, 256 * 4, 8192)), dim3(256), 0, st, p,
+                       count, value);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
+{
+    TravArgs A{};
+    A.off = g->off_out;
+    A.tt = g->t_out;
+    A.da = g->da_out;
+    A.off_in = g->off_in;
+    A.a_in = g->a_in;
+    A.st_in = g->st_in;
+    A.qp = s->qp;
+    A.n = g->n;
+    A.arr = arr;
+    A.done = s->done;
+    A.stamp = s->stamp;
+    A.fa = s->fa;
+    A.l1 = s->l1;
+    A.cnt = s->cnt;
+    A.chunks = s->chunks;
+    A.chunk_cap = (uint32_t)std::min<uint64_t>(s->chunk_cap, 0xFFFFFFF0u);
+    A.stats = s->stats;
+    A.split = std::max<uint32_t>(g->tuning.split, 1);
+    A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
+    A.nq = nq;
+    A.track_volume = g->tuning.pull_alpha ? 1u : 0u;
+    return A;
+}
+
+uint32_t next_stamp(Slot *s, int *rc)
+{
+    if (s->stamp_next >= 0xFFFFF000u) {
+        *rc = fill(s->stream, s->stamp, (uint64_t)s->qcap * s->n, 0u);
+        s->stamp_next = 1;
+    }
+    return s->stamp_next++;
+}
+
+// Runs frontier rounds until the frontier is empty.  The first round's
+// frontier (nq items) is already in s->queue[0] and the counters set for
+// round `r0`.
+template <bool SWEEP>
+int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint32_t *round_io)
+{
+    hipStream_t st = s->stream;
+    const kairos_tuning &tu = g->tuning;
+    const int spec_grid = std::max(1, g->num_cus * 8);
+    const int chunk_grid = std::max(1, g->num_cus * 4);
+    const uint32_t R = std::max<uint32_t>(1, tu.rounds_per_sync);
+    uint32_t r = *round_io;
+    uint32_t F = first_front;
+    uint64_t vol = 0;
+    bool pulling = false;
+    int which = 0;  // queue holding the current frontier
+    const uint64_t total_v = (uint64_t)A.nq * g->n;
+    int rc = KAIROS_OK;
+    while (F > 0) {
+        for (uint32_t k = 0; k < R; ++k) {
+            A.round = r;
+            A.stamp_val = next_stamp(s, &rc);
+            if (rc) return rc;
+            A.cur = s->queue[which];
+            A.next = s->queue[which ^ 1];
+            hipEvent_t ev;
+            if (k == 0 && tu.pull_alpha) {
+                // direction choice from the last read-back
+                if (!pulling && vol > (uint64_t)g->m * A.nq / tu.pull_alpha) pulling = true;
+                else if (pulling && (uint64_t)F * std::max<uint32_t>(tu.pull_beta, 1) < total_v) pulling = false;
+            }
+            if (pulling && k == 0) {
+                prof_begin(g, st, &ev);
+                hipLaunchKernelGGL(pull_kernel<SWEEP>, dim3(grid_cap(total_v, TB * 4, g->num_cus * 16)),
+                                   dim3(TB), 0, st, A);
+                prof_end(g, st, KAIROS_K_PULL, ev);
+            } else {
+                const int pg = k == 0 ? grid_cap(F, TB, spec_grid) : spec_grid;
+                prof_begin(g, st, &ev);
+                hipLaunchKernelGGL(push_kernel<SWEEP>, dim3(pg), dim3(TB), 0, st, A);
+                prof_end(g, st, KAIROS_K_PUSH, ev);
+                prof_begin(g, st, &ev);
+                hipLaunchKernelGGL(chunk_kernel<SWEEP>, dim3(chunk_grid), dim3(TB), 0, st, A);
+                prof_end(g, st, KAIROS_K_CHUNK, ev);
+            }
+            KAIROS_HIP(hipGetLastError());
+            ++r;
+            which ^= 1;
+            if (pulling) break;  // decide again after every pull round
+        }
+        KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, CNT_WORDS * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        KAIROS_HIP(hipStreamSynchronize(st));
+        F = s->h_pin[CNT_FRONT + r % 3u];
+        vol = s->h_pin[CNT_PULLVOL + r % 3u];
+        if (g->prof.on) {
+            std::lock_guard<std::mutex> lk(g->prof.mu);
+            g->prof.rounds += 1;
+        }
+        if (which == 1 && F > 0) {
+            // keep the invariant "current frontier in queue[0]" cheap: swap pointers
+            std::swap(s->queue[0], s->queue[1]);
+            which = 0;
+        }
+    }
+    *round_io = r;
+    return KAIROS_OK;
+}
+
+int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
+{
+    Slot *s = new Slot();
+    s->qcap = qcap;
+    s->n = g->n;
+    const size_t qn = (size_t)qcap * g->n;
+    uint64_t *acct = &s->bytes;
+    s->done = (uint32_t *)dev_alloc(qn * 4, acct);
+    s->stamp = (uint32_t *)dev_alloc(qn * 4, acct);
+    s->queue[0] = (uint32_t *)dev_alloc(std::max<size_t>(qn, qcap) * 4, acct);
+    s->queue[1] = (uint32_t *)dev_alloc(std::max<size_t>(qn, qcap) * 4, acct);
+    const uint64_t per_q = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
+                           g->m / std::max<uint32_t>(g->tuning.split, 64) + 1;
+    s->chunk_cap = std::min<uint64_t>((uint64_t)qcap * per_q, 1ull << 31);
+    s->chunks = (uint4 *)dev_alloc(s->chunk_cap * sizeof(uint4), acct);
+    s->qp = (uint4 *)dev_alloc((size_t)qcap * sizeof(uint4), acct);
+    s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
+    s->stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, acct);
+    if (qcap == 1) {
+        s->arr = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
+        s->fa = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
+        s->l1 = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
+    }
+    bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt &&
+              s->stats && (qcap != 1 || (s->arr && s->fa && s->l1));
+    if (ok && hipHostMalloc((void **)&s->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
+        s->h_pin = nullptr;
+        ok = false;
+    }
+    if (ok) {
+        if (g->stream) {
+            s->stream = g->stream;
+        } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
+            s->own_stream = true;
+        } else {
+            ok = false;
+        }
+    }
+    if (ok) {
+        ok = hipMemsetAsync(s->stamp, 0, qn * 4, s->stream) == hipSuccess &&
+             hipMemsetAsync(s->cnt, 0, CNT_WORDS * 4, s->stream) == hipSuccess &&
+             hipMemsetAsync(s->stats, 0, ST_WORDS * 8, s->stream) == hipSuccess &&
+             hipStreamSynchronize(s->stream) == hipSuccess;
+    }
+    if (!ok) {
+        slot_destroy(s);
+        return KAIROS_ERR_NOMEM;
+    }
+    *out = s;
+    return KAIROS_OK;
+}
+
+int read_stats(kairos_graph *g, Slot *s)
+{
+    if (!g->prof.on) return KAIROS_OK;
+    unsigned long long h[ST_WORDS];
+    KAIROS_HIP(hipMemcpyAsync(h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    KAIROS_HIP(hipStreamSynchronize(s->stream));
+    KAIROS_HIP(hipMemsetAsync(s->stats, 0, sizeof(h), s->stream));
+    prof_add_stats(g, h);
+    return KAIROS_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ profiling --
+void prof_begin(kairos_graph *g, hipStream_t st, hipEvent_t *ev0)
+{
+    *ev0 = nullptr;
+    if (!g->prof.on) return;
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    hipEvent_t e = nullptr;
+    if (!g->prof.free_events.empty()) {
+        e = g->prof.free_events.back();
+        g->prof.free_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return;
+    }
+    hipEventRecord(e, st);
+    *ev0 = e;
+}
+
+void prof_end(kairos_graph *g, hipStream_t st, int cls, hipEvent_t ev0)
+{
+    if (!g->prof.on || !ev0) return;
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    hipEvent_t e = nullptr;
+    if (!g->prof.free_events.empty()) {
+        e = g->prof.free_events.back();
+        g->prof.free_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        g->prof.free_events.push_back(ev0);
+        return;
+    }
+    hipEventRecord(e, st);
+    g->prof.pending.push_back({cls, {ev0, e}});
+    g->prof.launches[cls] += 1;
+}
+
+void prof_add_stats(kairos_graph *g, const unsigned long long *h)
+{
+    std::lock_guard<std::mutex> lk(g->prof.mu);
+    g->prof.edges += h[ST_EDGES];
+    g->prof.chunk_edges += h[ST_CHUNK_EDGES];
+    g->prof.items += h[ST_ITEMS];
+    g->prof.relax += h[ST_RELAX];
+    g->prof.pull_edges += h[ST_PULL_EDGES];
+    g->prof.pull_verts += h[ST_PULL_VERTS];
+}
+
+// ---------------------------------------------------------------- slots --
+void slot_destroy(Slot *s)
+{
+    if (!s) return;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    dev_free(s->done);
+    dev_free(s->stamp);
+    dev_free(s->queue[0]);
+    dev_free(s->queue[1]);
+    dev_free(s->chunks);
+    dev_free(s->qp);
+    dev_free(s->cnt);
+    dev_free(s->stats);
+    dev_free(s->arr);
+    dev_free(s->fa);
+    dev_free(s->l1);
+    if (s->h_pin) hipHostFree(s->h_pin);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int slot_acquire(kairos_graph *g, uint32_t qcap, bool /*sweep*/, Slot **out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g->pool_mu);
+        auto &pool = qcap == 1 ? g->free_slots : g->batch_slots;
+        for (size_t i = 0; i < pool.size(); ++i) {
+            if (pool[i]->qcap >= qcap) {
+                *out = pool[i];
+                pool.erase(pool.begin() + i);
+                return KAIROS_OK;
+            }
+        }
+        // a batch slot too small: drop the cached ones so memory is reused
+        if (qcap != 1) {
+            for (Slot *s : pool) slot_destroy(s);
+            pool.clear();
+        }
+    }
+    return slot_alloc(g, qcap, out);
+}
+
+void slot_release(kairos_graph *g, Slot *s)
+{
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    (s->qcap == 1 ? g->free_slots : g->batch_slots).push_back(s);
+}
+
+// -------------------------------------------------------------- queries --
+static int start_queries(kairos_graph *g, Slot *s, uint32_t *arr, const uint4 *hqp, uint32_t nq,
+                         bool from_w, TravArgs &A, uint32_t &round)
+{
+    hipStream_t st = s->stream;
+    A = make_args(g, s, arr, nq);
+    round = 0;
+    A.round = 0;
+    A.next = s->queue[0];
+    // parameters travel through the pinned mirror (256 B) or a staging copy
+    uint4 *dq = nullptr;
+    uint4 *staging = nullptr;
+    if (nq * sizeof(uint4) <= 128) {
+        std::memcpy(s->h_pin + 32, hqp, nq * sizeof(uint4));
+        dq = (uint4 *)(s->h_pin + 32);
+    } else {
+        if (hipHostMalloc((void **)&staging, nq * sizeof(uint4), hipHostMallocDefault) != hipSuccess)
+            return KAIROS_ERR_NOMEM;
+        std::memcpy(staging, hqp, nq * sizeof(uint4));
+        dq = staging;
+    }
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(init_queries_kernel, dim3(grid_cap(nq, 256, 1024)), dim3(256), 0, st, A, dq, nq,
+                       from_w ? 1u : 0u);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    hipError_t e1 = hipGetLastError();
+    if (staging) {
+        hipStreamSynchronize(st);
+        hipHostFree(staging);
+    }
+    if (e1 != hipSuccess) {
+        note_hip_error(e1, "init_queries_kernel", __FILE__, __LINE__);
+        return KAIROS_ERR_DEVICE;
+    }
+    return KAIROS_OK;
+}
+
+int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+{
+    hipStream_t st = s->stream;
+    int rc;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = fill(st, out, g->n, INF))) return rc;
+    if ((rc = fill(st, s->done, g->n, INF))) return rc;
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    const uint4 qp = make_uint4(src, ta, tw, ta);
+    TravArgs A;
+    uint32_t round;
+    if ((rc = start_queries(g, s, out, &qp, 1, false, A, round))) return rc;
+    if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
+    return read_stats(g, s);
+}
+
+int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
+              const uint32_t *tw, uint32_t *out)
+{
+    hipStream_t st = s->stream;
+    int rc;
+    const uint64_t qn = (uint64_t)q * g->n;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = fill(st, out, qn, INF))) return rc;
+    if ((rc = fill(st, s->done, qn, INF))) return rc;
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    std::vector<uint4> hq(q);
+    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(src[i], ta[i], tw[i], ta[i]);
+    TravArgs A;
+    uint32_t round;
+    if ((rc = start_queries(g, s, out, hq.data(), q, false, A, round))) return rc;
+    if ((rc = run_rounds<false>(g, s, A, q, &round))) return rc;
+    return read_stats(g, s);
+}
+
+// Latest departure / fastest (kind 1 / 2).  The departure times S of the
+// source's usable out-edges are taken in descending order; for each s the
+// source is set to s and push rounds run to a fixpoint, warm-started from
+// the previous s (arrivals for a later start bound those for an earlier
+// one from above).  Every arrival that improves during step s belongs to a
+// path leaving the source exactly at s (all later departures were already
+// at their fixpoint), so each improvement updates
+//   F[v] = min(F[v], a - s)   and   L1[v] = max(L1[v], s + 1),
+// the latter giving LD[v] = L1[v] - 1, with 0 meaning unreachable.
+int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+{
+    hipStream_t st = s->stream;
+    int rc;
+    uint32_t hoff[2];
+    KAIROS_HIP(hipMemcpyAsync(s->h_pin, g->off_out + src, 8, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    hoff[0] = s->h_pin[0];
+    hoff[1] = s->h_pin[1];
+    const uint32_t deg = hoff[1] - hoff[0];
+    std::vector<uint32_t> ht(deg);
+    std::vector<uint2> hda(deg);
+    if (deg) {
+        KAIROS_HIP(hipMemcpy(ht.data(), g->t_out + hoff[0], deg * 4ull, hipMemcpyDeviceToHost));
+        KAIROS_HIP(hipMemcpy(hda.data(), g->da_out + hoff[0], deg * 8ull, hipMemcpyDeviceToHost));
+    }
+    std::vector<uint32_t> S;
+    for (uint32_t i = 0; i < deg; ++i)
+        if (ht[i] >= ta && hda[i].y <= tw) S.push_back(ht[i]);
+    std::sort(S.begin(), S.end());
+    S.erase(std::unique(S.begin(), S.end()), S.end());
+    std::reverse(S.begin(), S.end());
+
+    // out doubles as L1 (latest departure) or F (fastest)
+    uint32_t *l1 = kind == 1 ? out : s->l1;
+    uint32_t *fa = kind == 2 ? out : s->fa;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = fill(st, s->arr, g->n, INF))) return rc;
+    if ((rc = fill(st, s->done, g->n, INF))) return rc;
+    if ((rc = fill(st, fa, g->n, INF))) return rc;
+    if ((rc = fill(st, l1, g->n, 0u))) return rc;
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    uint32_t round = 0;
+    for (uint32_t sd : S) {
+        const uint4 qp = make_uint4(src, ta, tw, sd);
+        TravArgs A;
+        uint32_t r0;
+        if ((rc = start_queries(g, s, s->arr, &qp, 1, true, A, r0))) return rc;
+        A.fa = fa;
+        A.l1 = l1;
+        // continue the global round numbering so counters rotate consistently
+        (void)r0;
+        uint32_t r = 0;
+        if ((rc = run_rounds<true>(g, s, A, 1, &r))) return rc;
+        round += r;
+    }
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out,
+                       l1, fa, g->n, kind, src, tw);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    KAIROS_HIP(hipStreamSynchronize(st));
+    return read_stats(g, s);
+}
+
+int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count)
+{
+    Slot *s = nullptr;
+    int rc = slot_acquire(g, 1, false, &s);
+    if (rc) return rc;
+    hipStream_t st = s->stream;
+    unsigned long long *d = s->stats + ST_WORDS - 1;
+    do {
+        if (hipMemsetAsync(d, 0, 8, st) != hipSuccess) { rc = KAIROS_ERR_DEVICE; break; }
+        if (g->m)
+            hipLaunchKernelGGL(count_traversed_kernel, dim3(grid_cap(g->m, 256 * 8, 16384)), dim3(256), 0,
+                               st, g->a_in, g->st_in, g->m, ea, ta, tw, d);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(s->h_pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = KAIROS_ERR_DEVICE;
+            break;
+        }
+        uint64_t v;
+        std::memcpy(&v, s->h_pin, 8);
+        *count = v;
+    } while (0);
+    slot_release(g, s);
+    return rc;
+}
+
+kairos_tuning default_tuning(const kairos_graph *)
+{
+    kairos_tuning t{};
+    t.block = 256;
+    t.chunk = 4096;
+    t.split = 4096;
+    t.pull_alpha = 0;
+    t.pull_beta = 24;
+    t.rounds_per_sync = 1;
+    t.batch_persistent = 0;
+    t.sweep_group = 1;
+    return t;
+}
+
+
+// ------------------------------------------------------ server stepping --
+namespace {
+
+__global__ void inject_kernel(TravArgs A, const Inject *__restrict__ list, uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const Inject in = list[i];
+        ((uint4 *)A.qp)[in.q] = make_uint4(in.src, in.ta, in.tw, in.sdep);
+        const size_t ss = (size_t)in.q * A.n + in.src;
+        A.arr[ss] = in.sdep == INF ? in.ta : in.sdep;
+        const uint32_t pos = atomicAdd(&A.cnt[CNT_FRONT + A.round % 3u], 1u);
+        A.next[pos] = (uint32_t)ss;  // `next` names the queue of the coming round here
+    }
+}
+
+// Fresh state for the listed slots: arrival, claims and fastest = INF,
+// latest departure + 1 = 0.  Block (x, y): slot list[y], stride over n.
+__global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list)
+{
+    const size_t base = (size_t)list[blockIdx.y] * A.n;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.n; v += gridDim.x * blockDim.x) {
+        A.arr[base + v] = INF;
+        A.done[base + v] = INF;
+        A.fa[base + v] = INF;
+        A.l1[base + v] = 0u;
+    }
+}
+
+TravArgs multi_args(kairos_graph *g, MultiState *ms)
+{
+    TravArgs A{};
+    A.off = g->off_out;
+    A.tt = g->t_out;
+    A.da = g->da_out;
+    A.off_in = g->off_in;
+    A.a_in = g->a_in;
+    A.st_in = g->st_in;
+    A.qp = ms->qp;
+    A.n = g->n;
+    A.arr = ms->arr;
+    A.done = ms->done;
+    A.stamp = ms->stamp;
+    A.fa = ms->fa;
+    A.l1 = ms->l1;
+    A.cnt = ms->cnt;
+    A.qflag = ms->cnt + CNT_WORDS;
+    A.chunks = ms->chunks;
+    A.chunk_cap = (uint32_t)std::min<uint64_t>(ms->chunk_cap, 0xFFFFFFF0u);
+    A.stats = ms->stats;
+    A.split = std::max<uint32_t>(g->tuning.split, 1);
+    A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
+    A.nq = ms->qcap;
+    A.round = ms->round;
+    A.cur = ms->queue[0];
+    A.next = ms->queue[1];
+    return A;
+}
+
+}  // namespace
+
+int multi_push_round(kairos_graph *g, MultiState *ms)
+{
+    TravArgs A = multi_args(g, ms);
+    if (ms->stamp_next >= 0xFFFFF000u) {
+        int rc = fill(ms->stream, ms->stamp, (uint64_t)ms->qcap * ms->n, 0u);
+        if (rc) return rc;
+        ms->stamp_next = 1;
+    }
+    A.stamp_val = ms->stamp_next++;
+    hipEvent_t ev;
+    prof_begin(g, ms->stream, &ev);
+    hipLaunchKernelGGL(push_kernel<true>, dim3(std::max(1, g->num_cus * 8)), dim3(TB), 0, ms->stream, A);
+    prof_end(g, ms->stream, KAIROS_K_PUSH, ev);
+    prof_begin(g, ms->stream, &ev);
+    hipLaunchKernelGGL(chunk_kernel<true>, dim3(std::max(1, g->num_cus * 4)), dim3(TB), 0, ms->stream, A);
+    prof_end(g, ms->stream, KAIROS_K_CHUNK, ev);
+    KAIROS_HIP(hipGetLastError());
+    ms->round += 1;
+    std::swap(ms->queue[0], ms->queue[1]);
+    return KAIROS_OK;
+}
+
+int multi_inject(kairos_graph *g, MultiState *ms, const Inject *host_pinned, uint32_t count)
+{
+    if (!count) return KAIROS_OK;
+    TravArgs A = multi_args(g, ms);
+    A.next = ms->queue[0];
+    hipLaunchKernelGGL(inject_kernel, dim3(grid_cap(count, 256, 64)), dim3(256), 0, ms->stream, A,
+                       host_pinned, count);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count)
+{
+    if (!count) return KAIROS_OK;
+    TravArgs A = multi_args(g, ms);
+    hipLaunchKernelGGL(init_slots_kernel, dim3(grid_cap(g->n, 256 * 4, 256), count), dim3(256), 0,
+                       ms->stream, A, host_pinned);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32_t src, uint32_t tw,
+                   uint32_t *out)
+{
+    const size_t base = (size_t)q * g->n;
+    if (kind == 0) {
+        KAIROS_HIP(hipMemcpyAsync(out, ms->arr + base, (size_t)g->n * 4, hipMemcpyDeviceToDevice, ms->stream));
+        return KAIROS_OK;
+    }
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, ms->stream, out,
+                       ms->l1 + base, ms->fa + base, g->n, kind, src, tw);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+}  // namespace kairos

@@ -1,0 +1,241 @@
+"""GPU parity of the index builder and single / batched queries against the
+CPU oracle, through the C interface.  Integer results: bit-exact."""
+import json
+import glob
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+import paper_2401_02563_amd as K  # noqa: E402
+from workloads import make_graph, make_queries, tiny_graph, Graph  # noqa: E402
+
+INF = 0xFFFFFFFF
+_CACHE = {}
+
+
+def dev(g):
+    return [K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)]
+
+
+def built(key, factory):
+    if key not in _CACHE:
+        g = factory()
+        G = K.kairos_graph_build(*dev(g), g.n)
+        se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+        _CACHE[key] = (g, G, se)
+    return _CACHE[key]
+
+
+def uniform():
+    return built("uniform", lambda: make_graph("uniform-10k"))
+
+
+def rmat16():
+    return built("rmat16", lambda: make_graph("rmat20-32m", scale_shift=4))
+
+
+def bursty16():
+    return built("bursty16", lambda: make_graph("bursty22-1b", scale_shift=6))
+
+
+def rmat_wide():
+    return built("rmat_wide", lambda: make_graph("rmat22-256m", scale_shift=8))
+
+
+def ea_gpu(G, s, a, w):
+    out = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    K.kairos_earliest_arrival(G, s, a, w, out)
+    return K.as_u32(out)
+
+
+def print_case(*a):
+    print("case:", *a, flush=True)
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat16", "bursty16", "rmat_wide"])
+def test_index_matches_lexsort(which):
+    g, G, _ = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
+    print_case("index", which, g.n, g.m)
+    want = O.temporal_csr(g.n, g.src, g.dst, g.t, g.lam)
+    ix = {k: K.as_u32(v) for k, v in K.kairos_graph_index(G).items()}
+    assert np.array_equal(ix["off_out"], want["off_out"].astype(np.uint32))
+    assert np.array_equal(ix["off_in"], want["off_in"].astype(np.uint32))
+    assert np.array_equal(ix["t_out"], want["t_out"])
+    da = ix["dst_a_out"].reshape(-1, 2)
+    assert np.array_equal(da[:, 0], want["dst_out"]) and np.array_equal(da[:, 1], want["a_out"])
+    assert np.array_equal(ix["a_in"], want["a_in"])
+    st = ix["src_t_in"].reshape(-1, 2)
+    assert np.array_equal(st[:, 0], want["src_in"]) and np.array_equal(st[:, 1], want["t_in"])
+
+
+def test_ea_uniform_all_sources():
+    g, G, se = uniform()
+    srcs, ta, tw = make_queries("uniform-10k", g)
+    for q in range(len(srcs)):
+        print_case("ea uniform", q)
+        got = ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q]))
+        want = O.earliest_arrival(se, srcs[q], ta[q], tw[q])
+        assert np.array_equal(got, want), q
+        assert O.ea_certificate(g.n, g.src, g.dst, g.t, g.lam, int(srcs[q]), int(ta[q]), int(tw[q]), got)
+
+
+@pytest.mark.parametrize("which", ["rmat16", "bursty16", "rmat_wide"])
+def test_ea_skewed(which):
+    g, G, se = {"rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
+    name = {"rmat16": "rmat20-32m", "bursty16": "bursty22-1b", "rmat_wide": "rmat22-256m"}[which]
+    srcs, ta, tw = make_queries(name, g, count=8)
+    for q in range(len(srcs)):
+        print_case("ea", which, q)
+        got = ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q]))
+        want = O.earliest_arrival(se, srcs[q], ta[q], tw[q])
+        assert np.array_equal(got, want), q
+        tg = K.kairos_traversed_edges(G, int(ta[q]), int(tw[q]), torch.from_numpy(got.view(np.int32)).cuda())
+        assert tg == O.traversed_edges(se, ta[q], tw[q], want)
+
+
+@pytest.mark.parametrize("tuning", [dict(split=64, chunk=64), dict(split=100000, chunk=4096),
+                                    dict(rounds_per_sync=4), dict(pull_alpha=1, pull_beta=1000000),
+                                    dict(pull_alpha=8, pull_beta=24)])
+def test_ea_independent_of_tuning(tuning):
+    """Results are unique, so every launch configuration must agree bit for bit."""
+    g, G, se = rmat16()
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, **tuning)
+        srcs, ta, tw = make_queries("rmat20-32m", g, count=4)
+        for q in range(len(srcs)):
+            print_case("tuning", tuning, q)
+            got = ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q]))
+            assert np.array_equal(got, O.earliest_arrival(se, srcs[q], ta[q], tw[q]))
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+GOLD = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "*.json")))
+
+
+@pytest.mark.parametrize("path", GOLD, ids=[os.path.basename(p) for p in GOLD])
+def test_golden_on_gpu(path):
+    d = json.load(open(path))
+    e = np.array(d["edges"], np.uint32).reshape(-1, 4)
+    G = K.kairos_graph_build(*[K.to_u32_tensor(e[:, i]) for i in range(4)], d["n"])
+    out = torch.empty(d["n"], dtype=torch.int32, device="cuda")
+    args = (d["source"], d["t_alpha"], d["t_omega"], out)
+    K.kairos_earliest_arrival(G, *args)
+    assert K.as_u32(out).tolist() == d["ea"]
+    K.kairos_latest_departure(G, *args)
+    assert K.as_u32(out).tolist() == d["ld"]
+    K.kairos_fastest(G, *args)
+    assert K.as_u32(out).tolist() == d["fastest"]
+    G.free()
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_tiny_all_kinds(seed):
+    g = tiny_graph(seed, n=7, m=12, t_max=8, lam_max=3)
+    G = K.kairos_graph_build(*dev(g), g.n)
+    se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for s in range(g.n):
+        ta, tw = seed % 4, 6 + seed % 7
+        pea, pld, pf = O.profile(se, s, ta, tw)
+        K.kairos_earliest_arrival(G, s, ta, tw, out)
+        assert np.array_equal(K.as_u32(out), pea)
+        K.kairos_latest_departure(G, s, ta, tw, out)
+        assert np.array_equal(K.as_u32(out), pld)
+        K.kairos_fastest(G, s, ta, tw, out)
+        assert np.array_equal(K.as_u32(out), pf)
+    G.free()
+
+
+def test_ld_fastest_uniform():
+    g, G, se = uniform()
+    srcs, ta, tw = make_queries("uniform-10k", g)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for q in range(4):
+        print_case("ldf uniform", q)
+        pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
+        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+        assert np.array_equal(K.as_u32(out), pld), q
+        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+        assert np.array_equal(K.as_u32(out), pf), q
+
+
+def test_ld_fastest_bursty():
+    g, G, se = bursty16()
+    srcs, ta, tw = make_queries("bursty22-1b", g, count=3)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for q in range(3):
+        print_case("ldf bursty", q)
+        pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
+        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+        assert np.array_equal(K.as_u32(out), pld), q
+        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+        assert np.array_equal(K.as_u32(out), pf), q
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat_wide"])
+def test_batch_rows_equal_single(which):
+    g, G, se = {"uniform": uniform, "rmat_wide": rmat_wide}[which]()
+    name = {"uniform": "uniform-10k", "rmat_wide": "rmat22-256m"}[which]
+    srcs, ta, tw = make_queries(name, g, count=16)
+    out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+    print_case("batch", which)
+    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+    rows = K.as_u32(out).reshape(len(srcs), g.n)
+    for q in range(len(srcs)):
+        assert np.array_equal(rows[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+
+
+def test_edge_cases():
+    # empty graph
+    g = Graph(5, *(np.zeros(0, np.uint32) for _ in range(4)))
+    G = K.kairos_graph_build(*dev(g), g.n)
+    assert ea_gpu(G, 3, 7, 9).tolist() == [INF, INF, INF, 7, INF]
+    out = torch.empty(5, dtype=torch.int32, device="cuda")
+    K.kairos_latest_departure(G, 3, 7, 9, out)
+    assert K.as_u32(out).tolist() == [INF, INF, INF, 9, INF]
+    G.free()
+    # one vertex with a self-loop; window of width zero
+    g = Graph(1, np.array([0], np.uint32), np.array([0], np.uint32), np.array([5], np.uint32),
+              np.array([1], np.uint32))
+    G = K.kairos_graph_build(*dev(g), 1)
+    assert ea_gpu(G, 0, 5, 5).tolist() == [5]
+    G.free()
+    # times at the top of the range, arrival exactly TMAX
+    T = 0xFFFFFFFE
+    g = Graph(3, np.array([0, 1], np.uint32), np.array([1, 2], np.uint32),
+              np.array([T - 3, T - 1], np.uint32), np.array([2, 1], np.uint32))
+    G = K.kairos_graph_build(*dev(g), 3)
+    assert ea_gpu(G, 0, 0, T).tolist() == [0, T - 1, T]
+    G.free()
+
+
+def test_build_rejects_bad_edges():
+    ok = tiny_graph(1)
+    for field, val, status in (("src", 7, 2), ("dst", 99, 2), ("lam", 0, 2)):
+        g = tiny_graph(1)
+        getattr(g, field)[3] = val
+        with pytest.raises(K.KairosError) as ei:
+            K.kairos_graph_build(*dev(g), g.n)
+        assert ei.value.status == status
+    g = tiny_graph(1)
+    g.t[0] = 0xFFFFFFFE
+    with pytest.raises(K.KairosError):
+        K.kairos_graph_build(*dev(g), g.n)
+    G = K.kairos_graph_build(*dev(ok), ok.n)
+    out = torch.full((ok.n,), 123, dtype=torch.int32, device="cuda")
+    for args in ((ok.n, 0, 5), (0, 6, 5), (0, 0, 0xFFFFFFFF)):
+        with pytest.raises(K.KairosError) as ei:
+            K.kairos_earliest_arrival(G, *args, out)
+        assert ei.value.status == 2
+    assert (out == 123).all()
+    G.free()
