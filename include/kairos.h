@@ -142,6 +142,12 @@ typedef struct kairos_tuning {
     uint32_t batch_persistent; /* 1: batched queries run in one persistent launch  */
     uint32_t sweep_group;    /* departure times handled together by the
                                 latest-departure / fastest sweep                     */
+    uint32_t batch_layout;   /* 0: one wavefront lane per query, arrivals stored
+                                vertex-major (edges read once per 64 queries);
+                                1: one thread per query and vertex             */
+    uint32_t tail_limit;     /* frontiers of at most this many entries run in one
+                                workgroup that loops over rounds without host
+                                round trips; 0 disables                          */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);
@@ -163,7 +169,9 @@ typedef enum kairos_kernel_class {
     KAIROS_K_INIT = 2,  /* per-query state initialisation and outputs       */
     KAIROS_K_SORT = 3,  /* index build                                      */
     KAIROS_K_CHUNK = 4, /* push temporal edge map: split long adjacencies   */
-    KAIROS_K_COUNT = 5
+    KAIROS_K_TAIL = 5,  /* push temporal edge map: small frontiers, one
+                           workgroup looping over rounds                  */
+    KAIROS_K_COUNT = 6
 } kairos_kernel_class;
 
 typedef struct kairos_profile {
@@ -173,6 +181,9 @@ typedef struct kairos_profile {
     uint64_t chunk_edges;        /* out-edges read by the chunk kernel (8 B each) */
     uint64_t items;              /* frontier entries expanded by push          */
     uint64_t relaxations;        /* successful atomic minimum updates          */
+    uint64_t relax_attempts;     /* atomic minimum updates issued              */
+    uint64_t tail_edges;         /* out-edges read by the small-frontier kernel */
+    uint64_t tail_items;         /* frontier entries expanded by it             */
     uint64_t pull_edges;         /* in-edges read by pull (12 B each)          */
     uint64_t pull_vertices;      /* vertices examined by pull                  */
     uint64_t rounds;             /* frontier rounds                            */

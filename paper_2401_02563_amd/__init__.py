@@ -40,12 +40,14 @@ _u32, _u64, _i32, _p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_
 
 class kairos_tuning(ctypes.Structure):
     _fields_ = [(k, _u32) for k in ("block", "chunk", "split", "pull_alpha", "pull_beta",
-                                    "rounds_per_sync", "batch_persistent", "sweep_group")]
+                                    "rounds_per_sync", "batch_persistent", "sweep_group", "batch_layout",
+                                    "tail_limit")]
 
 
 class kairos_profile(ctypes.Structure):
-    _fields_ = [("launches", _u64 * 5), ("ms", ctypes.c_double * 5), ("edges_scanned", _u64),
-                ("chunk_edges", _u64), ("items", _u64), ("relaxations", _u64), ("pull_edges", _u64),
+    _fields_ = [("launches", _u64 * 6), ("ms", ctypes.c_double * 6), ("edges_scanned", _u64),
+                ("chunk_edges", _u64), ("items", _u64), ("relaxations", _u64), ("relax_attempts", _u64), ("tail_edges", _u64),
+                ("tail_items", _u64), ("pull_edges", _u64),
                 ("pull_vertices", _u64), ("rounds", _u64)]
 
 
@@ -280,10 +282,10 @@ def kairos_profile_enable(g: Graph, on: bool = True):
 def kairos_profile_read(g: Graph) -> dict:
     p = kairos_profile()
     _check(_L.kairos_profile_read(g.handle, ctypes.byref(p)), "kairos_profile_read")
-    names = ["push", "pull", "init", "sort", "chunk"]
+    names = ["push", "pull", "init", "sort", "chunk", "tail"]
     d = {f"launches_{k}": p.launches[i] for i, k in enumerate(names)}
     d.update({f"ms_{k}": p.ms[i] for i, k in enumerate(names)})
-    for k in ("edges_scanned", "chunk_edges", "items", "relaxations", "pull_edges", "pull_vertices", "rounds"):
+    for k in ("edges_scanned", "chunk_edges", "tail_edges", "tail_items", "items", "relaxations", "relax_attempts", "pull_edges", "pull_vertices", "rounds"):
         d[k] = getattr(p, k)
     return d
 

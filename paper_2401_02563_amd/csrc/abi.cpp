@@ -58,8 +58,10 @@ static void graph_release(kairos_graph *g)
     if (!g) return;
     for (Slot *s : g->free_slots) slot_destroy(s);
     for (Slot *s : g->batch_slots) slot_destroy(s);
+    for (VBatch *b : g->vbatches) vbatch_destroy(b);
     g->free_slots.clear();
     g->batch_slots.clear();
+    g->vbatches.clear();
     {
         std::lock_guard<std::mutex> lk(g->prof.mu);
         for (auto &p : g->prof.pending) {
@@ -193,6 +195,25 @@ int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *s
         int rc = check_query(g, src[i], t_alpha[i], t_omega[i]);
         if (rc) return rc;
     }
+    if (g->tuning.batch_layout == 0) {
+        // groups of 64 queries; groups*n must fit the 32-bit frontier items
+        const uint64_t max_groups = std::max<uint64_t>(1, 0xFFFFFFFEull / g->n);
+        const uint64_t per_q = std::min<uint64_t>((uint64_t)q, max_groups * 64);
+        for (uint64_t b = 0; b < q; b += per_q) {
+            const uint32_t k = (uint32_t)std::min<uint64_t>(per_q, q - b);
+            VBatch *vb = nullptr;
+            int rc = vbatch_acquire(g, (k + 63) / 64, &vb);
+            if (rc) return rc;
+            rc = run_vbatch(g, vb, k, src + b, t_alpha + b, t_omega + b, out + b * g->n);
+            if (rc == KAIROS_OK) {
+                vbatch_release(g, vb);
+            } else {
+                vbatch_destroy(vb);
+                return rc;
+            }
+        }
+        return KAIROS_OK;
+    }
     // queries per launch: q*n must fit the 32-bit frontier item encoding
     const uint64_t per = std::max<uint64_t>(1, std::min<uint64_t>(q, 0xFFFFFFFEull / g->n));
     for (uint64_t b = 0; b < q; b += per) {
@@ -232,7 +253,8 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
 {
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 64 || in->split < 64 ||
-        in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64)
+        in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
+        in->batch_layout > 1)
         return KAIROS_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g->pool_mu);
     const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split;
@@ -241,8 +263,10 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
         // chunk lists are sized from these values: drop cached scratch
         for (Slot *s : g->free_slots) slot_destroy(s);
         for (Slot *s : g->batch_slots) slot_destroy(s);
+        for (VBatch *b : g->vbatches) vbatch_destroy(b);
         g->free_slots.clear();
         g->batch_slots.clear();
+        g->vbatches.clear();
     }
     return KAIROS_OK;
 }
@@ -277,12 +301,15 @@ int kairos_profile_read(kairos_graph *g, kairos_profile *out)
     }
     out->edges_scanned = g->prof.edges;
     out->chunk_edges = g->prof.chunk_edges;
+    out->relax_attempts = g->prof.attempts;
+    out->tail_edges = g->prof.tail_edges;
+    out->tail_items = g->prof.tail_items;
     out->items = g->prof.items;
     out->relaxations = g->prof.relax;
     out->pull_edges = g->prof.pull_edges;
     out->pull_vertices = g->prof.pull_verts;
     out->rounds = g->prof.rounds;
-    g->prof.edges = g->prof.chunk_edges = g->prof.items = g->prof.relax = g->prof.pull_edges = g->prof.pull_verts = 0;
+    g->prof.edges = g->prof.chunk_edges = g->prof.tail_edges = g->prof.tail_items = g->prof.attempts = g->prof.items = g->prof.relax = g->prof.pull_edges = g->prof.pull_verts = 0;
     g->prof.rounds = 0;
     return KAIROS_OK;
 }

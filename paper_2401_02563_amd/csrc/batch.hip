@@ -1,0 +1,551 @@
+// Batched earliest arrival, vertex-major: one wavefront lane per query.
+//
+// Queries are taken in groups of 64, the wavefront width of gfx950.  For a
+// group, the arrival of query q at vertex v lives at arr[v][q], so the 64
+// arrivals of one vertex are one contiguous 256-byte row.  A frontier entry
+// is a vertex together with the 64-bit mask of the queries for which it must
+// be expanded.  One wavefront expands one entry: lane q claims the part of
+// the vertex's time-sorted adjacency that query q may newly use (binary
+// search on the departure times from its own arrival, atomicMin on its own
+// claim word, as in the single-query kernel), then the wavefront reads the
+// union of the claimed ranges once, 64 edges at a time, and every lane
+// checks each edge against its own range and window.  Relaxing one edge for
+// all 64 queries is one coalesced row read and, where it improves, coalesced
+// atomicMin updates.  The lanes that improved an edge's head are OR-ed into
+// that head's next-round mask; the lane whose OR found the mask empty
+// enqueues the head, which also makes every head appear once per round.
+// Unions of at least `split` edges are cut into chunks that a second kernel
+// spreads over all wavefronts, with the per-lane ranges kept in a side table.
+//
+// Compared with one query per thread (query-major), the edge stream is read
+// once per group instead of once per query and the arrival reads coalesce,
+// which is where batching pays (the paper runs its 100 sources one after the
+// other, §6.1).
+
+#include "internal.h"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+namespace kairos {
+
+namespace {
+
+constexpr int BTB = 256;   // threads per block (4 wavefronts)
+constexpr int BU = 8;      // edges in flight per lane
+
+struct BArgs {
+    const uint32_t *off;
+    const uint32_t *tt;
+    const uint2 *da;
+    uint32_t n;
+    const uint2 *qw;                 // [groups*64] {t_alpha, t_omega}
+    uint32_t *arr;                   // [groups*n*64]
+    uint32_t *done;                  // [groups*n*64]
+    unsigned long long *mask_cur;    // [groups*n]
+    unsigned long long *mask_next;   // [groups*n]
+    const uint32_t *cur;             // frontier items g*n+u
+    uint32_t *next;
+    uint32_t *cnt;                   // counters (same rotation as the single-query path)
+    uint4 *chunks;                   // {item, range slot, start, len}
+    uint32_t chunk_cap;
+    uint2 *ranges;                   // [slot*64 + lane] {lo, end}
+    uint32_t range_cap;
+    unsigned long long *stats;
+    uint32_t round;
+    uint32_t split;
+    uint32_t chunk;
+    uint32_t max_t;                  // largest departure time in the graph
+};
+
+enum : int { BCNT_RANGE = 10 };  // [10..12] rotating range-table sizes
+
+__device__ __forceinline__ uint32_t lb_u32(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor(x, o));
+    return x;
+}
+
+// Per-wavefront staging of enqueued heads in LDS, flushed 64 at a time with
+// one global atomicAdd.  `wn` is wave-uniform.
+struct WaveQueue {
+    uint32_t *buf;
+    uint32_t wn;
+};
+
+__device__ __forceinline__ void wq_flush(const BArgs &A, WaveQueue &Q, uint32_t *next_cnt)
+{
+    if (Q.wn == 0) return;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(next_cnt, Q.wn);
+    base = __shfl(base, 0);
+    __builtin_amdgcn_wave_barrier();
+    if (lane < Q.wn) A.next[base + lane] = Q.buf[lane];
+    __builtin_amdgcn_wave_barrier();
+    Q.wn = 0;
+}
+
+// Relax edges [c0, c0 + cnt) of group g for every lane whose claimed range
+// [lo, end) holds them.  All loads of BU edges are issued before use.
+__device__ __forceinline__ void relax_span(const BArgs &A, uint32_t g, uint32_t c0, uint32_t total_end,
+                                           bool has, uint32_t lo, uint32_t end, uint32_t tw, WaveQueue &Q,
+                                           uint32_t *next_cnt, unsigned long long &n_relax)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const size_t gbase = (size_t)g * A.n;
+    for (uint32_t b0 = c0; b0 < total_end; b0 += 64) {
+        const uint32_t e_l = b0 + lane;
+        const uint2 dv = e_l < total_end ? A.da[e_l] : make_uint2(0u, INF);
+        const uint32_t cnt = min(64u, total_end - b0);
+        for (uint32_t k0 = 0; k0 < cnt; k0 += BU) {
+            uint32_t vk[BU], ak[BU], cur[BU];
+            bool ok[BU];
+#pragma unroll
+            for (int j = 0; j < BU; ++j) {
+                const uint32_t k = k0 + j;
+                vk[j] = __shfl(dv.x, k & 63);
+                ak[j] = __shfl(dv.y, k & 63);
+                const uint32_t ek = b0 + k;
+                ok[j] = k < cnt && has && ek >= lo && ek < end && ak[j] <= tw;
+                cur[j] = ok[j] ? A.arr[(gbase + vk[j]) * 64 + lane] : 0u;
+            }
+            // all BU atomic minima of this lane are in flight together
+            uint32_t old[BU];
+#pragma unroll
+            for (int j = 0; j < BU; ++j) {
+                ok[j] = ok[j] && ak[j] < cur[j];
+                old[j] = ok[j] ? atomicMin(&A.arr[(gbase + vk[j]) * 64 + lane], ak[j]) : 0u;
+            }
+            unsigned long long mymask = 0;
+            uint32_t myv = 0;
+#pragma unroll
+            for (int j = 0; j < BU; ++j) {
+                const bool succ = ok[j] && ak[j] < old[j];
+                n_relax += succ ? 1ull : 0ull;
+                const unsigned long long b = __ballot(succ);
+                if (lane == (uint32_t)j) {
+                    mymask = b;
+                    myv = vk[j];
+                }
+            }
+            // lanes 0..BU-1 publish the improved heads in parallel
+            bool first = false;
+            if (mymask) {
+                const unsigned long long old = atomicOr(&A.mask_next[gbase + myv], mymask);
+                first = old == 0ull;
+            }
+            const unsigned long long fb = __ballot(first);
+            if (fb) {
+                const uint32_t pos = Q.wn + __popcll(fb & ((1ull << lane) - 1ull));
+                if (first) Q.buf[pos] = (uint32_t)(gbase + myv);
+                __builtin_amdgcn_wave_barrier();
+                Q.wn += __popcll(fb);
+                if (Q.wn > 64 - BU) wq_flush(A, Q, next_cnt);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(BTB) void bpush_kernel(BArgs A)
+{
+    __shared__ uint32_t s_q[BTB / 64][64];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wid = threadIdx.x >> 6;
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t F = A.cnt[CNT_FRONT + r3];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
+        A.cnt[BCNT_RANGE + (A.round + 1u) % 3u] = 0u;
+    }
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
+    uint32_t *range_cnt = &A.cnt[BCNT_RANGE + r3];
+    WaveQueue Q{s_q[wid], 0};
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+    const uint32_t waves = gridDim.x * (BTB / 64);
+    for (uint32_t i = blockIdx.x * (BTB / 64) + wid; i < F; i += waves) {
+        const uint32_t item = A.cur[i];
+        const uint32_t g = item / A.n;
+        const uint32_t u = item - g * A.n;
+        const unsigned long long M = A.mask_cur[item];
+        if (lane == 0) A.mask_cur[item] = 0ull;  // reused as a next-round mask
+        const bool active = (M >> lane) & 1ull;
+        const uint2 w = A.qw[(size_t)g * 64 + lane];
+        const uint32_t b = A.off[u], e = A.off[u + 1];
+        uint32_t lo = 0, end = 0;
+        if (active) {
+            n_items += 1;
+            // one wavefront per entry per round, rounds are separate launches:
+            // plain reads and writes of the lane's own arrival and claim word
+            const size_t slot = (size_t)item * 64 + lane;
+            const uint32_t r = A.arr[slot];
+            const uint32_t old = A.done[slot];
+            lo = lb_u32(A.tt, b, old == INF ? e : min(old, e), r);
+            end = old == INF ? (w.y > A.max_t ? e : lb_u32(A.tt, lo, e, w.y)) : old;
+            if (end < lo) end = lo;
+            if (lo < end) A.done[slot] = lo;
+        }
+        const bool has = active && lo < end;
+        if (!__ballot(has)) continue;
+        uint32_t umin = wave_min(has ? lo : INF);
+        const uint32_t umax = wave_max(has ? end : 0u);
+        n_edges += umax - umin;
+        if (umax - umin >= A.split) {
+            uint32_t rs = 0;
+            if (lane == 0) rs = atomicAdd(range_cnt, 1u);
+            rs = __shfl(rs, 0);
+            if (rs < A.range_cap) {
+                A.ranges[(size_t)rs * 64 + lane] = has ? make_uint2(lo, end) : make_uint2(0u, 0u);
+                const uint32_t L = umax - umin;
+                const uint32_t nch = (L + A.chunk - 1) / A.chunk;
+                uint32_t cb = 0;
+                if (lane == 0) cb = atomicAdd(chunk_cnt, nch);
+                cb = __shfl(cb, 0);
+                const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
+                for (uint32_t k = lane; k < fit; k += 64)
+                    A.chunks[cb + k] = make_uint4(item, rs, umin + k * A.chunk, min(A.chunk, L - k * A.chunk));
+                const uint32_t covered = (uint32_t)min((uint64_t)L, (uint64_t)fit * A.chunk);
+                umin += covered;
+                n_edges -= covered;  // the chunk kernel counts what it reads
+            }
+        }
+        if (umin < umax) relax_span(A, g, umin, umax, has, lo, end, w.y, Q, next_cnt, n_relax);
+    }
+    wq_flush(A, Q, next_cnt);
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_relax += __shfl_xor(n_relax, o);
+            n_items += __shfl_xor(n_items, o);
+        }
+        if (lane == 0) {
+            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
+            if (n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BTB) void bchunk_kernel(BArgs A)
+{
+    __shared__ uint32_t s_q[BTB / 64][64];
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wid = threadIdx.x >> 6;
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    WaveQueue Q{s_q[wid], 0};
+    unsigned long long n_edges = 0, n_relax = 0;
+    const uint32_t waves = gridDim.x * (BTB / 64);
+    for (uint32_t c = blockIdx.x * (BTB / 64) + wid; c < C; c += waves) {
+        const uint4 ch = A.chunks[c];
+        const uint32_t g = ch.x / A.n;
+        const uint2 rg = A.ranges[(size_t)ch.y * 64 + lane];
+        const uint2 w = A.qw[(size_t)g * 64 + lane];
+        n_edges += ch.w;
+        relax_span(A, g, ch.z, ch.z + ch.w, rg.x < rg.y, rg.x, rg.y, w.y, Q, next_cnt, n_relax);
+    }
+    wq_flush(A, Q, next_cnt);
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
+        if (lane == 0) {
+            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+            if (n_edges) atomicAdd(&A.stats[ST_CHUNK_EDGES], n_edges);
+        }
+    }
+}
+
+// Group start: every query's source gets its t_alpha and its mask bit; the
+// lane that finds the source's mask empty enqueues it.
+__global__ void binit_kernel(BArgs A, const uint4 *__restrict__ hq, uint32_t q)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < q; i += gridDim.x * blockDim.x) {
+        const uint4 p = hq[i];  // {src, ta, tw, _}
+        const uint32_t g = i / 64, lane = i % 64;
+        const size_t item = (size_t)g * A.n + p.x;
+        ((uint2 *)A.qw)[i] = make_uint2(p.y, p.z);
+        A.arr[item * 64 + lane] = p.y;
+        const unsigned long long old = atomicOr(&A.mask_cur[item], 1ull << lane);
+        if (old == 0ull) {
+            const uint32_t pos = atomicAdd(&A.cnt[CNT_FRONT + A.round % 3u], 1u);
+            A.next[pos] = (uint32_t)item;  // `next` names the first round's queue here
+        }
+    }
+}
+
+// out[(g*64+q)*n + v] = arr[(g*n+v)*64 + q] through a 64x64 LDS tile.
+__global__ __launch_bounds__(256) void btranspose_kernel(const uint32_t *__restrict__ arr, uint32_t *__restrict__ out,
+                                                         uint32_t n, uint32_t q_total, uint32_t groups)
+{
+    __shared__ uint32_t tile[64][65];
+    const uint32_t tiles_v = (n + 63) / 64;
+    for (uint64_t t = blockIdx.x; t < (uint64_t)tiles_v * groups; t += gridDim.x) {
+        const uint32_t g = (uint32_t)(t / tiles_v);
+        const uint32_t v0 = (uint32_t)(t % tiles_v) * 64;
+        for (int k = threadIdx.x; k < 64 * 64; k += 256) {
+            const uint32_t vv = k / 64, qq = k % 64;
+            if (v0 + vv < n) tile[vv][qq] = arr[((size_t)g * n + v0 + vv) * 64 + qq];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < 64 * 64; k += 256) {
+            const uint32_t qq = k / 64, vv = k % 64;
+            const uint32_t qg = g * 64 + qq;
+            if (qg < q_total && v0 + vv < n) out[(size_t)qg * n + v0 + vv] = tile[vv][qq];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void bfill_kernel(uint32_t *p, uint64_t count, uint32_t value)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+int gridc(uint64_t work, int per_block, int cap)
+{
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+// Device state of one vertex-major batch (kept by the graph between calls).
+struct VBatch {
+    uint32_t groups = 0, n = 0;
+    uint32_t *arr = nullptr, *done = nullptr, *queue[2] = {nullptr, nullptr}, *cnt = nullptr;
+    unsigned long long *mask[2] = {nullptr, nullptr};
+    uint2 *qw = nullptr;
+    uint4 *chunks = nullptr;
+    uint2 *ranges = nullptr;
+    uint64_t chunk_cap = 0, range_cap = 0;
+    unsigned long long *stats = nullptr;
+    uint32_t *h_pin = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+void vbatch_destroy(VBatch *b)
+{
+    if (!b) return;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    dev_free(b->arr);
+    dev_free(b->done);
+    dev_free(b->queue[0]);
+    dev_free(b->queue[1]);
+    dev_free(b->cnt);
+    dev_free(b->mask[0]);
+    dev_free(b->mask[1]);
+    dev_free(b->qw);
+    dev_free(b->chunks);
+    dev_free(b->ranges);
+    dev_free(b->stats);
+    if (b->h_pin) hipHostFree(b->h_pin);
+    if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+    delete b;
+}
+
+static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
+{
+    VBatch *b = new VBatch();
+    b->groups = groups;
+    b->n = g->n;
+    const size_t gn = (size_t)groups * g->n;
+    b->arr = (uint32_t *)dev_alloc(gn * 64 * 4, nullptr);
+    b->done = (uint32_t *)dev_alloc(gn * 64 * 4, nullptr);
+    b->queue[0] = (uint32_t *)dev_alloc(gn * 4 + 256, nullptr);
+    b->queue[1] = (uint32_t *)dev_alloc(gn * 4 + 256, nullptr);
+    b->cnt = (uint32_t *)dev_alloc(64 * 4, nullptr);
+    b->mask[0] = (unsigned long long *)dev_alloc(gn * 8, nullptr);
+    b->mask[1] = (unsigned long long *)dev_alloc(gn * 8, nullptr);
+    b->qw = (uint2 *)dev_alloc((size_t)groups * 64 * sizeof(uint2), nullptr);
+    const uint64_t per_g = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
+                           g->m / std::max<uint32_t>(g->tuning.split, 64) + 1;
+    b->chunk_cap = std::min<uint64_t>((uint64_t)groups * per_g, 1ull << 26);
+    b->range_cap = std::min<uint64_t>((uint64_t)groups * (g->m / std::max<uint32_t>(g->tuning.split, 64) + 1),
+                                      1ull << 22);
+    if (const char *cap = std::getenv("KAIROS_TEST_CHUNK_CAP")) {
+        b->chunk_cap = std::strtoull(cap, nullptr, 10);
+        b->range_cap = std::min<uint64_t>(b->range_cap, b->chunk_cap);
+    }
+    b->chunks = (uint4 *)dev_alloc(std::max<uint64_t>(b->chunk_cap, 1) * sizeof(uint4), nullptr);
+    b->ranges = (uint2 *)dev_alloc(std::max<uint64_t>(b->range_cap, 1) * 64 * sizeof(uint2), nullptr);
+    b->stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, nullptr);
+    bool ok = b->arr && b->done && b->queue[0] && b->queue[1] && b->cnt && b->mask[0] && b->mask[1] && b->qw &&
+              b->chunks && b->ranges && b->stats;
+    if (ok && hipHostMalloc((void **)&b->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
+        b->h_pin = nullptr;
+        ok = false;
+    }
+    if (ok) {
+        if (g->stream) {
+            b->stream = g->stream;
+        } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess) {
+            b->own_stream = true;
+        } else {
+            ok = false;
+        }
+    }
+    if (ok)
+        ok = hipMemsetAsync(b->stats, 0, ST_WORDS * 8, b->stream) == hipSuccess &&
+             hipMemsetAsync(b->mask[0], 0, gn * 8, b->stream) == hipSuccess &&
+             hipMemsetAsync(b->mask[1], 0, gn * 8, b->stream) == hipSuccess &&
+             hipStreamSynchronize(b->stream) == hipSuccess;
+    if (!ok) {
+        vbatch_destroy(b);
+        return KAIROS_ERR_NOMEM;
+    }
+    *out = b;
+    return KAIROS_OK;
+}
+
+static int bfill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t v)
+{
+    hipLaunchKernelGGL(bfill_kernel, dim3(gridc(count, 256 * 8, 16384)), dim3(256), 0, st, p, count, v);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// q queries (q <= 64 * groups of b); out is query-major [q][n].
+int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, const uint32_t *ta,
+               const uint32_t *tw, uint32_t *out)
+{
+    hipStream_t st = b->stream;
+    const uint32_t groups = (q + 63) / 64;
+    const size_t gn = (size_t)groups * g->n;
+    int rc;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = bfill(st, b->arr, gn * 64, INF))) return rc;
+    if ((rc = bfill(st, b->done, gn * 64, INF))) return rc;
+    KAIROS_HIP(hipMemsetAsync(b->cnt, 0, 64 * 4, st));
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    // masks are left all-zero by every completed run (each processed entry
+    // clears its word); a failed run destroys this state instead
+
+    std::vector<uint4> hq(q);
+    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(src[i], ta[i], tw[i], 0);
+    uint4 *staging = nullptr;
+    if (hipHostMalloc((void **)&staging, std::max<size_t>(q, 1) * sizeof(uint4), hipHostMallocDefault) != hipSuccess)
+        return KAIROS_ERR_NOMEM;
+    std::memcpy(staging, hq.data(), q * sizeof(uint4));
+
+    BArgs A{};
+    A.off = g->off_out;
+    A.tt = g->t_out;
+    A.da = g->da_out;
+    A.n = g->n;
+    A.qw = b->qw;
+    A.arr = b->arr;
+    A.done = b->done;
+    A.cnt = b->cnt;
+    A.chunks = b->chunks;
+    A.chunk_cap = (uint32_t)std::min<uint64_t>(b->chunk_cap, 0xFFFFFFF0u);
+    A.ranges = b->ranges;
+    A.range_cap = (uint32_t)b->range_cap;
+    A.stats = b->stats;
+    A.split = std::max<uint32_t>(g->tuning.split, 64);
+    A.chunk = std::max<uint32_t>(g->tuning.chunk, 64);
+    A.max_t = g->max_t;
+    A.round = 0;
+    A.mask_cur = b->mask[0];
+    A.mask_next = b->mask[1];
+    A.next = b->queue[0];
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(binit_kernel, dim3(gridc(q, 256, 64)), dim3(256), 0, st, A, staging, q);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        hipHostFree(staging);
+        return KAIROS_ERR_DEVICE;
+    }
+    hipHostFree(staging);
+    KAIROS_HIP(hipMemcpyAsync(b->h_pin, b->cnt, 64, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    uint32_t F = b->h_pin[CNT_FRONT];
+    const int wave_cap = std::max(1, g->num_cus * 8);
+    uint32_t r = 0;
+    while (F > 0) {
+        A.round = r;
+        A.cur = b->queue[0];
+        A.next = b->queue[1];
+        A.mask_cur = b->mask[r & 1];
+        A.mask_next = b->mask[(r + 1) & 1];
+        prof_begin(g, st, &ev);
+        hipLaunchKernelGGL(bpush_kernel, dim3(gridc(F, BTB / 64, wave_cap)), dim3(BTB), 0, st, A);
+        prof_end(g, st, KAIROS_K_PUSH, ev);
+        prof_begin(g, st, &ev);
+        hipLaunchKernelGGL(bchunk_kernel, dim3(std::max(1, g->num_cus * 8)), dim3(BTB), 0, st, A);
+        prof_end(g, st, KAIROS_K_CHUNK, ev);
+        KAIROS_HIP(hipGetLastError());
+        ++r;
+        std::swap(b->queue[0], b->queue[1]);
+        KAIROS_HIP(hipMemcpyAsync(b->h_pin, b->cnt, 64, hipMemcpyDeviceToHost, st));
+        KAIROS_HIP(hipStreamSynchronize(st));
+        F = b->h_pin[CNT_FRONT + r % 3u];
+        if (g->prof.on) {
+            std::lock_guard<std::mutex> lk(g->prof.mu);
+            g->prof.rounds += 1;
+        }
+    }
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(btranspose_kernel, dim3(gridc((uint64_t)((g->n + 63) / 64) * groups, 1, 16384)), dim3(256), 0,
+                       st, b->arr, out, g->n, q, groups);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    KAIROS_HIP(hipStreamSynchronize(st));
+    if (g->prof.on) {
+        unsigned long long h[ST_WORDS];
+        KAIROS_HIP(hipMemcpy(h, b->stats, sizeof(h), hipMemcpyDeviceToHost));
+        KAIROS_HIP(hipMemset(b->stats, 0, sizeof(h)));
+        prof_add_stats(g, h);
+    }
+    return KAIROS_OK;
+}
+
+int vbatch_acquire(kairos_graph *g, uint32_t groups, VBatch **out)
+{
+    {
+        std::lock_guard<std::mutex> lk(g->pool_mu);
+        for (size_t i = 0; i < g->vbatches.size(); ++i)
+            if (g->vbatches[i]->groups >= groups) {
+                *out = g->vbatches[i];
+                g->vbatches.erase(g->vbatches.begin() + i);
+                return KAIROS_OK;
+            }
+        for (VBatch *b : g->vbatches) vbatch_destroy(b);
+        g->vbatches.clear();
+    }
+    return vbatch_alloc(g, groups, out);
+}
+
+void vbatch_release(kairos_graph *g, VBatch *b)
+{
+    std::lock_guard<std::mutex> lk(g->pool_mu);
+    g->vbatches.push_back(b);
+}
+
+}  // namespace kairos

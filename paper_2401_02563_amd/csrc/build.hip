@@ -390,6 +390,7 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
             break;
         }
         const uint32_t max_t = h_stats[1], max_a = h_stats[2], min_l = h_stats[3], max_l = h_stats[4];
+        g->max_t = max_t;
         const int nb = bits_for(n - 1);
         const int lb = bits_for(max_l - min_l);
         std::vector<Pass> out_p, in_p;

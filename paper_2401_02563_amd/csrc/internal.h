@@ -65,18 +65,21 @@ enum : int {
     CNT_CHUNK = 3,   // [3..5] rotating chunk-list sizes
     CNT_ERR = 6,     // sticky error bits
     CNT_PULLVOL = 7, // [7..9] rotating: out-edges of the next frontier (saturating)
+    CNT_TAIL_ROUND = 13, CNT_TAIL_WHICH = 14, CNT_TAIL_ROUNDS = 15,  // left by the tail kernel
     CNT_WORDS = 16
 };
 enum : int {
-    ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5,
-    ST_WORDS = 8
+    ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5, ST_ATTEMPTS = 6,
+    ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_WORDS = 16
 };
+
+struct VBatch;
 
 struct ProfileAcc {
     bool on = false;
     uint64_t launches[KAIROS_K_COUNT] = {};
     double ms[KAIROS_K_COUNT] = {};
-    uint64_t edges = 0, chunk_edges = 0, items = 0, relax = 0, pull_edges = 0, pull_verts = 0, rounds = 0;
+    uint64_t edges = 0, chunk_edges = 0, tail_edges = 0, tail_items = 0, attempts = 0, items = 0, relax = 0, pull_edges = 0, pull_verts = 0, rounds = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> free_events;
     std::mutex mu;
@@ -96,6 +99,7 @@ struct kairos_graph {
     uint32_t *a_in = nullptr;     // m
     uint2 *st_in = nullptr;       // m: {tail, departure}
     uint32_t max_out_degree = 0;
+    uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
     uint64_t index_bytes = 0;
     hipStream_t stream = nullptr; // caller's stream, or nullptr
     int device = 0;
@@ -104,6 +108,7 @@ struct kairos_graph {
     std::mutex pool_mu;
     std::vector<kairos::Slot *> free_slots;   // single-query slots
     std::vector<kairos::Slot *> batch_slots;  // batch slots (any qcap)
+    std::vector<kairos::VBatch *> vbatches;   // vertex-major batch state
     kairos::ProfileAcc prof;
 };
 
@@ -124,6 +129,13 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uin
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
               const uint32_t *tw, uint32_t *out);
 int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);
+
+// batch.hip: vertex-major batches of up to 64 queries per group
+int vbatch_acquire(kairos_graph *g, uint32_t groups, VBatch **out);
+void vbatch_release(kairos_graph *g, VBatch *b);
+void vbatch_destroy(VBatch *b);
+int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, const uint32_t *ta,
+               const uint32_t *tw, uint32_t *out);
 
 // Device state of a multi-slot round loop driven by the server (query
 // slots q in [0, qcap), query-major arrays of qcap*n words).

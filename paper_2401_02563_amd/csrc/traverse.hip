@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -68,6 +69,7 @@ struct TravArgs {
     uint32_t nq;             // queries (dense pull covers nq*n vertices)
     uint32_t track_volume;   // accumulate out-degree of enqueued vertices
     uint32_t *qflag;         // per query: round+1 when it enqueued something (or null)
+    uint32_t max_t;          // largest departure time in the graph
 };
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t lo,
@@ -110,38 +112,114 @@ __device__ __forceinline__ void enqueue(const TravArgs &A, bool push, uint32_t i
     }
 }
 
-// Relax out-edge e of query q: returns true when the head must be enqueued.
+// Edges are relaxed UNR at a time per lane: all loads of the group are
+// issued before any result is used, so each lane keeps several independent
+// memory requests in flight (the edge record, then the head's arrival).
+constexpr int UNR = 4;
+
+struct EdgeGroup {
+    uint32_t v[UNR], a[UNR], q[UNR], tw[UNR], sd[UNR], cur[UNR];
+    bool ok[UNR];
+};
+
+// Relax a group of UNR edges per lane.  The arrival reads, the atomic
+// minima and the stamp exchanges of the group are each issued together (they
+// are independent), so a lane waits for one round trip per stage instead of
+// one per edge, and the whole group is enqueued with a single atomicAdd per
+// wavefront.
 template <bool SWEEP>
-__device__ __forceinline__ bool relax(const TravArgs &A, uint32_t q, uint32_t e, uint32_t tw,
-                                      uint32_t sdep, uint32_t &item, uint32_t &vout,
-                                      unsigned long long &nrelax)
+__device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uint32_t *next_cnt,
+                                            uint32_t *vol_cnt, unsigned long long &nrelax)
 {
-    const uint2 dv = A.da[e];
-    const uint32_t v = dv.x, a = dv.y;
-    vout = v;
-    if (a > tw) return false;
-    const size_t sv = (size_t)q * A.n + v;
-    item = (uint32_t)sv;
-    if (!(a < A.arr[sv])) return false;
-    const uint32_t old = atomicMin(&A.arr[sv], a);
-    if (!(a < old)) return false;
-    ++nrelax;
-    if (SWEEP && sdep != INF) {
-        atomicMin(&A.fa[sv], a - sdep);
-        atomicMax(&A.l1[sv], sdep + 1u);
+    size_t sv[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        G.ok[k] = G.ok[k] && G.a[k] <= G.tw[k];
+        sv[k] = (size_t)G.q[k] * A.n + G.v[k];
+        G.cur[k] = G.ok[k] ? A.arr[sv[k]] : 0u;
     }
-    return atomicExch(&A.stamp[sv], A.stamp_val) != A.stamp_val;
+    uint32_t old[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        G.ok[k] = G.ok[k] && G.a[k] < G.cur[k];
+        old[k] = G.ok[k] ? atomicMin(&A.arr[sv[k]], G.a[k]) : 0u;
+    }
+    uint32_t st[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        nrelax += G.ok[k] ? (1ull << 32) : 0ull;  // high half: atomic attempts
+        G.ok[k] = G.ok[k] && G.a[k] < old[k];
+        nrelax += G.ok[k] ? 1ull : 0ull;
+        st[k] = G.ok[k] ? atomicExch(&A.stamp[sv[k]], A.stamp_val) : A.stamp_val;
+    }
+    if (SWEEP) {
+#pragma unroll
+        for (int k = 0; k < UNR; ++k)
+            if (G.ok[k] && G.sd[k] != INF) {
+                atomicMin(&A.fa[sv[k]], G.a[k] - G.sd[k]);
+                atomicMax(&A.l1[sv[k]], G.sd[k] + 1u);
+            }
+    }
+    unsigned long long bal[UNR];
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        bal[k] = __ballot(st[k] != A.stamp_val);
+        total += __popcll(bal[k]);
+    }
+    if (total == 0) return;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(next_cnt, total);
+    base = __shfl(base, 0);
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        if (bal[k] >> lane & 1ull) {
+            A.next[base + __popcll(bal[k] & lt)] = (uint32_t)sv[k];
+            if (A.qflag) A.qflag[G.q[k]] = A.round + 1u;
+            if (A.track_volume) {
+                const uint32_t deg = A.off[G.v[k] + 1] - A.off[G.v[k]];
+                if (deg) atomicAdd(vol_cnt, deg);
+            }
+        }
+        base += __popcll(bal[k]);
+    }
 }
 
+__device__ __forceinline__ void stats_flush(const TravArgs &A, unsigned long long n_relax,
+                                            unsigned long long n_items, int edge_slot,
+                                            unsigned long long n_edges_block)
+{
+    if (!A.stats) return;
+    unsigned long long n_att = n_relax >> 32;
+    n_relax &= 0xFFFFFFFFull;
+    for (int o = 32; o > 0; o >>= 1) {
+        n_relax += __shfl_xor(n_relax, o);
+        n_att += __shfl_xor(n_att, o);
+        n_items += __shfl_xor(n_items, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+        if (n_att) atomicAdd(&A.stats[ST_ATTEMPTS], n_att);
+        if (n_items) atomicAdd(&A.stats[edge_slot == ST_TAIL_EDGES ? ST_TAIL_ITEMS : ST_ITEMS], n_items);
+    }
+    if (threadIdx.x == 0 && n_edges_block) atomicAdd(&A.stats[edge_slot], n_edges_block);
+}
+
+// Push round, part 1: one thread per frontier item claims the newly usable
+// part of its adjacency; short claims are relaxed by the block with a
+// prefix-sum load balance, claims of at least `split` edges are cut into
+// chunks for part 2.
 template <bool SWEEP>
 __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
 {
-    __shared__ unsigned long long s_pref[TB + 1];
+    __shared__ uint32_t s_pref[TB + 1];
     __shared__ uint32_t s_lo[TB];
     __shared__ uint32_t s_q[TB];
     __shared__ uint32_t s_tw[TB];
     __shared__ uint32_t s_sd[TB];
-    __shared__ unsigned long long s_wsum[TB / 64];
+    __shared__ uint32_t s_wsum[TB / 64];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -160,7 +238,7 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
 
     for (uint32_t base = blockIdx.x * TB; base < F; base += gridDim.x * TB) {
         const uint32_t i = base + tid;
-        uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0;
+        uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, ser_lo = 0, ser_len = 0;
         if (i < F) {
             ++n_items;
             const uint32_t item = A.cur[i];
@@ -170,13 +248,19 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
             tw = p.z;
             sd = p.w;
             const size_t su = (size_t)q * A.n + u;
-            const uint32_t r = __hip_atomic_load(&A.arr[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // Each (query, vertex) is expanded by one thread per round (round
+            // stamps), and rounds are separate launches, so the tail's
+            // arrival and its claim word need no atomics here.
+            const uint32_t r = A.arr[su];
             const uint32_t b = A.off[u], e = A.off[u + 1];
-            lo = lower_bound_u32(A.tt, b, e, r);
-            const uint32_t old = atomicMin(&A.done[su], lo);
+            const uint32_t old = A.done[su];
+            lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), r);
             uint32_t end = old;
-            if (old == INF) end = lower_bound_u32(A.tt, lo, e, tw);
-            if (lo < end) len = end - lo;
+            if (old == INF) end = tw > A.max_t ? e : lower_bound_u32(A.tt, lo, e, tw);
+            if (lo < end) {
+                len = end - lo;
+                A.done[su] = lo;
+            }
             if (len >= A.split) {
                 const uint32_t nch = (len + A.chunk - 1) / A.chunk;
                 const uint32_t cb = atomicAdd(chunk_cnt, nch);
@@ -188,12 +272,19 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
                 const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
                 lo += covered;
                 len -= covered;
+                if (len >= A.split) {
+                    // chunk list full: this lane walks the rest by itself
+                    ser_lo = lo;
+                    ser_len = len;
+                    len = 0;
+                }
             }
         }
-        // exclusive prefix sum of len over the block
-        unsigned long long x = len;
+        // exclusive prefix sum of len over the block (short claims only, so
+        // the block total stays below TB * split)
+        uint32_t x = len;
         for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long y = __shfl_up(x, o);
+            const uint32_t y = __shfl_up(x, o);
             if (lane >= o) x += y;
         }
         if (lane == 63) s_wsum[w] = x;
@@ -202,7 +293,7 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
         s_tw[tid] = tw;
         s_sd[tid] = sd;
         __syncthreads();
-        unsigned long long woff = 0, total = 0;
+        uint32_t woff = 0, total = 0;
         for (int w2 = 0; w2 < TB / 64; ++w2) {
             if (w2 < w) woff += s_wsum[w2];
             total += s_wsum[w2];
@@ -211,36 +302,59 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
         if (tid == 0) s_pref[TB] = total;
         __syncthreads();
         n_edges += total;
-        for (unsigned long long j = tid; j < total; j += TB) {
-            // owner: the last k with s_pref[k] <= j
-            int lo_k = 0, hi_k = TB;
-            while (hi_k - lo_k > 1) {
-                const int mid = (lo_k + hi_k) >> 1;
-                if (s_pref[mid] <= j)
-                    lo_k = mid;
-                else
-                    hi_k = mid;
+        for (uint32_t j0 = 0; j0 < total; j0 += TB * UNR) {
+            EdgeGroup G;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const uint32_t j = j0 + k * TB + tid;
+                G.ok[k] = j < total;
+                int lo_k = 0, hi_k = TB;
+                if (G.ok[k]) {
+                    // owner: the last item whose prefix is <= j
+                    while (hi_k - lo_k > 1) {
+                        const int mid = (lo_k + hi_k) >> 1;
+                        if (s_pref[mid] <= j)
+                            lo_k = mid;
+                        else
+                            hi_k = mid;
+                    }
+                }
+                const uint32_t e = s_lo[lo_k] + (j - s_pref[lo_k]);
+                const uint2 dv = G.ok[k] ? A.da[e] : make_uint2(0, 0);
+                G.v[k] = dv.x;
+                G.a[k] = dv.y;
+                G.q[k] = s_q[lo_k];
+                G.tw[k] = s_tw[lo_k];
+                G.sd[k] = s_sd[lo_k];
             }
-            const uint32_t e = s_lo[lo_k] + (uint32_t)(j - s_pref[lo_k]);
-            uint32_t item = 0, v = 0;
-            const bool push = relax<SWEEP>(A, s_q[lo_k], e, s_tw[lo_k], s_sd[lo_k], item, v, n_relax);
-            enqueue(A, push, item, v, next_cnt, vol_cnt);
+            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
         }
+        // overflow of the chunk list (not expected with the list sized from
+        // the tuning): per-lane walk, wave-uniform trip count
+        unsigned long long ser_done = 0;
+        while (__ballot(ser_done < ser_len)) {
+            EdgeGroup G;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                G.ok[k] = ser_done < ser_len;
+                const uint2 dv = G.ok[k] ? A.da[ser_lo + (uint32_t)ser_done] : make_uint2(0, 0);
+                if (G.ok[k]) ++ser_done;
+                G.v[k] = dv.x;
+                G.a[k] = dv.y;
+                G.q[k] = q;
+                G.tw[k] = tw;
+                G.sd[k] = sd;
+            }
+            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
+        }
+        if (ser_len && A.stats) atomicAdd(&A.stats[ST_EDGES], (unsigned long long)ser_len);
         __syncthreads();
     }
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) {
-            n_relax += __shfl_xor(n_relax, o);
-            n_items += __shfl_xor(n_items, o);
-        }
-        if (lane == 0) {
-            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
-        }
-        if (tid == 0 && n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
-    }
+    stats_flush(A, n_relax, n_items, ST_EDGES, n_edges);
 }
 
+// Push round, part 2: every wave takes whole chunks (grid-stride over the
+// chunk list) and relaxes their edges UNR per lane at a time.
 template <bool SWEEP>
 __global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
 {
@@ -249,21 +363,192 @@ __global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
     uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     unsigned long long n_edges = 0, n_relax = 0;
-    for (uint32_t c = blockIdx.x; c < C; c += gridDim.x) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (TB / 64);
+    for (uint32_t c = blockIdx.x * (TB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
         const uint4 ch = A.chunks[c];
         const uint4 p = A.qp[ch.x];
         n_edges += ch.z;
-        for (uint32_t k = threadIdx.x; k < ch.z; k += TB) {
-            uint32_t item = 0, v = 0;
-            const bool push = relax<SWEEP>(A, ch.x, ch.y + k, p.z, p.w, item, v, n_relax);
-            enqueue(A, push, item, v, next_cnt, vol_cnt);
+        for (uint32_t k0 = 0; k0 < ch.z; k0 += 64 * UNR) {
+            EdgeGroup G;
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const uint32_t off = k0 + k * 64 + lane;
+                G.ok[k] = off < ch.z;
+                const uint2 dv = G.ok[k] ? A.da[ch.y + off] : make_uint2(0, 0);
+                G.v[k] = dv.x;
+                G.a[k] = dv.y;
+                G.q[k] = ch.x;
+                G.tw[k] = p.z;
+                G.sd[k] = p.w;
+            }
+            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
         }
     }
+    // edges: lane 0 of each wave holds its chunk total
+    unsigned long long blk = 0;
     if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
-        if ((threadIdx.x & 63) == 0 && n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-        if (threadIdx.x == 0 && n_edges) atomicAdd(&A.stats[ST_CHUNK_EDGES], n_edges);
+        __shared__ unsigned long long s_e[TB / 64];
+        if (lane == 0) s_e[threadIdx.x >> 6] = n_edges;
+        __syncthreads();
+        for (int w2 = 0; w2 < TB / 64; ++w2) blk += s_e[w2];
     }
+    stats_flush(A, n_relax, 0, ST_CHUNK_EDGES, blk);
+}
+
+// Small-frontier rounds in one workgroup.  While the frontier holds at most
+// `limit` entries, one 1024-thread workgroup runs round after round with a
+// workgroup barrier in between, keeping the frontier count in LDS; it stops
+// when the frontier is empty, outgrows the limit, or after `max_rounds`, and
+// leaves the round number, the queue holding the frontier and its size for
+// the host.  One workgroup never waits on another, so nothing here depends
+// on which workgroups are resident.  The tail's arrival is read with an
+// agent-scope atomic load: within one launch a cached copy may predate the
+// improvement that put the vertex in the frontier.
+constexpr int TT = 1024;
+
+template <bool SWEEP>
+__global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, uint32_t limit,
+                                                  uint32_t vol_limit, uint32_t max_rounds, uint32_t *q0,
+                                                  uint32_t *q1)
+{
+    __shared__ uint32_t s_pref[TT + 1];
+    __shared__ uint32_t s_lo[TT];
+    __shared__ uint32_t s_q[TT];
+    __shared__ uint32_t s_tw[TT];
+    __shared__ uint32_t s_sd[TT];
+    __shared__ uint32_t s_wsum[TT / 64];
+    __shared__ uint32_t s_next;
+    __shared__ uint32_t s_F;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    uint32_t r = A.round;
+    uint32_t which = which0;
+    if (tid == 0) s_F = A.cnt[CNT_FRONT + r % 3u];
+    __syncthreads();
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+    uint32_t rounds = 0;
+    uint32_t dummy_vol = 0;
+    for (;;) {
+        const uint32_t F = s_F;
+        if (F == 0 || F > limit || rounds >= max_rounds) break;
+        {
+            // out-degree volume of the frontier bounds this round's edge work;
+            // beyond vol_limit the multi-block kernels are faster
+            uint32_t vol = 0;
+            const uint32_t *cq = which ? q1 : q0;
+            for (uint32_t i = tid; i < F; i += TT) {
+                const uint32_t u = cq[i] % A.n;
+                vol += A.off[u + 1] - A.off[u];
+            }
+            for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o);
+            if (lane == 0) s_wsum[w] = vol;
+            __syncthreads();
+            uint32_t tot = 0;
+            for (int w2 = 0; w2 < TT / 64; ++w2) tot += s_wsum[w2];
+            __syncthreads();
+            if (tot > vol_limit) break;
+        }
+        TravArgs B = A;
+        B.cur = which ? q1 : q0;
+        B.next = which ? q0 : q1;
+        B.round = r;
+        B.stamp_val = A.stamp_val + rounds;
+        B.track_volume = 0;
+        if (tid == 0) s_next = 0;
+        __syncthreads();
+        for (uint32_t base = 0; base < F; base += TT) {
+            const uint32_t i = base + tid;
+            uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0;
+            if (i < F) {
+                ++n_items;
+                const uint32_t item = B.cur[i];
+                q = item / A.n;
+                const uint32_t u = item - q * A.n;
+                const uint4 p = A.qp[q];
+                tw = p.z;
+                sd = p.w;
+                const size_t su = (size_t)q * A.n + u;
+                const uint32_t ru = __hip_atomic_load(&A.arr[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t b = A.off[u], e = A.off[u + 1];
+                const uint32_t old = A.done[su];
+                lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), ru);
+                uint32_t end = old;
+                if (old == INF) end = tw > A.max_t ? e : lower_bound_u32(A.tt, lo, e, tw);
+                if (lo < end) {
+                    len = end - lo;
+                    A.done[su] = lo;
+                }
+            }
+            uint32_t x = len;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            if (lane == 63) s_wsum[w] = x;
+            s_lo[tid] = lo;
+            s_q[tid] = q;
+            s_tw[tid] = tw;
+            s_sd[tid] = sd;
+            __syncthreads();
+            uint32_t woff = 0, total = 0;
+            for (int w2 = 0; w2 < TT / 64; ++w2) {
+                if (w2 < w) woff += s_wsum[w2];
+                total += s_wsum[w2];
+            }
+            s_pref[tid] = woff + x - len;
+            if (tid == 0) s_pref[TT] = total;
+            __syncthreads();
+            n_edges += total;
+            for (uint32_t j0 = 0; j0 < total; j0 += TT * UNR) {
+                EdgeGroup G;
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const uint32_t j = j0 + k * TT + tid;
+                    G.ok[k] = j < total;
+                    int lo_k = 0, hi_k = TT;
+                    if (G.ok[k]) {
+                        while (hi_k - lo_k > 1) {
+                            const int mid = (lo_k + hi_k) >> 1;
+                            if (s_pref[mid] <= j)
+                                lo_k = mid;
+                            else
+                                hi_k = mid;
+                        }
+                    }
+                    const uint32_t e = s_lo[lo_k] + (j - s_pref[lo_k]);
+                    const uint2 dv = G.ok[k] ? A.da[e] : make_uint2(0, 0);
+                    G.v[k] = dv.x;
+                    G.a[k] = dv.y;
+                    G.q[k] = s_q[lo_k];
+                    G.tw[k] = s_tw[lo_k];
+                    G.sd[k] = s_sd[lo_k];
+                }
+                relax_group<SWEEP>(B, G, &s_next, &dummy_vol, n_relax);
+            }
+            __syncthreads();
+        }
+        ++r;
+        ++rounds;
+        which ^= 1u;
+        if (tid == 0) {
+            s_F = s_next;
+            A.cnt[CNT_FRONT + r % 3u] = s_next;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A.cnt[CNT_TAIL_ROUND] = r;
+        A.cnt[CNT_TAIL_WHICH] = which;
+        A.cnt[CNT_TAIL_ROUNDS] = rounds;
+        // the multi-block kernels of round r expect these zeroed
+        A.cnt[CNT_CHUNK + r % 3u] = 0u;
+        A.cnt[CNT_FRONT + (r + 1u) % 3u] = 0u;
+        A.cnt[CNT_PULLVOL + (r + 1u) % 3u] = 0u;
+    }
+    stats_flush(A, n_relax, n_items, ST_TAIL_EDGES, tid == 0 ? n_edges : 0);
 }
 
 // Dense pull round: every vertex v of every query looks at its in-edges in
@@ -432,6 +717,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
     A.nq = nq;
     A.track_volume = g->tuning.pull_alpha ? 1u : 0u;
+    A.max_t = g->max_t;
     return A;
 }
 
@@ -463,6 +749,35 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
     const uint64_t total_v = (uint64_t)A.nq * g->n;
     int rc = KAIROS_OK;
     while (F > 0) {
+        if (tu.tail_limit && F <= tu.tail_limit && !pulling) {
+            constexpr uint32_t kMaxTail = 4096;
+            if (s->stamp_next >= 0xFFFFF000u - kMaxTail) {
+                if ((rc = fill(st, s->stamp, (uint64_t)s->qcap * s->n, 0u))) return rc;
+                s->stamp_next = 1;
+            }
+            A.round = r;
+            A.stamp_val = s->stamp_next;
+            hipEvent_t ev;
+            prof_begin(g, st, &ev);
+            hipLaunchKernelGGL(tail_kernel<SWEEP>, dim3(1), dim3(TT), 0, st, A, (uint32_t)which, tu.tail_limit,
+                               tu.tail_limit * 32u, kMaxTail, s->queue[0], s->queue[1]);
+            prof_end(g, st, KAIROS_K_TAIL, ev);
+            KAIROS_HIP(hipGetLastError());
+            KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, CNT_WORDS * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            KAIROS_HIP(hipStreamSynchronize(st));
+            const uint32_t done_rounds = s->h_pin[CNT_TAIL_ROUNDS];
+            r = s->h_pin[CNT_TAIL_ROUND];
+            which = (int)s->h_pin[CNT_TAIL_WHICH];
+            s->stamp_next += done_rounds;
+            F = s->h_pin[CNT_FRONT + r % 3u];
+            if (g->prof.on) {
+                std::lock_guard<std::mutex> lk(g->prof.mu);
+                g->prof.rounds += done_rounds;
+            }
+            if (F == 0) break;
+            if (done_rounds > 0 && F <= tu.tail_limit) continue;  // stopped at max_rounds
+            vol = 0;
+        }
         for (uint32_t k = 0; k < R; ++k) {
             A.round = r;
             A.stamp_val = next_stamp(s, &rc);
@@ -525,7 +840,11 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     s->queue[1] = (uint32_t *)dev_alloc(std::max<size_t>(qn, qcap) * 4, acct);
     const uint64_t per_q = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
                            g->m / std::max<uint32_t>(g->tuning.split, 64) + 1;
-    s->chunk_cap = std::min<uint64_t>((uint64_t)qcap * per_q, 1ull << 31);
+    // bound on one round's chunks; beyond 2^26 entries (1 GiB) the push
+    // kernel walks the excess itself
+    s->chunk_cap = std::min<uint64_t>((uint64_t)qcap * per_q, 1ull << 26);
+    // test hook: a tiny list exercises the overflow walk
+    if (const char *cap = std::getenv("KAIROS_TEST_CHUNK_CAP")) s->chunk_cap = std::strtoull(cap, nullptr, 10);
     s->chunks = (uint4 *)dev_alloc(s->chunk_cap * sizeof(uint4), acct);
     s->qp = (uint4 *)dev_alloc((size_t)qcap * sizeof(uint4), acct);
     s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
@@ -616,6 +935,9 @@ void prof_add_stats(kairos_graph *g, const unsigned long long *h)
     std::lock_guard<std::mutex> lk(g->prof.mu);
     g->prof.edges += h[ST_EDGES];
     g->prof.chunk_edges += h[ST_CHUNK_EDGES];
+    g->prof.attempts += h[ST_ATTEMPTS];
+    g->prof.tail_edges += h[ST_TAIL_EDGES];
+    g->prof.tail_items += h[ST_TAIL_ITEMS];
     g->prof.items += h[ST_ITEMS];
     g->prof.relax += h[ST_RELAX];
     g->prof.pull_edges += h[ST_PULL_EDGES];
@@ -840,13 +1162,15 @@ kairos_tuning default_tuning(const kairos_graph *)
 {
     kairos_tuning t{};
     t.block = 256;
-    t.chunk = 4096;
-    t.split = 4096;
+    t.chunk = 512;
+    t.split = 256;
     t.pull_alpha = 0;
     t.pull_beta = 24;
     t.rounds_per_sync = 1;
     t.batch_persistent = 0;
     t.sweep_group = 1;
+    t.batch_layout = 0;
+    t.tail_limit = 4096;
     return t;
 }
 
@@ -906,6 +1230,7 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.round = ms->round;
     A.cur = ms->queue[0];
     A.next = ms->queue[1];
+    A.max_t = g->max_t;
     return A;
 }
 

@@ -239,3 +239,62 @@ def test_build_rejects_bad_edges():
         assert ei.value.status == 2
     assert (out == 123).all()
     G.free()
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_batch_layouts_ragged_groups(layout):
+    """100 queries = one full and one ragged group of 64 lanes."""
+    g, G, se = rmat16()
+    srcs, ta, tw = make_queries("rmat22-256m", g, count=100)  # log-uniform windows on this graph
+    ta = (ta.astype(np.uint64) * ((1 << 30) - 1) // 0xFFFFFFF4).astype(np.uint32)
+    tw = np.maximum(ta, (tw.astype(np.uint64) * ((1 << 30) - 1) // 0xFFFFFFF4).astype(np.uint32))
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, batch_layout=layout)
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        print_case("batch layout", layout)
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        rows = K.as_u32(out).reshape(len(srcs), g.n)
+        for qi in list(range(0, 100, 7)) + [63, 64, 99]:
+            assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+def test_batch_duplicate_sources():
+    g, G, se = uniform()
+    s = int(make_queries("uniform-10k", g)[0][0])
+    k = 70
+    ta = np.arange(k, dtype=np.uint32) * 1000
+    tw = np.full(k, 99_999, np.uint32)
+    tw[::3] = ta[::3] + 20_000
+    srcs = np.full(k, s, np.uint32)
+    out = torch.empty(k * g.n, dtype=torch.int32, device="cuda")
+    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+    rows = K.as_u32(out).reshape(k, g.n)
+    for qi in range(k):
+        assert np.array_equal(rows[qi], O.earliest_arrival(se, s, ta[qi], tw[qi])), qi
+
+
+def test_chunk_list_overflow_paths():
+    """A chunk list of 3 entries forces the in-kernel fallback walks."""
+    os.environ["KAIROS_TEST_CHUNK_CAP"] = "3"
+    try:
+        g = make_graph("rmat20-32m", scale_shift=6)
+        G = K.kairos_graph_build(*dev(g), g.n)
+        K.kairos_set_tuning(G, split=64, chunk=64)
+        se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+        srcs, ta, tw = make_queries("rmat20-32m", g, count=70)
+        for qi in range(3):
+            assert np.array_equal(ea_gpu(G, int(srcs[qi]), int(ta[qi]), int(tw[qi])),
+                                  O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi]))
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        for layout in (0, 1):
+            K.kairos_set_tuning(G, batch_layout=layout)
+            K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+            rows = K.as_u32(out).reshape(len(srcs), g.n)
+            for qi in (0, 5, 64, 69):
+                assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), (layout, qi)
+        G.free()
+    finally:
+        del os.environ["KAIROS_TEST_CHUNK_CAP"]
