@@ -89,6 +89,7 @@ int kairos_graph_build(const uint32_t *src, const uint32_t *dst, const uint32_t 
     if (m >= (1ull << 32)) return KAIROS_ERR_RANGE;
     kairos_graph *g = new (std::nothrow) kairos_graph();
     if (!g) return KAIROS_ERR_NOMEM;
+    (void)hipGetLastError();
     g->n = n;
     g->m = m;
     g->stream = (hipStream_t)hip_stream;
@@ -155,6 +156,7 @@ static int check_query(const kairos_graph *g, uint32_t src, uint32_t ta, uint32_
 static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
 {
     if (!g || !out) return KAIROS_ERR_INVALID;
+    (void)hipGetLastError();  // errors of unrelated earlier calls on this thread are not ours
     int rc = check_query(g, src, ta, tw);
     if (rc) return rc;
     Slot *s = nullptr;
@@ -191,6 +193,7 @@ int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *s
     if (!g) return KAIROS_ERR_INVALID;
     if (q == 0) return KAIROS_OK;
     if (!src || !t_alpha || !t_omega || !out) return KAIROS_ERR_INVALID;
+    (void)hipGetLastError();
     for (uint32_t i = 0; i < q; ++i) {
         int rc = check_query(g, src[i], t_alpha[i], t_omega[i]);
         if (rc) return rc;
@@ -239,6 +242,7 @@ int kairos_traversed_edges(kairos_graph *g, uint32_t t_alpha, uint32_t t_omega, 
 {
     if (!g || !ea || !count) return KAIROS_ERR_INVALID;
     if (t_alpha > t_omega || t_omega > KAIROS_TMAX) return KAIROS_ERR_RANGE;
+    (void)hipGetLastError();
     return count_traversed(g, t_alpha, t_omega, ea, count);
 }
 

@@ -1,0 +1,137 @@
+"""Continuous-batching server: results equal the same query run alone and the
+CPU oracle (bit for bit), admission waits for device memory, the waiting
+queue is bounded, slots are reused without stale state."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+import paper_2401_02563_amd as K  # noqa: E402
+from workloads import make_graph, query_kinds  # noqa: E402
+from workloads.gen import log_uniform_windows, sample_sources  # noqa: E402
+
+_G = {}
+
+
+def graph(name, shift):
+    key = (name, shift)
+    if key not in _G:
+        g = make_graph(name, scale_shift=shift)
+        G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+        se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+        _G[key] = (g, G, se)
+    return _G[key]
+
+
+def mixed_queries(g, count, seed, t_lo, t_hi):
+    src = sample_sources(g, count, seed)
+    ta, tw = log_uniform_windows(count, t_lo, t_hi, seed + 1, f_lo_exp=-1.5)
+    kinds = query_kinds(count, seed + 2)
+    return src, ta, tw, kinds
+
+
+def drain(srv, want, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < want:
+        for c in K.kairos_server_poll(srv, 512):
+            got[c["ticket"]] = c
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"only {len(got)} of {want} completions")
+        time.sleep(0.0005)
+    return got
+
+
+def expected(se, kind, s, a, w):
+    ea, ld, fa = O.profile(se, s, a, w)
+    return (ea, ld, fa)[kind]
+
+
+@pytest.mark.parametrize("name,shift,t_lo,t_hi", [("uniform-10k", 0, 0, 99_999),
+                                                   ("rmat20-32m", 6, 0, (1 << 30) - 1)])
+def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi):
+    g, G, se = graph(name, shift)
+    count = 120
+    src, ta, tw, kinds = mixed_queries(g, count, 7, t_lo, t_hi)
+    outs = torch.full((count, g.n), 7, dtype=torch.int32, device="cuda")
+    srv = K.kairos_server_create(G, max_slots=8, queue_capacity=4096)
+    tickets = {}
+
+    def producer():
+        # arrivals in bursts while earlier queries are on the device
+        for i in range(count):
+            tickets[K.kairos_server_submit(srv, int(kinds[i]), int(src[i]), int(ta[i]), int(tw[i]), outs[i])] = i
+            if i % 10 == 9:
+                time.sleep(0.002)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    done = drain(srv, count)
+    st = K.kairos_server_stats_read(srv)
+    K.kairos_server_free(srv)
+    assert st["completed"] == count and st["max_slots_seen"] >= 2, st
+    alone = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
+    for tk, c in done.items():
+        i = tickets[tk]
+        assert c["status"] == 0 and c["kind"] == kinds[i]
+        assert c["t_done_ns"] >= c["t_submit_ns"]
+        mixed = K.as_u32(outs[i])
+        fns[kinds[i]](G, int(src[i]), int(ta[i]), int(tw[i]), alone)
+        assert np.array_equal(mixed, K.as_u32(alone)), (i, kinds[i])
+        assert np.array_equal(mixed, expected(se, int(kinds[i]), src[i], ta[i], tw[i])), (i, kinds[i])
+
+
+def test_admission_waits_for_memory_and_queue_is_bounded():
+    g, G, se = graph("uniform-10k", 0)
+    srv = K.kairos_server_create(G, max_slots=4, queue_capacity=3)
+    K.kairos_server_set_free_bytes_override(srv, 0)
+    outs = torch.empty((4, g.n), dtype=torch.int32, device="cuda")
+    src = sample_sources(g, 4, 3)
+    for i in range(3):
+        K.kairos_server_submit(srv, 0, int(src[i]), 0, 99_999, outs[i])
+    with pytest.raises(K.KairosError) as ei:
+        K.kairos_server_submit(srv, 0, int(src[3]), 0, 99_999, outs[3])
+    assert ei.value.status == 5  # queue full
+    time.sleep(0.05)
+    assert K.kairos_server_poll(srv) == []
+    st = K.kairos_server_stats_read(srv)
+    assert st["admitted_waits_mem"] > 0 and st["completed"] == 0
+    K.kairos_server_set_free_bytes_override(srv, (1 << 64) - 1)  # real device memory again
+    done = drain(srv, 3)
+    assert all(c["status"] == 0 for c in done.values())
+    for i in range(3):
+        assert np.array_equal(K.as_u32(outs[i]), O.earliest_arrival(se, src[i], 0, 99_999))
+    with pytest.raises(K.KairosError) as ei:
+        K.kairos_server_submit(srv, 0, g.n, 0, 5, outs[0])
+    assert ei.value.status == 2
+    K.kairos_server_free(srv)
+
+
+def test_slot_reuse_has_no_stale_state():
+    """One slot, queries alternating between wide and narrow windows: each
+    result must match its own oracle, so nothing leaks from the previous
+    occupant of the slot."""
+    g, G, se = graph("uniform-10k", 0)
+    srv = K.kairos_server_create(G, max_slots=1, queue_capacity=64)
+    k = 12
+    src = sample_sources(g, k, 11)
+    ta = np.array([0 if i % 2 == 0 else 60_000 for i in range(k)], np.uint32)
+    tw = np.array([99_999 if i % 2 == 0 else 61_000 for i in range(k)], np.uint32)
+    kinds = np.array([i % 3 for i in range(k)])
+    outs = torch.empty((k, g.n), dtype=torch.int32, device="cuda")
+    tickets = {K.kairos_server_submit(srv, int(kinds[i]), int(src[i]), int(ta[i]), int(tw[i]), outs[i]): i
+               for i in range(k)}
+    drain(srv, k)
+    K.kairos_server_free(srv)
+    for i in tickets.values():
+        assert np.array_equal(K.as_u32(outs[i]), expected(se, int(kinds[i]), src[i], ta[i], tw[i])), i
