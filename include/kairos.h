@@ -142,9 +142,12 @@ typedef struct kairos_tuning {
     uint32_t batch_persistent; /* 1: batched queries run in one persistent launch  */
     uint32_t sweep_group;    /* departure times handled together by the
                                 latest-departure / fastest sweep                     */
-    uint32_t batch_layout;   /* 0: one wavefront lane per query, arrivals stored
-                                vertex-major (edges read once per 64 queries);
-                                1: one thread per query and vertex             */
+    uint32_t batch_layout;   /* 0: one wavefront per frontier vertex, one lane per
+                                query, arrivals stored vertex-major (edges read
+                                once per 64 queries); 1: one thread per query
+                                and vertex, arrivals query-major; 2: vertex-major
+                                arrivals, (vertex, query) pairs dealt densely to
+                                threads                                         */
     uint32_t tail_limit;     /* frontiers of at most this many entries run in one
                                 workgroup that loops over rounds without host
                                 round trips; 0 disables                          */

@@ -198,7 +198,7 @@ int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *s
         int rc = check_query(g, src[i], t_alpha[i], t_omega[i]);
         if (rc) return rc;
     }
-    if (g->tuning.batch_layout == 0) {
+    if (g->tuning.batch_layout != 1) {
         // groups of 64 queries; groups*n must fit the 32-bit frontier items
         const uint64_t max_groups = std::max<uint64_t>(1, 0xFFFFFFFEull / g->n);
         const uint64_t per_q = std::min<uint64_t>((uint64_t)q, max_groups * 64);
@@ -258,10 +258,11 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 64 || in->split < 64 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
-        in->batch_layout > 1)
+        in->batch_layout > 2)
         return KAIROS_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g->pool_mu);
-    const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split;
+    const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split ||
+                        in->batch_layout != g->tuning.batch_layout;
     g->tuning = *in;
     if (resize) {
         // chunk lists are sized from these values: drop cached scratch

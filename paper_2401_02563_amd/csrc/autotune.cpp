@@ -89,7 +89,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         {&kairos_tuning::rounds_per_sync, {1, 2, 4, 8}},
         {&kairos_tuning::pull_alpha, {0, 4, 14, 32}},
         {&kairos_tuning::pull_beta, {8, 24, 64}},
-        {&kairos_tuning::batch_layout, {0, 1}},
+        {&kairos_tuning::batch_layout, {0, 1, 2}},
         {&kairos_tuning::tail_limit, {0, 1024, 4096, 16384}},
     };
     for (const Axis &ax : axes) {

@@ -276,6 +276,297 @@ __global__ __launch_bounds__(BTB) void bchunk_kernel(BArgs A)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lane-dense variant of the same batch (batch_layout 2).  The frontier and
+// the arrival rows are those of the vertex-major kernel, but an entry's mask
+// is expanded into (vertex, query) pairs that are dealt to threads densely,
+// so a pair with one active query costs one thread, not a wavefront.  Each
+// thread claims its pair's range as the single-query kernel does; claims
+// shorter than `split` are relaxed by the block through a prefix sum over
+// claim lengths, longer ones go to the chunk kernel below.  Pairs of one
+// vertex sit in neighbouring threads, so their edge records and arrival rows
+// are fetched together.
+constexpr int HU = 4;  // edges in flight per lane
+
+struct HGroup {
+    uint32_t v[HU], a[HU], row[HU], bit[HU], tw[HU];
+    bool ok[HU];
+};
+
+__device__ __forceinline__ uint32_t nth_set_bit(unsigned long long m, uint32_t j)
+{
+    for (uint32_t i = 0; i < j; ++i) m &= m - 1ull;
+    return (uint32_t)__builtin_ctzll(m);
+}
+
+// Relax HU edges per lane: arrival-row reads, atomic minima and head-mask ORs
+// are each issued together; heads whose mask was empty are enqueued with one
+// atomicAdd per wavefront.
+__device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, uint32_t *next_cnt, unsigned long long &n_relax)
+{
+    uint32_t cur[HU];
+    size_t idx[HU];
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+        H.ok[k] = H.ok[k] && H.a[k] <= H.tw[k];
+        idx[k] = ((size_t)H.row[k] + H.v[k]) * 64 + H.bit[k];
+        cur[k] = H.ok[k] ? A.arr[idx[k]] : 0u;
+    }
+    uint32_t old[HU];
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+        H.ok[k] = H.ok[k] && H.a[k] < cur[k];
+        old[k] = H.ok[k] ? atomicMin(&A.arr[idx[k]], H.a[k]) : 0u;
+    }
+    unsigned long long om[HU];
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+        H.ok[k] = H.ok[k] && H.a[k] < old[k];
+        n_relax += H.ok[k] ? 1ull : 0ull;
+        om[k] = H.ok[k] ? atomicOr(&A.mask_next[(size_t)H.row[k] + H.v[k]], 1ull << H.bit[k]) : 1ull;
+    }
+    unsigned long long bal[HU];
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+        bal[k] = __ballot(om[k] == 0ull);
+        total += __popcll(bal[k]);
+    }
+    if (total == 0) return;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(next_cnt, total);
+    base = __shfl(base, 0);
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int k = 0; k < HU; ++k) {
+        if ((bal[k] >> lane) & 1ull) A.next[base + __popcll(bal[k] & lt)] = H.row[k] + H.v[k];
+        base += __popcll(bal[k]);
+    }
+}
+
+__global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
+{
+    __shared__ uint32_t s_ent[BTB];
+    __shared__ unsigned long long s_mask[BTB];
+    __shared__ uint32_t s_pp[BTB + 1];
+    __shared__ uint32_t s_lo[BTB], s_row[BTB], s_bit[BTB], s_tw[BTB];
+    __shared__ uint32_t s_pref[BTB + 1];
+    __shared__ uint32_t s_wsum[BTB / 64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t F = A.cnt[CNT_FRONT + r3];
+    if (blockIdx.x == 0 && tid == 0) {
+        A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
+        A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
+    }
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+
+    for (uint32_t base = blockIdx.x * BTB; base < F; base += gridDim.x * BTB) {
+        // entries of this block and their query counts
+        const uint32_t i = base + tid;
+        uint32_t ent = 0, c = 0;
+        unsigned long long M = 0;
+        if (i < F) {
+            ent = A.cur[i];
+            M = A.mask_cur[ent];
+            A.mask_cur[ent] = 0ull;  // one expander per entry per round; reused next round
+            c = __popcll(M);
+        }
+        uint32_t x = c;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_wsum[w] = x;
+        s_ent[tid] = ent;
+        s_mask[tid] = M;
+        __syncthreads();
+        uint32_t woff = 0, P = 0;
+        for (int w2 = 0; w2 < BTB / 64; ++w2) {
+            if (w2 < w) woff += s_wsum[w2];
+            P += s_wsum[w2];
+        }
+        s_pp[tid] = woff + x - c;
+        if (tid == 0) s_pp[BTB] = P;
+        __syncthreads();
+        for (uint32_t p0 = 0; p0 < P; p0 += BTB) {
+            // one (vertex, query) pair per thread: claim its newly usable range
+            const uint32_t p = p0 + tid;
+            uint32_t lo = 0, len = 0, row = 0, bit = 0, tw = 0, ser_lo = 0, ser_len = 0;
+            if (p < P) {
+                int lk = 0, hk = BTB;
+                while (hk - lk > 1) {
+                    const int mid = (lk + hk) >> 1;
+                    if (s_pp[mid] <= p)
+                        lk = mid;
+                    else
+                        hk = mid;
+                }
+                const uint32_t e_ = s_ent[lk];
+                bit = nth_set_bit(s_mask[lk], p - s_pp[lk]);
+                const uint32_t g = e_ / A.n;
+                const uint32_t u = e_ - g * A.n;
+                row = g * A.n;
+                tw = A.qw[(size_t)g * 64 + bit].y;
+                const size_t slot = (size_t)e_ * 64 + bit;
+                const uint32_t r = A.arr[slot];
+                const uint32_t b = A.off[u], e = A.off[u + 1];
+                const uint32_t old = A.done[slot];
+                lo = lb_u32(A.tt, b, old == INF ? e : min(old, e), r);
+                uint32_t end = old == INF ? (tw > A.max_t ? e : lb_u32(A.tt, lo, e, tw)) : old;
+                ++n_items;
+                if (lo < end) {
+                    len = end - lo;
+                    A.done[slot] = lo;
+                }
+                if (len >= A.split) {
+                    const uint32_t nch = (len + A.chunk - 1) / A.chunk;
+                    const uint32_t cb = atomicAdd(chunk_cnt, nch);
+                    const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
+                    for (uint32_t k = 0; k < fit; ++k)
+                        A.chunks[cb + k] = make_uint4(e_, bit, lo + k * A.chunk, min(A.chunk, len - k * A.chunk));
+                    const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
+                    lo += covered;
+                    len -= covered;
+                    if (len >= A.split) {
+                        // chunk list full: this lane walks the rest by itself
+                        ser_lo = lo;
+                        ser_len = len;
+                        len = 0;
+                    }
+                }
+            }
+            // prefix over claim lengths, each below `split`
+            uint32_t y2 = len;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t2 = __shfl_up(y2, o);
+                if (lane >= o) y2 += t2;
+            }
+            __syncthreads();
+            if (lane == 63) s_wsum[w] = y2;
+            s_lo[tid] = lo;
+            s_row[tid] = row;
+            s_bit[tid] = bit;
+            s_tw[tid] = tw;
+            __syncthreads();
+            uint32_t wo = 0, total = 0;
+            for (int w2 = 0; w2 < BTB / 64; ++w2) {
+                if (w2 < w) wo += s_wsum[w2];
+                total += s_wsum[w2];
+            }
+            s_pref[tid] = wo + y2 - len;
+            if (tid == 0) s_pref[BTB] = total;
+            __syncthreads();
+            n_edges += total;
+            for (uint32_t j0 = 0; j0 < total; j0 += BTB * HU) {
+                HGroup H;
+#pragma unroll
+                for (int k = 0; k < HU; ++k) {
+                    const uint32_t j = j0 + k * BTB + tid;
+                    H.ok[k] = j < total;
+                    int lk = 0, hk = BTB;
+                    if (H.ok[k]) {
+                        while (hk - lk > 1) {
+                            const int mid = (lk + hk) >> 1;
+                            if (s_pref[mid] <= j)
+                                lk = mid;
+                            else
+                                hk = mid;
+                        }
+                    }
+                    const uint2 dv = H.ok[k] ? A.da[s_lo[lk] + (j - s_pref[lk])] : make_uint2(0u, 0u);
+                    H.v[k] = dv.x;
+                    H.a[k] = dv.y;
+                    H.row[k] = s_row[lk];
+                    H.bit[k] = s_bit[lk];
+                    H.tw[k] = s_tw[lk];
+                }
+                hrelax(A, H, next_cnt, n_relax);
+            }
+            uint32_t ser_done = 0;
+            while (__ballot(ser_done < ser_len)) {
+                HGroup H;
+#pragma unroll
+                for (int k = 0; k < HU; ++k) {
+                    H.ok[k] = ser_done < ser_len;
+                    const uint2 dv = H.ok[k] ? A.da[ser_lo + ser_done] : make_uint2(0u, 0u);
+                    if (H.ok[k]) ++ser_done;
+                    H.v[k] = dv.x;
+                    H.a[k] = dv.y;
+                    H.row[k] = row;
+                    H.bit[k] = bit;
+                    H.tw[k] = tw;
+                }
+                hrelax(A, H, next_cnt, n_relax);
+            }
+            if (ser_len && A.stats) atomicAdd(&A.stats[ST_EDGES], (unsigned long long)ser_len);
+            __syncthreads();
+        }
+    }
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) {
+            n_relax += __shfl_xor(n_relax, o);
+            n_items += __shfl_xor(n_items, o);
+        }
+        if (lane == 0) {
+            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
+        }
+        if (tid == 0 && n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
+    }
+}
+
+// Chunks of the lane-dense variant: {entry, query bit, start, len}; one
+// wavefront per chunk, HU edges per lane in flight, every lane active.
+__global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
+{
+    const uint32_t r3 = A.round % 3u;
+    const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
+    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    unsigned long long n_edges = 0, n_relax = 0;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (BTB / 64);
+    for (uint32_t c = blockIdx.x * (BTB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
+        const uint4 ch = A.chunks[c];
+        const uint32_t g = ch.x / A.n;
+        const uint32_t tw = A.qw[(size_t)g * 64 + ch.y].y;
+        n_edges += ch.w;
+        for (uint32_t k0 = 0; k0 < ch.w; k0 += 64 * HU) {
+            HGroup H;
+#pragma unroll
+            for (int k = 0; k < HU; ++k) {
+                const uint32_t off = k0 + k * 64 + lane;
+                H.ok[k] = off < ch.w;
+                const uint2 dv = H.ok[k] ? A.da[ch.z + off] : make_uint2(0u, 0u);
+                H.v[k] = dv.x;
+                H.a[k] = dv.y;
+                H.row[k] = g * A.n;
+                H.bit[k] = ch.y;
+                H.tw[k] = tw;
+            }
+            hrelax(A, H, next_cnt, n_relax);
+        }
+    }
+    __shared__ unsigned long long s_e[BTB / 64];
+    if (lane == 0) s_e[threadIdx.x >> 6] = n_edges;
+    __syncthreads();
+    if (A.stats) {
+        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
+        if (lane == 0 && n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
+        if (threadIdx.x == 0) {
+            unsigned long long blk = 0;
+            for (int w2 = 0; w2 < BTB / 64; ++w2) blk += s_e[w2];
+            if (blk) atomicAdd(&A.stats[ST_CHUNK_EDGES], blk);
+        }
+    }
+}
+
 // Group start: every query's source gets its t_alpha and its mask bit; the
 // lane that finds the source's mask empty enqueues it.
 __global__ void binit_kernel(BArgs A, const uint4 *__restrict__ hq, uint32_t q)
@@ -383,8 +674,10 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
     b->mask[0] = (unsigned long long *)dev_alloc(gn * 8, nullptr);
     b->mask[1] = (unsigned long long *)dev_alloc(gn * 8, nullptr);
     b->qw = (uint2 *)dev_alloc((size_t)groups * 64 * sizeof(uint2), nullptr);
-    const uint64_t per_g = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
-                           g->m / std::max<uint32_t>(g->tuning.split, 64) + 1;
+    // chunks of one round: the lane-dense layout can split per query
+    const uint64_t per_g = (g->tuning.batch_layout == 2 ? 64 : 1) *
+                           (g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
+                            g->m / std::max<uint32_t>(g->tuning.split, 64) + 1);
     b->chunk_cap = std::min<uint64_t>((uint64_t)groups * per_g, 1ull << 26);
     b->range_cap = std::min<uint64_t>((uint64_t)groups * (g->m / std::max<uint32_t>(g->tuning.split, 64) + 1),
                                       1ull << 22);
@@ -487,6 +780,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     KAIROS_HIP(hipStreamSynchronize(st));
     uint32_t F = b->h_pin[CNT_FRONT];
     const int wave_cap = std::max(1, g->num_cus * 8);
+    const bool dense = g->tuning.batch_layout == 2;
     uint32_t r = 0;
     while (F > 0) {
         A.round = r;
@@ -495,10 +789,16 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
         A.mask_cur = b->mask[r & 1];
         A.mask_next = b->mask[(r + 1) & 1];
         prof_begin(g, st, &ev);
-        hipLaunchKernelGGL(bpush_kernel, dim3(gridc(F, BTB / 64, wave_cap)), dim3(BTB), 0, st, A);
+        if (dense)
+            hipLaunchKernelGGL(hpush_kernel, dim3(gridc(F, BTB, wave_cap / 4)), dim3(BTB), 0, st, A);
+        else
+            hipLaunchKernelGGL(bpush_kernel, dim3(gridc(F, BTB / 64, wave_cap)), dim3(BTB), 0, st, A);
         prof_end(g, st, KAIROS_K_PUSH, ev);
         prof_begin(g, st, &ev);
-        hipLaunchKernelGGL(bchunk_kernel, dim3(std::max(1, g->num_cus * 8)), dim3(BTB), 0, st, A);
+        if (dense)
+            hipLaunchKernelGGL(hchunk_kernel, dim3(std::max(1, g->num_cus * 8)), dim3(BTB), 0, st, A);
+        else
+            hipLaunchKernelGGL(bchunk_kernel, dim3(std::max(1, g->num_cus * 8)), dim3(BTB), 0, st, A);
         prof_end(g, st, KAIROS_K_CHUNK, ev);
         KAIROS_HIP(hipGetLastError());
         ++r;

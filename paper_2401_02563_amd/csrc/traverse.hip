@@ -1162,14 +1162,14 @@ kairos_tuning default_tuning(const kairos_graph *)
 {
     kairos_tuning t{};
     t.block = 256;
-    t.chunk = 512;
-    t.split = 256;
+    t.chunk = 256;
+    t.split = 128;
     t.pull_alpha = 0;
     t.pull_beta = 24;
     t.rounds_per_sync = 1;
     t.batch_persistent = 0;
     t.sweep_group = 1;
-    t.batch_layout = 0;
+    t.batch_layout = 2;
     t.tail_limit = 4096;
     return t;
 }

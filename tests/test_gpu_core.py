@@ -241,7 +241,7 @@ def test_build_rejects_bad_edges():
     G.free()
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 def test_batch_layouts_ragged_groups(layout):
     """100 queries = one full and one ragged group of 64 lanes."""
     g, G, se = rmat16()
@@ -289,7 +289,7 @@ def test_chunk_list_overflow_paths():
             assert np.array_equal(ea_gpu(G, int(srcs[qi]), int(ta[qi]), int(tw[qi])),
                                   O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi]))
         out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
-        for layout in (0, 1):
+        for layout in (0, 1, 2):
             K.kairos_set_tuning(G, batch_layout=layout)
             K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
             rows = K.as_u32(out).reshape(len(srcs), g.n)

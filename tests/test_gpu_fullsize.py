@@ -1,0 +1,103 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+The scale-20 R-MAT workload (2^25 edges) is checked in full: every row of
+the 64-query batch the benchmark times, single queries, latest departure /
+fastest samples and traversed-edge counts, all bit-exact against the oracle.
+The larger workloads (about 10^9 bursty edges, 2^28 and 2^29 R-MAT edges) are
+checked on sampled queries (oracle scan, EA certificate) when
+KAIROS_FULL_SIZE=1, since generating them takes minutes of host time."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+import paper_2401_02563_amd as K  # noqa: E402
+from workloads import make_graph, make_queries  # noqa: E402
+
+FULL = os.environ.get("KAIROS_FULL_SIZE") == "1"
+_C = {}
+
+
+def load(name):
+    if name not in _C:
+        print(f"case: generating {name}", flush=True)
+        g = make_graph(name)
+        G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+        print(f"case: index built for {name} (m={g.m})", flush=True)
+        se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+        _C.clear()  # keep one large workload in memory at a time
+        _C[name] = (g, G, se)
+    return _C[name]
+
+
+def test_rmat20_batch_all_rows_bit_exact():
+    g, G, se = load("rmat20-32m")
+    srcs, ta, tw = make_queries("rmat20-32m", g)
+    out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+    rows = K.as_u32(out).reshape(len(srcs), g.n)
+    for q in range(len(srcs)):
+        want = O.earliest_arrival(se, srcs[q], ta[q], tw[q])
+        assert np.array_equal(rows[q], want), q
+        if q % 16 == 0:
+            ec = K.kairos_traversed_edges(G, int(ta[q]), int(tw[q]), out[q * g.n:(q + 1) * g.n])
+            assert ec == O.traversed_edges(se, ta[q], tw[q], want)
+
+
+def test_rmat20_single_and_sweeps():
+    g, G, se = load("rmat20-32m")
+    srcs, ta, tw = make_queries("rmat20-32m", g)
+    one = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for q in range(0, 64, 8):
+        print("case: single", q, flush=True)
+        K.kairos_earliest_arrival(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        assert np.array_equal(K.as_u32(one), O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+    for q in (1, 2):
+        print("case: sweep", q, flush=True)
+        pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
+        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        assert np.array_equal(K.as_u32(one), pld), q
+        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        assert np.array_equal(K.as_u32(one), pf), q
+
+
+@pytest.mark.skipif(not FULL, reason="set KAIROS_FULL_SIZE=1 (minutes of host time)")
+@pytest.mark.parametrize("name,kind", [("rmat22-256m", "batch"), ("rmat24-512m", "single"),
+                                       ("bursty22-1b", "single")])
+def test_large_sampled(name, kind):
+    g, G, se = load(name)
+    srcs, ta, tw = make_queries(name, g)
+    sample = [0, 1, len(srcs) // 2, len(srcs) - 1]
+    if kind == "batch":
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        print(f"case: {name} batch of {len(srcs)}", flush=True)
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        rows = out.view(len(srcs), g.n)
+        got = {q: K.as_u32(rows[q]) for q in sample}
+    else:
+        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        got = {}
+        for q in sample:
+            K.kairos_earliest_arrival(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+            got[q] = K.as_u32(one)
+    for q in sample:
+        print(f"case: {name} query {q}", flush=True)
+        assert np.array_equal(got[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+    q = sample[0]
+    assert O.ea_certificate(g.n, g.src, g.dst, g.t, g.lam, int(srcs[q]), int(ta[q]), int(tw[q]), got[q])
+    if name == "bursty22-1b":
+        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        q = 1
+        print("case: bursty sweeps", flush=True)
+        pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
+        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        assert np.array_equal(K.as_u32(one), pld)
+        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        assert np.array_equal(K.as_u32(one), pf)
