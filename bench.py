@@ -226,7 +226,7 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     res["batch_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt}
-    k = min(8, q)
+    k = min(4, q)
     for kind, fn in (("latest_departure", K.kairos_latest_departure), ("fastest", K.kairos_fastest)):
         t = time.perf_counter()
         for i in range(k):

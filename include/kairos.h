@@ -84,7 +84,11 @@ void kairos_graph_free(kairos_graph *g);
 /* n, m and the device bytes held by the index (any pointer may be NULL). */
 int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t *device_bytes);
 
-/* Device pointers of the index, for inspection (read only, owned by g):
+/* Device pointers of the index, for inspection (read only, owned by g).
+ * The index numbers vertices internally in order of decreasing in-degree
+ * (ties by caller id), so that the arrival words of the most-targeted
+ * vertices share cache lines; perm[v] is the internal id of caller vertex v.
+ * All calls take and return caller ids.  In internal ids:
  *   off_out[n+1]  first out-edge of each tail;  out-edge e has
  *   t_out[e], and dst_a_out[2e], dst_a_out[2e+1] = head, arrival;
  *   off_in[n+1]   first in-edge of each head;   in-edge e has
@@ -92,6 +96,7 @@ int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t
 typedef struct kairos_index_view {
     const uint32_t *off_out, *t_out, *dst_a_out;
     const uint32_t *off_in, *a_in, *src_t_in;
+    const uint32_t *perm;
 } kairos_index_view;
 int kairos_graph_index(const kairos_graph *g, kairos_index_view *view);
 
@@ -151,6 +156,9 @@ typedef struct kairos_tuning {
     uint32_t tail_limit;     /* frontiers of at most this many entries run in one
                                 workgroup that loops over rounds without host
                                 round trips; 0 disables                          */
+    uint32_t dense_frontier; /* single queries: a frontier of at least
+                                n / dense_frontier vertices is expanded by
+                                walking all vertices in id order; 0 disables     */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);

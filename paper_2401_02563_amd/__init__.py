@@ -41,7 +41,7 @@ _u32, _u64, _i32, _p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_
 class kairos_tuning(ctypes.Structure):
     _fields_ = [(k, _u32) for k in ("block", "chunk", "split", "pull_alpha", "pull_beta",
                                     "rounds_per_sync", "batch_persistent", "sweep_group", "batch_layout",
-                                    "tail_limit")]
+                                    "tail_limit", "dense_frontier")]
 
 
 class kairos_profile(ctypes.Structure):
@@ -52,7 +52,7 @@ class kairos_profile(ctypes.Structure):
 
 
 class kairos_index_view(ctypes.Structure):
-    _fields_ = [(k, _p) for k in ("off_out", "t_out", "dst_a_out", "off_in", "a_in", "src_t_in")]
+    _fields_ = [(k, _p) for k in ("off_out", "t_out", "dst_a_out", "off_in", "a_in", "src_t_in", "perm")]
 
 
 class kairos_server_opts(ctypes.Structure):
@@ -202,7 +202,8 @@ def kairos_graph_index(g: Graph) -> dict:
     n, m = g.n, g.m
     return dict(off_out=_copy_from_device(v.off_out, n + 1), t_out=_copy_from_device(v.t_out, m),
                 dst_a_out=_copy_from_device(v.dst_a_out, 2 * m), off_in=_copy_from_device(v.off_in, n + 1),
-                a_in=_copy_from_device(v.a_in, m), src_t_in=_copy_from_device(v.src_t_in, 2 * m))
+                a_in=_copy_from_device(v.a_in, m), src_t_in=_copy_from_device(v.src_t_in, 2 * m),
+                perm=_copy_from_device(v.perm, n))
 
 
 def _single(name, g, src, ta, tw, out):

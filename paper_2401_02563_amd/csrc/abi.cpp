@@ -78,6 +78,8 @@ static void graph_release(kairos_graph *g)
     dev_free(g->off_in);
     dev_free(g->a_in);
     dev_free(g->st_in);
+    dev_free(g->perm);
+    dev_free(g->inv);
     delete g;
 }
 
@@ -144,6 +146,7 @@ int kairos_graph_index(const kairos_graph *g, kairos_index_view *view)
     view->off_in = g->off_in;
     view->a_in = g->a_in;
     view->src_t_in = (const uint32_t *)g->st_in;
+    view->perm = g->perm;
     return KAIROS_OK;
 }
 
@@ -256,7 +259,7 @@ int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out)
 int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
 {
     if (!g || !in) return KAIROS_ERR_INVALID;
-    if ((in->block != 256 && in->block != 512) || in->chunk < 64 || in->split < 64 ||
+    if ((in->block != 256 && in->block != 512) || in->chunk < 16 || in->split < 16 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
         in->batch_layout > 2)
         return KAIROS_ERR_INVALID;

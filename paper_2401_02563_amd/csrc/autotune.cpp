@@ -8,8 +8,8 @@
 //
 // Search: coordinate descent from the current setting, one parameter at a
 // time over its candidate values, keeping a change only when the measured
-// time (median of three runs of the whole sample: each query alone, then the
-// sample as one batch) drops.
+// time (median of three runs of the sample: one query alone, or the sample as
+// one batch) drops by more than 2%.
 #include "internal.h"
 
 #include <algorithm>
@@ -28,12 +28,13 @@ double seconds_now()
 int run_sample(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *ta, const uint32_t *tw,
                uint32_t *d_single, uint32_t *d_batch, double *secs)
 {
+    // a sample of one query tunes the single-query path, a larger sample the
+    // batched path it will be answered with
     const double t0 = seconds_now();
-    for (uint32_t i = 0; i < q; ++i) {
-        int rc = kairos_earliest_arrival(g, src[i], ta[i], tw[i], d_single);
+    if (q == 1) {
+        int rc = kairos_earliest_arrival(g, src[0], ta[0], tw[0], d_single);
         if (rc) return rc;
-    }
-    if (q > 1) {
+    } else {
         int rc = kairos_earliest_arrival_batch(g, q, src, ta, tw, d_batch);
         if (rc) return rc;
     }
@@ -84,13 +85,14 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         std::vector<uint32_t> values;
     };
     const std::vector<Axis> axes = {
-        {&kairos_tuning::chunk, {1024, 2048, 4096, 8192, 16384}},
-        {&kairos_tuning::split, {1024, 4096, 16384, 65536}},
-        {&kairos_tuning::rounds_per_sync, {1, 2, 4, 8}},
-        {&kairos_tuning::pull_alpha, {0, 4, 14, 32}},
-        {&kairos_tuning::pull_beta, {8, 24, 64}},
         {&kairos_tuning::batch_layout, {0, 1, 2}},
+        {&kairos_tuning::split, {64, 128, 256, 1024}},
+        {&kairos_tuning::chunk, {128, 256, 512, 2048}},
         {&kairos_tuning::tail_limit, {0, 1024, 4096, 16384}},
+        {&kairos_tuning::dense_frontier, {0, 4, 16, 64}},
+        {&kairos_tuning::rounds_per_sync, {1, 2, 4}},
+        {&kairos_tuning::pull_alpha, {0, 4, 14}},
+        {&kairos_tuning::pull_beta, {8, 24, 64}},
     };
     for (const Axis &ax : axes) {
         if (rc) break;

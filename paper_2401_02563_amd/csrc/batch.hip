@@ -23,6 +23,7 @@
 // other, §6.1).
 
 #include "internal.h"
+#include "stage.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -86,37 +87,20 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t x)
     return x;
 }
 
-// Per-wavefront staging of enqueued heads in LDS, flushed 64 at a time with
-// one global atomicAdd.  `wn` is wave-uniform.
-struct WaveQueue {
-    uint32_t *buf;
-    uint32_t wn;
-};
-
-__device__ __forceinline__ void wq_flush(const BArgs &A, WaveQueue &Q, uint32_t *next_cnt)
-{
-    if (Q.wn == 0) return;
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(next_cnt, Q.wn);
-    base = __shfl(base, 0);
-    __builtin_amdgcn_wave_barrier();
-    if (lane < Q.wn) A.next[base + lane] = Q.buf[lane];
-    __builtin_amdgcn_wave_barrier();
-    Q.wn = 0;
-}
+constexpr int SCAP = 512;  // staged frontier entries per wavefront
+using BStage = Stage<SCAP>;
 
 // Relax edges [c0, c0 + cnt) of group g for every lane whose claimed range
 // [lo, end) holds them.  All loads of BU edges are issued before use.
 __device__ __forceinline__ void relax_span(const BArgs &A, uint32_t g, uint32_t c0, uint32_t total_end,
-                                           bool has, uint32_t lo, uint32_t end, uint32_t tw, WaveQueue &Q,
-                                           uint32_t *next_cnt, unsigned long long &n_relax)
+                                           bool has, uint32_t lo, uint32_t end, uint32_t tw, BStage &S,
+                                           unsigned long long &n_relax)
 {
     const uint32_t lane = threadIdx.x & 63;
     const size_t gbase = (size_t)g * A.n;
     for (uint32_t b0 = c0; b0 < total_end; b0 += 64) {
         const uint32_t e_l = b0 + lane;
-        const uint2 dv = e_l < total_end ? A.da[e_l] : make_uint2(0u, INF);
+        const uint2 dv = A.da[e_l < total_end ? e_l : b0];
         const uint32_t cnt = min(64u, total_end - b0);
         for (uint32_t k0 = 0; k0 < cnt; k0 += BU) {
             uint32_t vk[BU], ak[BU], cur[BU];
@@ -128,14 +112,14 @@ __device__ __forceinline__ void relax_span(const BArgs &A, uint32_t g, uint32_t 
                 ak[j] = __shfl(dv.y, k & 63);
                 const uint32_t ek = b0 + k;
                 ok[j] = k < cnt && has && ek >= lo && ek < end && ak[j] <= tw;
-                cur[j] = ok[j] ? A.arr[(gbase + vk[j]) * 64 + lane] : 0u;
+                cur[j] = A.arr[ok[j] ? (gbase + vk[j]) * 64 + lane : 0];
             }
             // all BU atomic minima of this lane are in flight together
             uint32_t old[BU];
 #pragma unroll
             for (int j = 0; j < BU; ++j) {
                 ok[j] = ok[j] && ak[j] < cur[j];
-                old[j] = ok[j] ? atomicMin(&A.arr[(gbase + vk[j]) * 64 + lane], ak[j]) : 0u;
+                if (ok[j]) old[j] = atomicMin(&A.arr[(gbase + vk[j]) * 64 + lane], ak[j]);
             }
             unsigned long long mymask = 0;
             uint32_t myv = 0;
@@ -155,21 +139,16 @@ __device__ __forceinline__ void relax_span(const BArgs &A, uint32_t g, uint32_t 
                 const unsigned long long old = atomicOr(&A.mask_next[gbase + myv], mymask);
                 first = old == 0ull;
             }
-            const unsigned long long fb = __ballot(first);
-            if (fb) {
-                const uint32_t pos = Q.wn + __popcll(fb & ((1ull << lane) - 1ull));
-                if (first) Q.buf[pos] = (uint32_t)(gbase + myv);
-                __builtin_amdgcn_wave_barrier();
-                Q.wn += __popcll(fb);
-                if (Q.wn > 64 - BU) wq_flush(A, Q, next_cnt);
-            }
+            const unsigned long long fb[1] = {__ballot(first)};
+            const uint32_t head[1] = {(uint32_t)(gbase + myv)};
+            stage_append(S, fb, head);
         }
     }
 }
 
 __global__ __launch_bounds__(BTB) void bpush_kernel(BArgs A)
 {
-    __shared__ uint32_t s_q[BTB / 64][64];
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wid = threadIdx.x >> 6;
     const uint32_t r3 = A.round % 3u;
@@ -179,10 +158,9 @@ __global__ __launch_bounds__(BTB) void bpush_kernel(BArgs A)
         A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
         A.cnt[BCNT_RANGE + (A.round + 1u) % 3u] = 0u;
     }
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    BStage S{s_stage[wid], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
     uint32_t *range_cnt = &A.cnt[BCNT_RANGE + r3];
-    WaveQueue Q{s_q[wid], 0};
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
     const uint32_t waves = gridDim.x * (BTB / 64);
     for (uint32_t i = blockIdx.x * (BTB / 64) + wid; i < F; i += waves) {
@@ -231,31 +209,22 @@ __global__ __launch_bounds__(BTB) void bpush_kernel(BArgs A)
                 n_edges -= covered;  // the chunk kernel counts what it reads
             }
         }
-        if (umin < umax) relax_span(A, g, umin, umax, has, lo, end, w.y, Q, next_cnt, n_relax);
+        if (umin < umax) relax_span(A, g, umin, umax, has, lo, end, w.y, S, n_relax);
     }
-    wq_flush(A, Q, next_cnt);
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) {
-            n_relax += __shfl_xor(n_relax, o);
-            n_items += __shfl_xor(n_items, o);
-        }
-        if (lane == 0) {
-            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
-            if (n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
-        }
-    }
+    stage_flush_block<SCAP, BTB / 64>(S);
+    unsigned long long v[3] = {n_relax, n_items, lane == 0 ? n_edges : 0ull};  // n_edges is per wavefront
+    const int slot[3] = {ST_RELAX, ST_ITEMS, ST_EDGES};
+    block_stats<BTB / 64>(A.stats, v, slot);
 }
 
 __global__ __launch_bounds__(BTB) void bchunk_kernel(BArgs A)
 {
-    __shared__ uint32_t s_q[BTB / 64][64];
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wid = threadIdx.x >> 6;
     const uint32_t r3 = A.round % 3u;
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
-    WaveQueue Q{s_q[wid], 0};
+    BStage S{s_stage[wid], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0;
     const uint32_t waves = gridDim.x * (BTB / 64);
     for (uint32_t c = blockIdx.x * (BTB / 64) + wid; c < C; c += waves) {
@@ -264,16 +233,12 @@ __global__ __launch_bounds__(BTB) void bchunk_kernel(BArgs A)
         const uint2 rg = A.ranges[(size_t)ch.y * 64 + lane];
         const uint2 w = A.qw[(size_t)g * 64 + lane];
         n_edges += ch.w;
-        relax_span(A, g, ch.z, ch.z + ch.w, rg.x < rg.y, rg.x, rg.y, w.y, Q, next_cnt, n_relax);
+        relax_span(A, g, ch.z, ch.z + ch.w, rg.x < rg.y, rg.x, rg.y, w.y, S, n_relax);
     }
-    wq_flush(A, Q, next_cnt);
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
-        if (lane == 0) {
-            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-            if (n_edges) atomicAdd(&A.stats[ST_CHUNK_EDGES], n_edges);
-        }
-    }
+    stage_flush_block<SCAP, BTB / 64>(S);
+    unsigned long long v[2] = {n_relax, lane == 0 ? n_edges : 0ull};  // n_edges is per wavefront
+    const int slot[2] = {ST_RELAX, ST_CHUNK_EDGES};
+    block_stats<BTB / 64>(A.stats, v, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,49 +265,41 @@ __device__ __forceinline__ uint32_t nth_set_bit(unsigned long long m, uint32_t j
 }
 
 // Relax HU edges per lane: arrival-row reads, atomic minima and head-mask ORs
-// are each issued together; heads whose mask was empty are enqueued with one
-// atomicAdd per wavefront.
-__device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, uint32_t *next_cnt, unsigned long long &n_relax)
+// are each issued together.  Heads whose mask was empty go to the next
+// frontier through the wavefront's staging buffer.
+__device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, unsigned long long &n_relax)
 {
-    uint32_t cur[HU];
+    // unconditional loads from valid addresses, predicated atomics without
+    // default values: nothing forces a wait between the HU requests
     size_t idx[HU];
+    uint32_t cur[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] <= H.tw[k];
         idx[k] = ((size_t)H.row[k] + H.v[k]) * 64 + H.bit[k];
-        cur[k] = H.ok[k] ? A.arr[idx[k]] : 0u;
+        cur[k] = A.arr[H.ok[k] ? idx[k] : 0];
     }
     uint32_t old[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] < cur[k];
-        old[k] = H.ok[k] ? atomicMin(&A.arr[idx[k]], H.a[k]) : 0u;
+        if (H.ok[k]) old[k] = atomicMin(&A.arr[idx[k]], H.a[k]);
     }
     unsigned long long om[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] < old[k];
         n_relax += H.ok[k] ? 1ull : 0ull;
-        om[k] = H.ok[k] ? atomicOr(&A.mask_next[(size_t)H.row[k] + H.v[k]], 1ull << H.bit[k]) : 1ull;
+        if (H.ok[k]) om[k] = atomicOr(&A.mask_next[(size_t)H.row[k] + H.v[k]], 1ull << H.bit[k]);
     }
     unsigned long long bal[HU];
-    uint32_t total = 0;
+    uint32_t head[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
-        bal[k] = __ballot(om[k] == 0ull);
-        total += __popcll(bal[k]);
+        bal[k] = __ballot(H.ok[k] && om[k] == 0ull);
+        head[k] = H.row[k] + H.v[k];
     }
-    if (total == 0) return;
-    const uint32_t lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(next_cnt, total);
-    base = __shfl(base, 0);
-    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-    for (int k = 0; k < HU; ++k) {
-        if ((bal[k] >> lane) & 1ull) A.next[base + __popcll(bal[k] & lt)] = H.row[k] + H.v[k];
-        base += __popcll(bal[k]);
-    }
+    stage_append(S, bal, head);
 }
 
 __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
@@ -353,6 +310,9 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
     __shared__ uint32_t s_lo[BTB], s_row[BTB], s_bit[BTB], s_tw[BTB];
     __shared__ uint32_t s_pref[BTB + 1];
     __shared__ uint32_t s_wsum[BTB / 64];
+    __shared__ uint32_t s_csum[BTB / 64];
+    __shared__ uint32_t s_cb;
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -363,7 +323,7 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
         A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
         A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
     }
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    BStage S{s_stage[w], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
 
@@ -398,7 +358,7 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
         for (uint32_t p0 = 0; p0 < P; p0 += BTB) {
             // one (vertex, query) pair per thread: claim its newly usable range
             const uint32_t p = p0 + tid;
-            uint32_t lo = 0, len = 0, row = 0, bit = 0, tw = 0, ser_lo = 0, ser_len = 0;
+            uint32_t lo = 0, len = 0, row = 0, bit = 0, tw = 0, e_ = 0, nch = 0;
             if (p < P) {
                 int lk = 0, hk = BTB;
                 while (hk - lk > 1) {
@@ -408,7 +368,7 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
                     else
                         hk = mid;
                 }
-                const uint32_t e_ = s_ent[lk];
+                e_ = s_ent[lk];
                 bit = nth_set_bit(s_mask[lk], p - s_pp[lk]);
                 const uint32_t g = e_ / A.n;
                 const uint32_t u = e_ - g * A.n;
@@ -425,45 +385,57 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
                     len = end - lo;
                     A.done[slot] = lo;
                 }
-                if (len >= A.split) {
-                    const uint32_t nch = (len + A.chunk - 1) / A.chunk;
-                    const uint32_t cb = atomicAdd(chunk_cnt, nch);
-                    const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
-                    for (uint32_t k = 0; k < fit; ++k)
-                        A.chunks[cb + k] = make_uint4(e_, bit, lo + k * A.chunk, min(A.chunk, len - k * A.chunk));
-                    const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
-                    lo += covered;
-                    len -= covered;
-                    if (len >= A.split) {
-                        // chunk list full: this lane walks the rest by itself
-                        ser_lo = lo;
-                        ser_len = len;
-                        len = 0;
-                    }
-                }
+                if (len >= A.split) nch = (len + A.chunk - 1) / A.chunk;
             }
-            // prefix over claim lengths, each below `split`
-            uint32_t y2 = len;
+            // prefix sums over the block: short claim lengths (each below
+            // `split`) and chunk counts (one chunk-list reservation per pass)
+            const uint32_t sl = nch ? 0u : len;
+            uint32_t y2 = sl, c2 = nch;
             for (int o = 1; o < 64; o <<= 1) {
                 const uint32_t t2 = __shfl_up(y2, o);
-                if (lane >= o) y2 += t2;
+                const uint32_t t3 = __shfl_up(c2, o);
+                if (lane >= o) {
+                    y2 += t2;
+                    c2 += t3;
+                }
             }
             __syncthreads();
-            if (lane == 63) s_wsum[w] = y2;
+            if (lane == 63) {
+                s_wsum[w] = y2;
+                s_csum[w] = c2;
+            }
             s_lo[tid] = lo;
             s_row[tid] = row;
             s_bit[tid] = bit;
             s_tw[tid] = tw;
             __syncthreads();
-            uint32_t wo = 0, total = 0;
+            uint32_t wo = 0, total = 0, co = 0, ctotal = 0;
             for (int w2 = 0; w2 < BTB / 64; ++w2) {
-                if (w2 < w) wo += s_wsum[w2];
+                if (w2 < w) {
+                    wo += s_wsum[w2];
+                    co += s_csum[w2];
+                }
                 total += s_wsum[w2];
+                ctotal += s_csum[w2];
             }
-            s_pref[tid] = wo + y2 - len;
-            if (tid == 0) s_pref[BTB] = total;
+            s_pref[tid] = wo + y2 - sl;
+            if (tid == 0) {
+                s_pref[BTB] = total;
+                if (ctotal) s_cb = atomicAdd(chunk_cnt, ctotal);
+            }
             __syncthreads();
-            n_edges += total;
+            uint32_t ser_lo = 0, ser_len = 0;
+            if (nch) {
+                const uint32_t cb = s_cb + co + c2 - nch;
+                const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
+                for (uint32_t k = 0; k < fit; ++k)
+                    A.chunks[cb + k] = make_uint4(e_, bit, lo + k * A.chunk, min(A.chunk, len - k * A.chunk));
+                const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
+                // chunk list full: this lane walks the rest by itself
+                ser_lo = lo + covered;
+                ser_len = len - covered;
+            }
+            if (tid == 0) n_edges += total;
             for (uint32_t j0 = 0; j0 < total; j0 += BTB * HU) {
                 HGroup H;
 #pragma unroll
@@ -471,31 +443,30 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
                     const uint32_t j = j0 + k * BTB + tid;
                     H.ok[k] = j < total;
                     int lk = 0, hk = BTB;
-                    if (H.ok[k]) {
-                        while (hk - lk > 1) {
-                            const int mid = (lk + hk) >> 1;
-                            if (s_pref[mid] <= j)
-                                lk = mid;
-                            else
-                                hk = mid;
-                        }
+                    while (hk - lk > 1) {
+                        const int mid = (lk + hk) >> 1;
+                        if (s_pref[mid] <= j)
+                            lk = mid;
+                        else
+                            hk = mid;
                     }
-                    const uint2 dv = H.ok[k] ? A.da[s_lo[lk] + (j - s_pref[lk])] : make_uint2(0u, 0u);
+                    const uint2 dv = A.da[H.ok[k] ? s_lo[lk] + (j - s_pref[lk]) : 0u];
                     H.v[k] = dv.x;
                     H.a[k] = dv.y;
                     H.row[k] = s_row[lk];
                     H.bit[k] = s_bit[lk];
                     H.tw[k] = s_tw[lk];
                 }
-                hrelax(A, H, next_cnt, n_relax);
+                hrelax(A, H, S, n_relax);
             }
+            n_edges += ser_len;
             uint32_t ser_done = 0;
             while (__ballot(ser_done < ser_len)) {
                 HGroup H;
 #pragma unroll
                 for (int k = 0; k < HU; ++k) {
                     H.ok[k] = ser_done < ser_len;
-                    const uint2 dv = H.ok[k] ? A.da[ser_lo + ser_done] : make_uint2(0u, 0u);
+                    const uint2 dv = A.da[H.ok[k] ? ser_lo + ser_done : 0u];
                     if (H.ok[k]) ++ser_done;
                     H.v[k] = dv.x;
                     H.a[k] = dv.y;
@@ -503,32 +474,25 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
                     H.bit[k] = bit;
                     H.tw[k] = tw;
                 }
-                hrelax(A, H, next_cnt, n_relax);
+                hrelax(A, H, S, n_relax);
             }
-            if (ser_len && A.stats) atomicAdd(&A.stats[ST_EDGES], (unsigned long long)ser_len);
             __syncthreads();
         }
     }
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) {
-            n_relax += __shfl_xor(n_relax, o);
-            n_items += __shfl_xor(n_items, o);
-        }
-        if (lane == 0) {
-            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-            if (n_items) atomicAdd(&A.stats[ST_ITEMS], n_items);
-        }
-        if (tid == 0 && n_edges) atomicAdd(&A.stats[ST_EDGES], n_edges);
-    }
+    stage_flush_block<SCAP, BTB / 64>(S);
+    unsigned long long v[3] = {n_relax, n_items, n_edges};
+    const int slot[3] = {ST_RELAX, ST_ITEMS, ST_EDGES};
+    block_stats<BTB / 64>(A.stats, v, slot);
 }
 
 // Chunks of the lane-dense variant: {entry, query bit, start, len}; one
 // wavefront per chunk, HU edges per lane in flight, every lane active.
 __global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
 {
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
     const uint32_t r3 = A.round % 3u;
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    BStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (BTB / 64);
@@ -536,35 +500,27 @@ __global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
         const uint4 ch = A.chunks[c];
         const uint32_t g = ch.x / A.n;
         const uint32_t tw = A.qw[(size_t)g * 64 + ch.y].y;
-        n_edges += ch.w;
+        if (lane == 0) n_edges += ch.w;
         for (uint32_t k0 = 0; k0 < ch.w; k0 += 64 * HU) {
             HGroup H;
 #pragma unroll
             for (int k = 0; k < HU; ++k) {
                 const uint32_t off = k0 + k * 64 + lane;
                 H.ok[k] = off < ch.w;
-                const uint2 dv = H.ok[k] ? A.da[ch.z + off] : make_uint2(0u, 0u);
+                const uint2 dv = A.da[H.ok[k] ? ch.z + off : 0u];
                 H.v[k] = dv.x;
                 H.a[k] = dv.y;
                 H.row[k] = g * A.n;
                 H.bit[k] = ch.y;
                 H.tw[k] = tw;
             }
-            hrelax(A, H, next_cnt, n_relax);
+            hrelax(A, H, S, n_relax);
         }
     }
-    __shared__ unsigned long long s_e[BTB / 64];
-    if (lane == 0) s_e[threadIdx.x >> 6] = n_edges;
-    __syncthreads();
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) n_relax += __shfl_xor(n_relax, o);
-        if (lane == 0 && n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-        if (threadIdx.x == 0) {
-            unsigned long long blk = 0;
-            for (int w2 = 0; w2 < BTB / 64; ++w2) blk += s_e[w2];
-            if (blk) atomicAdd(&A.stats[ST_CHUNK_EDGES], blk);
-        }
-    }
+    stage_flush_block<SCAP, BTB / 64>(S);
+    unsigned long long v[2] = {n_relax, n_edges};
+    const int slot[2] = {ST_RELAX, ST_CHUNK_EDGES};
+    block_stats<BTB / 64>(A.stats, v, slot);
 }
 
 // Group start: every query's source gets its t_alpha and its mask bit; the
@@ -585,9 +541,11 @@ __global__ void binit_kernel(BArgs A, const uint4 *__restrict__ hq, uint32_t q)
     }
 }
 
-// out[(g*64+q)*n + v] = arr[(g*n+v)*64 + q] through a 64x64 LDS tile.
+// out[(g*64+q)*n + v] = arr[(g*n+perm[v])*64 + q] (caller id v) through a
+// 64x64 LDS tile: 64 gathered 256-byte rows in, 64 coalesced columns out.
 __global__ __launch_bounds__(256) void btranspose_kernel(const uint32_t *__restrict__ arr, uint32_t *__restrict__ out,
-                                                         uint32_t n, uint32_t q_total, uint32_t groups)
+                                                         const uint32_t *__restrict__ perm, uint32_t n,
+                                                         uint32_t q_total, uint32_t groups)
 {
     __shared__ uint32_t tile[64][65];
     const uint32_t tiles_v = (n + 63) / 64;
@@ -596,7 +554,7 @@ __global__ __launch_bounds__(256) void btranspose_kernel(const uint32_t *__restr
         const uint32_t v0 = (uint32_t)(t % tiles_v) * 64;
         for (int k = threadIdx.x; k < 64 * 64; k += 256) {
             const uint32_t vv = k / 64, qq = k % 64;
-            if (v0 + vv < n) tile[vv][qq] = arr[((size_t)g * n + v0 + vv) * 64 + qq];
+            if (v0 + vv < n) tile[vv][qq] = arr[((size_t)g * n + perm[v0 + vv]) * 64 + qq];
         }
         __syncthreads();
         for (int k = threadIdx.x; k < 64 * 64; k += 256) {
@@ -687,7 +645,7 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
     }
     b->chunks = (uint4 *)dev_alloc(std::max<uint64_t>(b->chunk_cap, 1) * sizeof(uint4), nullptr);
     b->ranges = (uint2 *)dev_alloc(std::max<uint64_t>(b->range_cap, 1) * 64 * sizeof(uint2), nullptr);
-    b->stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, nullptr);
+    b->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, nullptr);
     bool ok = b->arr && b->done && b->queue[0] && b->queue[1] && b->cnt && b->mask[0] && b->mask[1] && b->qw &&
               b->chunks && b->ranges && b->stats;
     if (ok && hipHostMalloc((void **)&b->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
@@ -704,7 +662,7 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
         }
     }
     if (ok)
-        ok = hipMemsetAsync(b->stats, 0, ST_WORDS * 8, b->stream) == hipSuccess &&
+        ok = hipMemsetAsync(b->stats, 0, ST_TOTAL_WORDS * 8, b->stream) == hipSuccess &&
              hipMemsetAsync(b->mask[0], 0, gn * 8, b->stream) == hipSuccess &&
              hipMemsetAsync(b->mask[1], 0, gn * 8, b->stream) == hipSuccess &&
              hipStreamSynchronize(b->stream) == hipSuccess;
@@ -741,7 +699,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     // clears its word); a failed run destroys this state instead
 
     std::vector<uint4> hq(q);
-    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(src[i], ta[i], tw[i], 0);
+    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], 0);
     uint4 *staging = nullptr;
     if (hipHostMalloc((void **)&staging, std::max<size_t>(q, 1) * sizeof(uint4), hipHostMallocDefault) != hipSuccess)
         return KAIROS_ERR_NOMEM;
@@ -760,9 +718,9 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     A.chunk_cap = (uint32_t)std::min<uint64_t>(b->chunk_cap, 0xFFFFFFF0u);
     A.ranges = b->ranges;
     A.range_cap = (uint32_t)b->range_cap;
-    A.stats = b->stats;
-    A.split = std::max<uint32_t>(g->tuning.split, 64);
-    A.chunk = std::max<uint32_t>(g->tuning.chunk, 64);
+    A.stats = g->prof.on ? b->stats : nullptr;
+    A.split = std::max<uint32_t>(g->tuning.split, 16);
+    A.chunk = std::max<uint32_t>(g->tuning.chunk, 16);
     A.max_t = g->max_t;
     A.round = 0;
     A.mask_cur = b->mask[0];
@@ -813,14 +771,16 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     }
     prof_begin(g, st, &ev);
     hipLaunchKernelGGL(btranspose_kernel, dim3(gridc((uint64_t)((g->n + 63) / 64) * groups, 1, 16384)), dim3(256), 0,
-                       st, b->arr, out, g->n, q, groups);
+                       st, b->arr, out, g->perm, g->n, q, groups);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
     KAIROS_HIP(hipStreamSynchronize(st));
     if (g->prof.on) {
+        std::vector<unsigned long long> raw((size_t)ST_SHARDS * ST_WORDS);
         unsigned long long h[ST_WORDS];
-        KAIROS_HIP(hipMemcpy(h, b->stats, sizeof(h), hipMemcpyDeviceToHost));
-        KAIROS_HIP(hipMemset(b->stats, 0, sizeof(h)));
+        KAIROS_HIP(hipMemcpy(raw.data(), b->stats, raw.size() * 8, hipMemcpyDeviceToHost));
+        KAIROS_HIP(hipMemset(b->stats, 0, raw.size() * 8));
+        stats_sum_shards(raw.data(), h);
         prof_add_stats(g, h);
     }
     return KAIROS_OK;

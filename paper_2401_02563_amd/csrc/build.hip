@@ -279,6 +279,49 @@ __global__ void max_degree_kernel(const uint32_t *__restrict__ off, uint32_t n, 
     if ((threadIdx.x & 63) == 0) atomicMax(out, best);
 }
 
+// Vertex relabelling: new ids in order of decreasing in-degree (ties by id),
+// so the arrival words of the most-targeted heads share cache lines.
+__global__ void indegree_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t *deg)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&deg[e[i].y], 1u);
+}
+
+__global__ void vertex_keys_kernel(const uint32_t *__restrict__ deg, uint32_t n, uint4 *out)
+{
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
+        out[v] = make_uint4(~deg[v], (uint32_t)v, 0u, 0u);  // ascending ~deg = descending in-degree
+}
+
+__global__ void perm_kernel(const uint4 *__restrict__ sorted, uint32_t n, uint32_t *perm, uint32_t *inv)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = sorted[i].y;
+        perm[v] = (uint32_t)i;
+        inv[i] = v;
+    }
+}
+
+__global__ void remap_kernel(uint4 *e, uint64_t m, const uint32_t *__restrict__ perm)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 r = e[i];
+        r.x = perm[r.x];
+        r.y = perm[r.y];
+        e[i] = r;
+    }
+}
+
+__global__ void identity_perm_kernel(uint32_t n, uint32_t *perm, uint32_t *inv)
+{
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
+        perm[v] = (uint32_t)v;
+        inv[v] = (uint32_t)v;
+    }
+}
+
 int bits_for(uint64_t x)
 {
     int b = 0;
@@ -338,9 +381,12 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
     g->a_in = (uint32_t *)dev_alloc(sizeof(uint32_t) * words, acct);
     g->da_out = (uint2 *)dev_alloc(sizeof(uint2) * words, acct);
     g->st_in = (uint2 *)dev_alloc(sizeof(uint2) * words, acct);
-    if (!g->off_out || !g->off_in || !g->t_out || !g->a_in || !g->da_out || !g->st_in)
+    g->perm = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)n, acct);
+    g->inv = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)n, acct);
+    if (!g->off_out || !g->off_in || !g->t_out || !g->a_in || !g->da_out || !g->st_in || !g->perm || !g->inv)
         return KAIROS_ERR_NOMEM;
     if (m == 0) {
+        hipLaunchKernelGGL(identity_perm_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, n, g->perm, g->inv);
         hipLaunchKernelGGL(zero_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256),
                            0, st, g->off_out, n);
         hipLaunchKernelGGL(zero_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256),
@@ -348,6 +394,8 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         KAIROS_HIP(hipGetLastError());
         KAIROS_HIP(hipStreamSynchronize(st));
         g->max_out_degree = 0;
+        g->h_perm.resize(n);
+        for (uint32_t v = 0; v < n; ++v) g->h_perm[v] = v;
         return KAIROS_OK;
     }
     uint64_t scratch = 0;
@@ -402,6 +450,45 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         add_field(in_p, F_LAMREV, lb, max_l);
         add_field(in_p, F_A, bits_for(max_a), 0);
         add_field(in_p, F_DST, nb, 0);
+        {
+            // relabel: in-degrees, stable sort of vertices by descending
+            // in-degree, then remap both endpoints of every record
+            uint64_t vs = 0;
+            const uint64_t vtiles = ((uint64_t)n + STILE - 1) / STILE;
+            const uint32_t vblocks = (uint32_t)std::min<uint64_t>(vtiles, 1024);
+            uint32_t *deg = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)n, &vs);
+            uint4 *va = (uint4 *)dev_alloc(sizeof(uint4) * (size_t)n, &vs);
+            uint4 *vb = (uint4 *)dev_alloc(sizeof(uint4) * (size_t)n, &vs);
+            uint32_t *vhist = (uint32_t *)dev_alloc(sizeof(uint32_t) * 256 * (size_t)vblocks, &vs);
+            if (!deg || !va || !vb || !vhist) {
+                dev_free(deg);
+                dev_free(va);
+                dev_free(vb);
+                dev_free(vhist);
+                rc = KAIROS_ERR_NOMEM;
+                break;
+            }
+            prof_begin(g, st, &ev);
+            const bool okm = hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st) == hipSuccess;
+            hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, a, m, deg);
+            hipLaunchKernelGGL(vertex_keys_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, deg, n, va);
+            prof_end(g, st, KAIROS_K_SORT, ev);
+            std::vector<Pass> vp;
+            add_field(vp, F_SRC, 32, 0);
+            rc = okm ? run_passes(g, va, vb, n, vp, vhist, st) : KAIROS_ERR_DEVICE;
+            if (rc == KAIROS_OK) {
+                hipLaunchKernelGGL(perm_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, va, n, g->perm,
+                                   g->inv);
+                hipLaunchKernelGGL(remap_kernel, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, a, m, g->perm);
+                if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+            }
+            hipStreamSynchronize(st);
+            dev_free(deg);
+            dev_free(va);
+            dev_free(vb);
+            dev_free(vhist);
+            if (rc != KAIROS_OK) break;
+        }
         if ((rc = run_passes(g, a, b, m, out_p, hist, st)) != KAIROS_OK) break;
         const int fg = grid_for(m, 256, 16384);
         hipLaunchKernelGGL(finalize_kernel, dim3(fg), dim3(256), 0, st, a, m, n, 0, g->off_out,
@@ -421,6 +508,11 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
             rc = KAIROS_ERR_DEVICE;
         else
             g->max_out_degree = h_stats[0];
+    }
+    if (rc == KAIROS_OK) {
+        g->h_perm.resize(n);
+        if (hipMemcpy(g->h_perm.data(), g->perm, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = KAIROS_ERR_DEVICE;
     }
     hipStreamSynchronize(st);
     dev_free(a);

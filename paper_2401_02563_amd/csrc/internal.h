@@ -50,10 +50,11 @@ struct Slot {
     uint32_t *arr = nullptr;     // n: arrival scratch for the sweep queries
     uint32_t *fa = nullptr;      // n: fastest duration (sweep)
     uint32_t *l1 = nullptr;      // n: latest departure + 1 (sweep), 0 = none
+    uint32_t *steps = nullptr;   // sweep departure times, descending (max out-degree)
     uint32_t *cnt = nullptr;     // device counters, see CNT_* below
     unsigned long long *stats = nullptr; // device work counters, see ST_*
     uint32_t *h_pin = nullptr;   // pinned host mirror for counter read-back
-    uint32_t stamp_next = 1;     // next round stamp value
+    uint32_t stamp_next = 2;     // next round stamp value (0 = never stamped, 1 = spare)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t bytes = 0;
@@ -63,7 +64,7 @@ struct Slot {
 enum : int {
     CNT_FRONT = 0,   // [0..2] rotating frontier sizes
     CNT_CHUNK = 3,   // [3..5] rotating chunk-list sizes
-    CNT_ERR = 6,     // sticky error bits
+    CNT_STEP = 6,    // next departure step of a latest-departure / fastest sweep
     CNT_PULLVOL = 7, // [7..9] rotating: out-edges of the next frontier (saturating)
     CNT_TAIL_ROUND = 13, CNT_TAIL_WHICH = 14, CNT_TAIL_ROUNDS = 15,  // left by the tail kernel
     CNT_WORDS = 16
@@ -72,6 +73,19 @@ enum : int {
     ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5, ST_ATTEMPTS = 6,
     ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_WORDS = 16
 };
+// The work counters are kept in ST_SHARDS copies (a block adds to copy
+// blockIdx % ST_SHARDS, so concurrent additions hit different addresses),
+// followed by ST_SHARDS partial sums used by the traversed-edge count.
+constexpr int ST_SHARDS = 64;
+constexpr size_t ST_TOTAL_WORDS = (size_t)ST_SHARDS * ST_WORDS + ST_SHARDS;
+
+// Sums the shards of a host copy of the work counters into h[ST_WORDS].
+inline void stats_sum_shards(const unsigned long long *raw, unsigned long long *h)
+{
+    for (int k = 0; k < ST_WORDS; ++k) h[k] = 0;
+    for (int sh = 0; sh < ST_SHARDS; ++sh)
+        for (int k = 0; k < ST_WORDS; ++k) h[k] += raw[sh * ST_WORDS + k];
+}
 
 struct VBatch;
 
@@ -98,6 +112,11 @@ struct kairos_graph {
     uint32_t *off_in = nullptr;   // n+1
     uint32_t *a_in = nullptr;     // m
     uint2 *st_in = nullptr;       // m: {tail, departure}
+    // vertex labels: the index uses internal ids ordered by decreasing
+    // in-degree; perm maps caller ids to internal ids, inv the reverse
+    uint32_t *perm = nullptr;     // n
+    uint32_t *inv = nullptr;      // n
+    std::vector<uint32_t> h_perm; // host copy of perm
     uint32_t max_out_degree = 0;
     uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
     uint64_t index_bytes = 0;
@@ -147,7 +166,7 @@ struct MultiState {
     uint4 *chunks = nullptr, *qp = nullptr;
     uint64_t chunk_cap = 0;
     unsigned long long *stats = nullptr;
-    uint32_t round = 0, stamp_next = 1;
+    uint32_t round = 0, stamp_next = 2;
     hipStream_t stream = nullptr;
 };
 // One slot start or sweep step: qp[q] = {src, ta, tw, sdep}; the source

@@ -133,13 +133,13 @@ bool grow(kairos_server *s, uint32_t ncap)
     nm.cnt = (uint32_t *)dev_alloc((CNT_WORDS + (size_t)ncap) * 4, nullptr);
     nm.chunks = (uint4 *)dev_alloc(nm.chunk_cap * sizeof(uint4), nullptr);
     nm.qp = (uint4 *)dev_alloc((size_t)ncap * sizeof(uint4), nullptr);
-    nm.stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, nullptr);
+    nm.stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, nullptr);
     hipStream_t st = s->ms.stream;
     bool ok = nm.arr && nm.done && nm.stamp && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
               nm.chunks && nm.qp && nm.stats;
     ok = ok && hipMemsetAsync(nm.stamp, 0, qn * 4, st) == hipSuccess &&
          hipMemsetAsync(nm.cnt, 0, (CNT_WORDS + (size_t)ncap) * 4, st) == hipSuccess &&
-         hipMemsetAsync(nm.stats, 0, ST_WORDS * 8, st) == hipSuccess;
+         hipMemsetAsync(nm.stats, 0, ST_TOTAL_WORDS * 8, st) == hipSuccess;
     if (ok && s->cap) {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
         ok = hipMemcpyAsync(nm.arr, s->ms.arr, on * 4, k, st) == hipSuccess &&
@@ -158,7 +158,7 @@ bool grow(kairos_server *s, uint32_t ncap)
         (void)hipGetLastError();
         return false;
     }
-    free_state(s->ms);
+    free_state(s->ms);  // nm already carries the stream
     s->ms = nm;
     s->cap = ncap;
     s->slots.resize(ncap);
@@ -182,7 +182,7 @@ int sweep_steps(kairos_server *s, const Query &q, std::vector<uint32_t> &steps)
     kairos_graph *g = s->g;
     hipStream_t st = s->ms.stream;
     uint32_t off[2];
-    KAIROS_HIP(hipMemcpyAsync(s->h_pin, g->off_out + q.src, 8, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipMemcpyAsync(s->h_pin, g->off_out + g->h_perm[q.src], 8, hipMemcpyDeviceToHost, st));
     KAIROS_HIP(hipStreamSynchronize(st));
     off[0] = s->h_pin[0];
     off[1] = s->h_pin[1];
@@ -284,14 +284,14 @@ int iterate(kairos_server *s, std::vector<Inject> &pending, uint32_t &front)
     for (uint32_t slot : admitted) {
         SlotRun &sl = s->slots[slot];
         if (sl.q.kind == 0) {
-            pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, INF, 0, 0, 0});
+            pending.push_back(Inject{slot, g->h_perm[sl.q.src], sl.q.ta, sl.q.tw, INF, 0, 0, 0});
         } else {
             int rc = sweep_steps(s, sl.q, sl.steps);
             if (rc) return rc;
             if (sl.steps.empty()) {
                 finish_now.push_back(slot);
             } else {
-                pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, sl.steps[0], 0, 0, 0});
+                pending.push_back(Inject{slot, g->h_perm[sl.q.src], sl.q.ta, sl.q.tw, sl.steps[0], 0, 0, 0});
                 sl.next_step = 1;
             }
         }
@@ -323,7 +323,7 @@ int iterate(kairos_server *s, std::vector<Inject> &pending, uint32_t &front)
         if (std::find(finish_now.begin(), finish_now.end(), slot) != finish_now.end()) continue;
         if (flags[slot] == s->ms.round) continue;  // still has frontier work
         if (sl.q.kind != 0 && sl.next_step < sl.steps.size()) {
-            pending.push_back(Inject{slot, sl.q.src, sl.q.ta, sl.q.tw, sl.steps[sl.next_step++], 0, 0, 0});
+            pending.push_back(Inject{slot, g->h_perm[sl.q.src], sl.q.ta, sl.q.tw, sl.steps[sl.next_step++], 0, 0, 0});
             continue;
         }
         finished.push_back(slot);
@@ -470,10 +470,11 @@ void kairos_server_free(kairos_server *s)
         s->cv.notify_all();
     }
     if (s->th.joinable()) s->th.join();
-    hipStreamSynchronize(s->ms.stream);
+    hipStream_t st = s->ms.stream;  // free_state clears the struct
+    (void)hipStreamSynchronize(st);
     free_state(s->ms);
-    if (s->h_pin) hipHostFree(s->h_pin);
-    if (s->own_stream) hipStreamDestroy(s->ms.stream);
+    if (s->h_pin) (void)hipHostFree(s->h_pin);
+    if (s->own_stream) (void)hipStreamDestroy(st);
     delete s;
 }
 

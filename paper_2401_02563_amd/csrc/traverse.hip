@@ -22,12 +22,15 @@
 //    redundant atomic, never a missed update; the tail's own arrival is read
 //    with an atomic load.
 //  * Each frontier vertex is enqueued at most once per round through a round
-//    stamp; enqueueing is aggregated per wave with a ballot.
+//    stamp.  New entries are collected per wave in LDS and reserved in the
+//    global frontier with one atomicAdd per flush, since same-address atomics
+//    are serialised at the memory side.
 //  * Work is balanced inside a block by a prefix sum over the claimed range
 //    lengths; ranges of at least `split` edges are cut into chunks of `chunk`
 //    edges that a second kernel spreads over the whole GPU.
 
 #include "internal.h"
+#include "stage.h"
 
 #include <algorithm>
 #include <chrono>
@@ -70,6 +73,10 @@ struct TravArgs {
     uint32_t track_volume;   // accumulate out-degree of enqueued vertices
     uint32_t *qflag;         // per query: round+1 when it enqueued something (or null)
     uint32_t max_t;          // largest departure time in the graph
+    const uint32_t *steps;   // sweep departure times, descending (single query)
+    uint32_t nsteps;
+    uint32_t dense;          // 1: walk all vertices, members have stamp == front_stamp
+    uint32_t front_stamp;    // stamp value that marked the current frontier
 };
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t lo,
@@ -85,33 +92,6 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__
     return lo;
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt()
-{
-    const uint32_t lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Wave-aggregated append of `item` for the lanes with `push` set.
-__device__ __forceinline__ void enqueue(const TravArgs &A, bool push, uint32_t item, uint32_t v,
-                                        uint32_t *next_cnt, uint32_t *vol_cnt)
-{
-    if (push && A.qflag) A.qflag[item / A.n] = A.round + 1u;
-    const uint64_t bal = __ballot(push);
-    if (bal == 0) return;
-    const uint32_t lane = threadIdx.x & 63;
-    const int leader = __ffsll((unsigned long long)bal) - 1;
-    uint32_t base = 0;
-    if ((int)lane == leader) base = atomicAdd(next_cnt, (uint32_t)__popcll(bal));
-    base = __shfl(base, leader);
-    if (push) {
-        A.next[base + __popcll(bal & lanemask_lt())] = item;
-        if (A.track_volume) {
-            const uint32_t deg = A.off[v + 1] - A.off[v];
-            if (deg) atomicAdd(vol_cnt, deg);
-        }
-    }
-}
-
 // Edges are relaxed UNR at a time per lane: all loads of the group are
 // issued before any result is used, so each lane keeps several independent
 // memory requests in flight (the edge record, then the head's arrival).
@@ -125,24 +105,29 @@ struct EdgeGroup {
 // Relax a group of UNR edges per lane.  The arrival reads, the atomic
 // minima and the stamp exchanges of the group are each issued together (they
 // are independent), so a lane waits for one round trip per stage instead of
-// one per edge, and the whole group is enqueued with a single atomicAdd per
-// wavefront.
+// one per edge.  On return bal[k] holds the lanes whose edge k put its head
+// into the next frontier (first improvement of the round) and item[k] that
+// entry; the caller appends them to its output.
 template <bool SWEEP>
-__device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uint32_t *next_cnt,
-                                            uint32_t *vol_cnt, unsigned long long &nrelax)
+__device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, unsigned long long (&bal)[UNR],
+                                            uint32_t (&item)[UNR], uint32_t *vol_cnt, unsigned long long &nrelax)
 {
+    // Loads are unconditional from a valid address (a masked-off lane reads
+    // word 0), and results of predicated atomics get no default value: a
+    // conditional load or atomic whose register is also written on the other
+    // path must complete before that write, which would serialise the group.
     size_t sv[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         G.ok[k] = G.ok[k] && G.a[k] <= G.tw[k];
         sv[k] = (size_t)G.q[k] * A.n + G.v[k];
-        G.cur[k] = G.ok[k] ? A.arr[sv[k]] : 0u;
+        G.cur[k] = A.arr[G.ok[k] ? sv[k] : 0];
     }
     uint32_t old[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         G.ok[k] = G.ok[k] && G.a[k] < G.cur[k];
-        old[k] = G.ok[k] ? atomicMin(&A.arr[sv[k]], G.a[k]) : 0u;
+        if (G.ok[k]) old[k] = atomicMin(&A.arr[sv[k]], G.a[k]);
     }
     uint32_t st[UNR];
 #pragma unroll
@@ -150,7 +135,7 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uin
         nrelax += G.ok[k] ? (1ull << 32) : 0ull;  // high half: atomic attempts
         G.ok[k] = G.ok[k] && G.a[k] < old[k];
         nrelax += G.ok[k] ? 1ull : 0ull;
-        st[k] = G.ok[k] ? atomicExch(&A.stamp[sv[k]], A.stamp_val) : A.stamp_val;
+        if (G.ok[k]) st[k] = atomicExch(&A.stamp[sv[k]], A.stamp_val);
     }
     if (SWEEP) {
 #pragma unroll
@@ -160,57 +145,51 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uin
                 atomicMax(&A.l1[sv[k]], G.sd[k] + 1u);
             }
     }
-    unsigned long long bal[UNR];
-    uint32_t total = 0;
+    uint32_t vol = 0;
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
-        bal[k] = __ballot(st[k] != A.stamp_val);
-        total += __popcll(bal[k]);
+        const bool push = G.ok[k] && st[k] != A.stamp_val;
+        bal[k] = __ballot(push);
+        item[k] = (uint32_t)sv[k];
+        if (push) {
+            if (A.qflag) A.qflag[G.q[k]] = A.round + 1u;
+            if (A.track_volume) vol += A.off[G.v[k] + 1] - A.off[G.v[k]];
+        }
     }
+    if (A.track_volume) {
+        for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o);
+        if ((threadIdx.x & 63) == 0 && vol) atomicAdd(vol_cnt, vol);
+    }
+}
+
+// Appends the group's entries to a frontier whose length lives in LDS (the
+// one-workgroup kernel): one LDS atomic per wavefront.
+__device__ __forceinline__ void lds_append(uint32_t *next, uint32_t *s_cnt, const unsigned long long (&bal)[UNR],
+                                           const uint32_t (&item)[UNR])
+{
+    uint32_t total = 0;
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) total += __popcll(bal[k]);
     if (total == 0) return;
     const uint32_t lane = threadIdx.x & 63;
     uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(next_cnt, total);
+    if (lane == 0) base = atomicAdd(s_cnt, total);
     base = __shfl(base, 0);
-    const uint64_t lt = lanemask_lt();
+    const uint64_t lt = lanes_below();
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
-        if (bal[k] >> lane & 1ull) {
-            A.next[base + __popcll(bal[k] & lt)] = (uint32_t)sv[k];
-            if (A.qflag) A.qflag[G.q[k]] = A.round + 1u;
-            if (A.track_volume) {
-                const uint32_t deg = A.off[G.v[k] + 1] - A.off[G.v[k]];
-                if (deg) atomicAdd(vol_cnt, deg);
-            }
-        }
+        if ((bal[k] >> lane) & 1ull) next[base + __popcll(bal[k] & lt)] = item[k];
         base += __popcll(bal[k]);
     }
 }
 
-__device__ __forceinline__ void stats_flush(const TravArgs &A, unsigned long long n_relax,
-                                            unsigned long long n_items, int edge_slot,
-                                            unsigned long long n_edges_block)
-{
-    if (!A.stats) return;
-    unsigned long long n_att = n_relax >> 32;
-    n_relax &= 0xFFFFFFFFull;
-    for (int o = 32; o > 0; o >>= 1) {
-        n_relax += __shfl_xor(n_relax, o);
-        n_att += __shfl_xor(n_att, o);
-        n_items += __shfl_xor(n_items, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-        if (n_att) atomicAdd(&A.stats[ST_ATTEMPTS], n_att);
-        if (n_items) atomicAdd(&A.stats[edge_slot == ST_TAIL_EDGES ? ST_TAIL_ITEMS : ST_ITEMS], n_items);
-    }
-    if (threadIdx.x == 0 && n_edges_block) atomicAdd(&A.stats[edge_slot], n_edges_block);
-}
+constexpr int SCAP = 512;  // staged frontier entries per wavefront
+using TStage = Stage<SCAP>;
 
 // Push round, part 1: one thread per frontier item claims the newly usable
 // part of its adjacency; short claims are relaxed by the block with a
 // prefix-sum load balance, claims of at least `split` edges are cut into
-// chunks for part 2.
+// chunks for part 2 (one chunk-list reservation per block and pass).
 template <bool SWEEP>
 __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
 {
@@ -220,6 +199,9 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
     __shared__ uint32_t s_tw[TB];
     __shared__ uint32_t s_sd[TB];
     __shared__ uint32_t s_wsum[TB / 64];
+    __shared__ uint32_t s_csum[TB / 64];
+    __shared__ uint32_t s_cb;
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -231,17 +213,21 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
         A.cnt[CNT_PULLVOL + (A.round + 2u) % 3u] = 0u;
         A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
     }
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    TStage S{s_stage[w], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
 
-    for (uint32_t base = blockIdx.x * TB; base < F; base += gridDim.x * TB) {
+    // sparse rounds walk the frontier queue; dense rounds walk every vertex
+    // in id order and expand the members (stamped by the previous round), so
+    // offsets, claim words and adjacency ranges are read in address order
+    const uint32_t span = A.dense ? A.n : F;
+    for (uint32_t base = blockIdx.x * TB; base < span; base += gridDim.x * TB) {
         const uint32_t i = base + tid;
-        uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, ser_lo = 0, ser_len = 0;
-        if (i < F) {
+        uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, nch = 0;
+        if (i < span && (!A.dense || A.stamp[i] == A.front_stamp)) {
             ++n_items;
-            const uint32_t item = A.cur[i];
+            const uint32_t item = A.dense ? i : A.cur[i];
             q = item / A.n;
             const uint32_t u = item - q * A.n;
             const uint4 p = A.qp[q];
@@ -261,83 +247,94 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
                 len = end - lo;
                 A.done[su] = lo;
             }
-            if (len >= A.split) {
-                const uint32_t nch = (len + A.chunk - 1) / A.chunk;
-                const uint32_t cb = atomicAdd(chunk_cnt, nch);
-                const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
-                for (uint32_t k = 0; k < fit; ++k) {
-                    const uint32_t s0 = lo + k * A.chunk;
-                    A.chunks[cb + k] = make_uint4(q, s0, min(A.chunk, len - k * A.chunk), 0u);
-                }
-                const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
-                lo += covered;
-                len -= covered;
-                if (len >= A.split) {
-                    // chunk list full: this lane walks the rest by itself
-                    ser_lo = lo;
-                    ser_len = len;
-                    len = 0;
-                }
-            }
+            if (len >= A.split) nch = (len + A.chunk - 1) / A.chunk;
         }
-        // exclusive prefix sum of len over the block (short claims only, so
-        // the block total stays below TB * split)
-        uint32_t x = len;
+        // exclusive prefix sums over the block of the short claim lengths
+        // (so the block total stays below TB * split) and of the chunk counts
+        const uint32_t sl = nch ? 0u : len;
+        uint32_t x = sl, c = nch;
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(x, o);
-            if (lane >= o) x += y;
+            const uint32_t z = __shfl_up(c, o);
+            if (lane >= o) {
+                x += y;
+                c += z;
+            }
         }
-        if (lane == 63) s_wsum[w] = x;
+        if (lane == 63) {
+            s_wsum[w] = x;
+            s_csum[w] = c;
+        }
         s_lo[tid] = lo;
         s_q[tid] = q;
         s_tw[tid] = tw;
         s_sd[tid] = sd;
         __syncthreads();
-        uint32_t woff = 0, total = 0;
+        uint32_t woff = 0, total = 0, coff = 0, ctotal = 0;
         for (int w2 = 0; w2 < TB / 64; ++w2) {
-            if (w2 < w) woff += s_wsum[w2];
+            if (w2 < w) {
+                woff += s_wsum[w2];
+                coff += s_csum[w2];
+            }
             total += s_wsum[w2];
+            ctotal += s_csum[w2];
         }
-        s_pref[tid] = woff + x - len;
-        if (tid == 0) s_pref[TB] = total;
+        s_pref[tid] = woff + x - sl;
+        if (tid == 0) {
+            s_pref[TB] = total;
+            if (ctotal) s_cb = atomicAdd(chunk_cnt, ctotal);
+        }
         __syncthreads();
-        n_edges += total;
+        uint32_t ser_lo = 0, ser_len = 0;
+        if (nch) {
+            const uint32_t cb = s_cb + coff + c - nch;
+            const uint32_t fit = cb >= A.chunk_cap ? 0u : min(nch, A.chunk_cap - cb);
+            for (uint32_t k = 0; k < fit; ++k)
+                A.chunks[cb + k] = make_uint4(q, lo + k * A.chunk, min(A.chunk, len - k * A.chunk), 0u);
+            const uint32_t covered = (uint32_t)min((uint64_t)len, (uint64_t)fit * A.chunk);
+            // chunk list full (not expected with the list sized from the
+            // tuning): this lane walks the rest by itself
+            ser_lo = lo + covered;
+            ser_len = len - covered;
+        }
+        if (tid == 0) n_edges += total;
         for (uint32_t j0 = 0; j0 < total; j0 += TB * UNR) {
             EdgeGroup G;
 #pragma unroll
             for (int k = 0; k < UNR; ++k) {
                 const uint32_t j = j0 + k * TB + tid;
                 G.ok[k] = j < total;
+                // owner: the last item whose prefix is <= j
                 int lo_k = 0, hi_k = TB;
-                if (G.ok[k]) {
-                    // owner: the last item whose prefix is <= j
-                    while (hi_k - lo_k > 1) {
-                        const int mid = (lo_k + hi_k) >> 1;
-                        if (s_pref[mid] <= j)
-                            lo_k = mid;
-                        else
-                            hi_k = mid;
-                    }
+                while (hi_k - lo_k > 1) {
+                    const int mid = (lo_k + hi_k) >> 1;
+                    if (s_pref[mid] <= j)
+                        lo_k = mid;
+                    else
+                        hi_k = mid;
                 }
-                const uint32_t e = s_lo[lo_k] + (j - s_pref[lo_k]);
-                const uint2 dv = G.ok[k] ? A.da[e] : make_uint2(0, 0);
+                const uint32_t e = G.ok[k] ? s_lo[lo_k] + (j - s_pref[lo_k]) : 0u;
+                const uint2 dv = A.da[e];
                 G.v[k] = dv.x;
                 G.a[k] = dv.y;
                 G.q[k] = s_q[lo_k];
                 G.tw[k] = s_tw[lo_k];
                 G.sd[k] = s_sd[lo_k];
             }
-            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
+            unsigned long long bal[UNR];
+            uint32_t item[UNR];
+            relax_group<SWEEP>(A, G, bal, item, vol_cnt, n_relax);
+            stage_append(S, bal, item);
         }
-        // overflow of the chunk list (not expected with the list sized from
-        // the tuning): per-lane walk, wave-uniform trip count
-        unsigned long long ser_done = 0;
+        // per-lane walk of an overflowed claim, wave-uniform trip count
+        n_edges += ser_len;
+        uint32_t ser_done = 0;
         while (__ballot(ser_done < ser_len)) {
             EdgeGroup G;
 #pragma unroll
             for (int k = 0; k < UNR; ++k) {
                 G.ok[k] = ser_done < ser_len;
-                const uint2 dv = G.ok[k] ? A.da[ser_lo + (uint32_t)ser_done] : make_uint2(0, 0);
+                const uint2 dv = A.da[G.ok[k] ? ser_lo + ser_done : 0u];
                 if (G.ok[k]) ++ser_done;
                 G.v[k] = dv.x;
                 G.a[k] = dv.y;
@@ -345,12 +342,17 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
                 G.tw[k] = tw;
                 G.sd[k] = sd;
             }
-            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
+            unsigned long long bal[UNR];
+            uint32_t item[UNR];
+            relax_group<SWEEP>(A, G, bal, item, vol_cnt, n_relax);
+            stage_append(S, bal, item);
         }
-        if (ser_len && A.stats) atomicAdd(&A.stats[ST_EDGES], (unsigned long long)ser_len);
         __syncthreads();
     }
-    stats_flush(A, n_relax, n_items, ST_EDGES, n_edges);
+    stage_flush_block<SCAP, TB / 64>(S);
+    unsigned long long v[4] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges};
+    const int slot[4] = {ST_RELAX, ST_ATTEMPTS, ST_ITEMS, ST_EDGES};
+    block_stats<TB / 64>(A.stats, v, slot);
 }
 
 // Push round, part 2: every wave takes whole chunks (grid-stride over the
@@ -358,9 +360,10 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
 template <bool SWEEP>
 __global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
 {
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
     const uint32_t r3 = A.round % 3u;
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     unsigned long long n_edges = 0, n_relax = 0;
     const uint32_t lane = threadIdx.x & 63;
@@ -368,32 +371,30 @@ __global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
     for (uint32_t c = blockIdx.x * (TB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
         const uint4 ch = A.chunks[c];
         const uint4 p = A.qp[ch.x];
-        n_edges += ch.z;
+        if (lane == 0) n_edges += ch.z;
         for (uint32_t k0 = 0; k0 < ch.z; k0 += 64 * UNR) {
             EdgeGroup G;
 #pragma unroll
             for (int k = 0; k < UNR; ++k) {
                 const uint32_t off = k0 + k * 64 + lane;
                 G.ok[k] = off < ch.z;
-                const uint2 dv = G.ok[k] ? A.da[ch.y + off] : make_uint2(0, 0);
+                const uint2 dv = A.da[G.ok[k] ? ch.y + off : 0u];
                 G.v[k] = dv.x;
                 G.a[k] = dv.y;
                 G.q[k] = ch.x;
                 G.tw[k] = p.z;
                 G.sd[k] = p.w;
             }
-            relax_group<SWEEP>(A, G, next_cnt, vol_cnt, n_relax);
+            unsigned long long bal[UNR];
+            uint32_t item[UNR];
+            relax_group<SWEEP>(A, G, bal, item, vol_cnt, n_relax);
+            stage_append(S, bal, item);
         }
     }
-    // edges: lane 0 of each wave holds its chunk total
-    unsigned long long blk = 0;
-    if (A.stats) {
-        __shared__ unsigned long long s_e[TB / 64];
-        if (lane == 0) s_e[threadIdx.x >> 6] = n_edges;
-        __syncthreads();
-        for (int w2 = 0; w2 < TB / 64; ++w2) blk += s_e[w2];
-    }
-    stats_flush(A, n_relax, 0, ST_CHUNK_EDGES, blk);
+    stage_flush_block<SCAP, TB / 64>(S);
+    unsigned long long v[3] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_edges};
+    const int slot[3] = {ST_RELAX, ST_ATTEMPTS, ST_CHUNK_EDGES};
+    block_stats<TB / 64>(A.stats, v, slot);
 }
 
 // Small-frontier rounds in one workgroup.  While the frontier holds at most
@@ -424,14 +425,35 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
+    __shared__ uint32_t s_step, s_sdep;
     uint32_t r = A.round;
     uint32_t which = which0;
-    if (tid == 0) s_F = A.cnt[CNT_FRONT + r % 3u];
+    if (tid == 0) {
+        s_F = A.cnt[CNT_FRONT + r % 3u];
+        s_step = A.cnt[CNT_STEP];
+        s_sdep = A.qp[0].w;
+    }
     __syncthreads();
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
     uint32_t rounds = 0;
     uint32_t dummy_vol = 0;
     for (;;) {
+        if (SWEEP && s_F == 0 && s_step < A.nsteps && rounds < max_rounds) {
+            // next departure time of the sweep: the source leaves at s
+            if (tid == 0) {
+                const uint32_t sd = A.steps[s_step];
+                const uint32_t src = A.qp[0].x;
+                ((uint4 *)A.qp)[0].w = sd;
+                atomicMin(&A.arr[src], sd);
+                A.stamp[src] = A.stamp_val + rounds - 1u;  // mark of the coming round's frontier
+                (which ? q1 : q0)[0] = src;
+                s_sdep = sd;
+                s_step += 1;
+                s_F = 1;
+                A.cnt[CNT_FRONT + r % 3u] = 1u;
+            }
+            __syncthreads();
+        }
         const uint32_t F = s_F;
         if (F == 0 || F > limit || rounds >= max_rounds) break;
         {
@@ -469,7 +491,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                 const uint32_t u = item - q * A.n;
                 const uint4 p = A.qp[q];
                 tw = p.z;
-                sd = p.w;
+                sd = SWEEP ? s_sdep : p.w;
                 const size_t su = (size_t)q * A.n + u;
                 const uint32_t ru = __hip_atomic_load(&A.arr[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t b = A.off[u], e = A.off[u + 1];
@@ -501,7 +523,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
             s_pref[tid] = woff + x - len;
             if (tid == 0) s_pref[TT] = total;
             __syncthreads();
-            n_edges += total;
+            if (tid == 0) n_edges += total;
             for (uint32_t j0 = 0; j0 < total; j0 += TT * UNR) {
                 EdgeGroup G;
 #pragma unroll
@@ -509,24 +531,25 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                     const uint32_t j = j0 + k * TT + tid;
                     G.ok[k] = j < total;
                     int lo_k = 0, hi_k = TT;
-                    if (G.ok[k]) {
-                        while (hi_k - lo_k > 1) {
-                            const int mid = (lo_k + hi_k) >> 1;
-                            if (s_pref[mid] <= j)
-                                lo_k = mid;
-                            else
-                                hi_k = mid;
-                        }
+                    while (hi_k - lo_k > 1) {
+                        const int mid = (lo_k + hi_k) >> 1;
+                        if (s_pref[mid] <= j)
+                            lo_k = mid;
+                        else
+                            hi_k = mid;
                     }
-                    const uint32_t e = s_lo[lo_k] + (j - s_pref[lo_k]);
-                    const uint2 dv = G.ok[k] ? A.da[e] : make_uint2(0, 0);
+                    const uint32_t e = G.ok[k] ? s_lo[lo_k] + (j - s_pref[lo_k]) : 0u;
+                    const uint2 dv = A.da[e];
                     G.v[k] = dv.x;
                     G.a[k] = dv.y;
                     G.q[k] = s_q[lo_k];
                     G.tw[k] = s_tw[lo_k];
                     G.sd[k] = s_sd[lo_k];
                 }
-                relax_group<SWEEP>(B, G, &s_next, &dummy_vol, n_relax);
+                unsigned long long bal[UNR];
+                uint32_t item[UNR];
+                relax_group<SWEEP>(B, G, bal, item, &dummy_vol, n_relax);
+                lds_append(B.next, &s_next, bal, item);
             }
             __syncthreads();
         }
@@ -543,12 +566,15 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
         A.cnt[CNT_TAIL_ROUND] = r;
         A.cnt[CNT_TAIL_WHICH] = which;
         A.cnt[CNT_TAIL_ROUNDS] = rounds;
+        A.cnt[CNT_STEP] = s_step;
         // the multi-block kernels of round r expect these zeroed
         A.cnt[CNT_CHUNK + r % 3u] = 0u;
         A.cnt[CNT_FRONT + (r + 1u) % 3u] = 0u;
         A.cnt[CNT_PULLVOL + (r + 1u) % 3u] = 0u;
     }
-    stats_flush(A, n_relax, n_items, ST_TAIL_EDGES, tid == 0 ? n_edges : 0);
+    unsigned long long v[4] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges};
+    const int slot[4] = {ST_RELAX, ST_ATTEMPTS, ST_TAIL_ITEMS, ST_TAIL_EDGES};
+    block_stats<TT / 64>(A.stats, v, slot);
 }
 
 // Dense pull round: every vertex v of every query looks at its in-edges in
@@ -558,7 +584,8 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
 template <bool SWEEP>
 __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
 {
-    uint32_t *next_cnt = &A.cnt[CNT_FRONT + (A.round + 1u) % 3u];
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
@@ -598,25 +625,40 @@ __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
                         }
                         push = true;
                         item = (uint32_t)sv;
+                        A.stamp[sv] = A.stamp_val;  // frontier membership for dense rounds
                         break;
                     }
                 }
             }
         }
-        enqueue(A, push, item, v, next_cnt, vol_cnt);
-    }
-    if (A.stats) {
-        for (int o = 32; o > 0; o >>= 1) {
-            n_edges += __shfl_xor(n_edges, o);
-            n_verts += __shfl_xor(n_verts, o);
-            n_relax += __shfl_xor(n_relax, o);
+        if (A.track_volume) {
+            uint32_t vol = push ? A.off[v + 1] - A.off[v] : 0u;
+            for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o);
+            if ((threadIdx.x & 63) == 0 && vol) atomicAdd(vol_cnt, vol);
         }
-        if ((threadIdx.x & 63) == 0) {
-            if (n_edges) atomicAdd(&A.stats[ST_PULL_EDGES], n_edges);
-            if (n_verts) atomicAdd(&A.stats[ST_PULL_VERTS], n_verts);
-            if (n_relax) atomicAdd(&A.stats[ST_RELAX], n_relax);
-        }
+        const unsigned long long bal[1] = {__ballot(push)};
+        const uint32_t items[1] = {item};
+        stage_append(S, bal, items);
     }
+    stage_flush_block<SCAP, TB / 64>(S);
+    unsigned long long vals[3] = {n_edges, n_verts, n_relax};
+    const int slot[3] = {ST_PULL_EDGES, ST_PULL_VERTS, ST_RELAX};
+    block_stats<TB / 64>(A.stats, vals, slot);
+}
+
+// Start the next departure step of a sweep from the host side of the loop
+// (the one-workgroup kernel does the same by itself).
+__global__ void step_kernel(TravArgs A, uint32_t *queue)
+{
+    const uint32_t idx = A.cnt[CNT_STEP];
+    const uint32_t sd = A.steps[idx];
+    const uint32_t src = A.qp[0].x;
+    ((uint4 *)A.qp)[0].w = sd;
+    atomicMin(&A.arr[src], sd);
+    A.stamp[src] = A.front_stamp;
+    queue[0] = src;
+    A.cnt[CNT_FRONT + A.round % 3u] = 1u;
+    A.cnt[CNT_STEP] = idx + 1u;
 }
 
 // Query start: parameters, source arrival, first frontier, counters.
@@ -628,6 +670,7 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
         ((uint4 *)A.qp)[q] = p;
         const size_t ss = (size_t)q * A.n + p.x;
         A.arr[ss] = src_arrival_from_w ? p.w : p.y;
+        A.stamp[ss] = A.front_stamp;  // a dense first round finds the source
         A.next[q] = (uint32_t)ss;  // `next` names the buffer read by the first round here
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -636,37 +679,52 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
         A.cnt[CNT_CHUNK + A.round % 3u] = 0u;
         A.cnt[CNT_PULLVOL + A.round % 3u] = 0u;
         A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u] = 0u;
+        A.cnt[CNT_STEP] = src_arrival_from_w ? 1u : 0u;  // a sweep starts at its first step
     }
 }
 
-__global__ void finalize_sweep_kernel(uint32_t *out, const uint32_t *l1, const uint32_t *fa, uint32_t n,
+// Results back in caller ids: out[v] for caller vertex v from internal slot
+// perm[v].  kind 0 copies arrivals, 1 turns latest departure + 1 into latest
+// departure, 2 copies fastest durations; the source gets its convention.
+__global__ void finalize_sweep_kernel(uint32_t *out, const uint32_t *__restrict__ arr, const uint32_t *__restrict__ l1,
+                                      const uint32_t *__restrict__ fa, const uint32_t *__restrict__ perm, uint32_t n,
                                       int kind, uint32_t src, uint32_t tw)
 {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t x = perm[v];
         uint32_t r;
-        if (v == src)
+        if (kind == 0)
+            r = arr[x];
+        else if (v == src)
             r = kind == 1 ? tw : 0u;
         else if (kind == 1)
-            r = l1[v] ? l1[v] - 1u : INF;
+            r = l1[x] ? l1[x] - 1u : INF;
         else
-            r = fa[v];
+            r = fa[x];
         out[v] = r;
     }
 }
 
 __global__ void count_traversed_kernel(const uint32_t *__restrict__ a_in, const uint2 *__restrict__ st_in,
-                                       uint64_t m, const uint32_t *__restrict__ ea, uint32_t ta, uint32_t tw,
-                                       unsigned long long *out)
+                                       uint64_t m, const uint32_t *__restrict__ ea, const uint32_t *__restrict__ inv,
+                                       uint32_t ta, uint32_t tw, unsigned long long *out)
 {
+    __shared__ unsigned long long s_c[4];
     unsigned long long c = 0;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (uint64_t)gridDim.x * blockDim.x) {
         const uint2 st = st_in[e];
-        const uint32_t r = ea[st.x];
+        const uint32_t r = ea[inv[st.x]];  // ea is in caller ids
         if (r != INF && st.y >= max(r, ta) && a_in[e] <= tw) ++c;
     }
     for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    // one partial sum per shard, out[blockIdx % ST_SHARDS] (256 threads)
+    if (threadIdx.x == 0) {
+        const unsigned long long t = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (t) atomicAdd(&out[blockIdx.x % ST_SHARDS], t);
+    }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value)
@@ -712,7 +770,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
     A.cnt = s->cnt;
     A.chunks = s->chunks;
     A.chunk_cap = (uint32_t)std::min<uint64_t>(s->chunk_cap, 0xFFFFFFF0u);
-    A.stats = s->stats;
+    A.stats = g->prof.on ? s->stats : nullptr;
     A.split = std::max<uint32_t>(g->tuning.split, 1);
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
     A.nq = nq;
@@ -725,7 +783,7 @@ uint32_t next_stamp(Slot *s, int *rc)
 {
     if (s->stamp_next >= 0xFFFFF000u) {
         *rc = fill(s->stream, s->stamp, (uint64_t)s->qcap * s->n, 0u);
-        s->stamp_next = 1;
+        s->stamp_next = 2;
     }
     return s->stamp_next++;
 }
@@ -748,12 +806,22 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
     int which = 0;  // queue holding the current frontier
     const uint64_t total_v = (uint64_t)A.nq * g->n;
     int rc = KAIROS_OK;
-    while (F > 0) {
+    uint32_t step = (SWEEP && A.steps) ? 1u : 0u;  // host mirror of CNT_STEP
+    for (;;) {
+        if (F == 0) {
+            if (!SWEEP || !A.steps || step >= A.nsteps) break;
+            A.round = r;
+            A.front_stamp = s->stamp_next - 1u;
+            hipLaunchKernelGGL(step_kernel, dim3(1), dim3(1), 0, st, A, s->queue[which]);
+            KAIROS_HIP(hipGetLastError());
+            F = 1;
+            ++step;
+        }
         if (tu.tail_limit && F <= tu.tail_limit && !pulling) {
             constexpr uint32_t kMaxTail = 4096;
             if (s->stamp_next >= 0xFFFFF000u - kMaxTail) {
                 if ((rc = fill(st, s->stamp, (uint64_t)s->qcap * s->n, 0u))) return rc;
-                s->stamp_next = 1;
+                s->stamp_next = 2;
             }
             A.round = r;
             A.stamp_val = s->stamp_next;
@@ -770,11 +838,12 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
             which = (int)s->h_pin[CNT_TAIL_WHICH];
             s->stamp_next += done_rounds;
             F = s->h_pin[CNT_FRONT + r % 3u];
+            step = s->h_pin[CNT_STEP];
             if (g->prof.on) {
                 std::lock_guard<std::mutex> lk(g->prof.mu);
                 g->prof.rounds += done_rounds;
             }
-            if (F == 0) break;
+            if (F == 0) continue;
             if (done_rounds > 0 && F <= tu.tail_limit) continue;  // stopped at max_rounds
             vol = 0;
         }
@@ -796,7 +865,12 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
                                    dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_PULL, ev);
             } else {
-                const int pg = k == 0 ? grid_cap(F, TB, spec_grid) : spec_grid;
+                // dense walk when the frontier is a large share of the vertices
+                A.dense = (A.nq == 1 && tu.dense_frontier && k == 0 &&
+                           (uint64_t)F * tu.dense_frontier >= g->n) ? 1u : 0u;
+                A.front_stamp = A.stamp_val - 1u;
+                const int pg = A.dense ? grid_cap(g->n, TB, spec_grid)
+                                       : (k == 0 ? grid_cap(F, TB, spec_grid) : spec_grid);
                 prof_begin(g, st, &ev);
                 hipLaunchKernelGGL(push_kernel<SWEEP>, dim3(pg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_PUSH, ev);
@@ -848,15 +922,16 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     s->chunks = (uint4 *)dev_alloc(s->chunk_cap * sizeof(uint4), acct);
     s->qp = (uint4 *)dev_alloc((size_t)qcap * sizeof(uint4), acct);
     s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
-    s->stats = (unsigned long long *)dev_alloc(ST_WORDS * 8, acct);
+    s->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, acct);
+    s->arr = (uint32_t *)dev_alloc(qn * 4, acct);
     if (qcap == 1) {
-        s->arr = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->fa = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->l1 = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
+        s->steps = (uint32_t *)dev_alloc((size_t)std::max<uint32_t>(g->max_out_degree, 1) * 4, acct);
     }
     bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt &&
-              s->stats && (qcap != 1 || (s->arr && s->fa && s->l1));
-    if (ok && hipHostMalloc((void **)&s->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
+              s->stats && s->arr && (qcap != 1 || (s->fa && s->l1 && s->steps));
+    if (ok && hipHostMalloc((void **)&s->h_pin, 1024, hipHostMallocDefault) != hipSuccess) {
         s->h_pin = nullptr;
         ok = false;
     }
@@ -872,7 +947,7 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     if (ok) {
         ok = hipMemsetAsync(s->stamp, 0, qn * 4, s->stream) == hipSuccess &&
              hipMemsetAsync(s->cnt, 0, CNT_WORDS * 4, s->stream) == hipSuccess &&
-             hipMemsetAsync(s->stats, 0, ST_WORDS * 8, s->stream) == hipSuccess &&
+             hipMemsetAsync(s->stats, 0, ST_TOTAL_WORDS * 8, s->stream) == hipSuccess &&
              hipStreamSynchronize(s->stream) == hipSuccess;
     }
     if (!ok) {
@@ -886,10 +961,12 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
 int read_stats(kairos_graph *g, Slot *s)
 {
     if (!g->prof.on) return KAIROS_OK;
+    std::vector<unsigned long long> raw((size_t)ST_SHARDS * ST_WORDS);
     unsigned long long h[ST_WORDS];
-    KAIROS_HIP(hipMemcpyAsync(h, s->stats, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    KAIROS_HIP(hipMemcpyAsync(raw.data(), s->stats, raw.size() * 8, hipMemcpyDeviceToHost, s->stream));
     KAIROS_HIP(hipStreamSynchronize(s->stream));
-    KAIROS_HIP(hipMemsetAsync(s->stats, 0, sizeof(h), s->stream));
+    KAIROS_HIP(hipMemsetAsync(s->stats, 0, raw.size() * 8, s->stream));
+    stats_sum_shards(raw.data(), h);
     prof_add_stats(g, h);
     return KAIROS_OK;
 }
@@ -960,6 +1037,7 @@ void slot_destroy(Slot *s)
     dev_free(s->arr);
     dev_free(s->fa);
     dev_free(s->l1);
+    dev_free(s->steps);
     if (s->h_pin) hipHostFree(s->h_pin);
     if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
     delete s;
@@ -1001,6 +1079,7 @@ static int start_queries(kairos_graph *g, Slot *s, uint32_t *arr, const uint4 *h
     round = 0;
     A.round = 0;
     A.next = s->queue[0];
+    A.front_stamp = s->stamp_next - 1u;
     // parameters travel through the pinned mirror (256 B) or a staging copy
     uint4 *dq = nullptr;
     uint4 *staging = nullptr;
@@ -1036,14 +1115,19 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
     int rc;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
-    if ((rc = fill(st, out, g->n, INF))) return rc;
+    if ((rc = fill(st, s->arr, g->n, INF))) return rc;
     if ((rc = fill(st, s->done, g->n, INF))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
-    const uint4 qp = make_uint4(src, ta, tw, ta);
+    const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, out, &qp, 1, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, s->arr, &qp, 1, false, A, round))) return rc;
     if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->arr,
+                       s->l1, s->fa, g->perm, g->n, 0, src, tw);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
     return read_stats(g, s);
 }
 
@@ -1055,15 +1139,22 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
     const uint64_t qn = (uint64_t)q * g->n;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
-    if ((rc = fill(st, out, qn, INF))) return rc;
+    if ((rc = fill(st, s->arr, qn, INF))) return rc;
     if ((rc = fill(st, s->done, qn, INF))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
     std::vector<uint4> hq(q);
-    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(src[i], ta[i], tw[i], ta[i]);
+    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], ta[i]);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, out, hq.data(), q, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, s->arr, hq.data(), q, false, A, round))) return rc;
     if ((rc = run_rounds<false>(g, s, A, q, &round))) return rc;
+    prof_begin(g, st, &ev);
+    for (uint32_t i = 0; i < q; ++i)
+        hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st,
+                           out + (size_t)i * g->n, s->arr + (size_t)i * g->n, s->l1, s->fa, g->perm, g->n, 0,
+                           src[i], tw[i]);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
     return read_stats(g, s);
 }
 
@@ -1076,10 +1167,11 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
 // at their fixpoint), so each improvement updates
 //   F[v] = min(F[v], a - s)   and   L1[v] = max(L1[v], s + 1),
 // the latter giving LD[v] = L1[v] - 1, with 0 meaning unreachable.
-int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t ta, uint32_t tw, uint32_t *out)
 {
     hipStream_t st = s->stream;
     int rc;
+    const uint32_t src = g->h_perm[src_caller];
     uint32_t hoff[2];
     KAIROS_HIP(hipMemcpyAsync(s->h_pin, g->off_out + src, 8, hipMemcpyDeviceToHost, st));
     KAIROS_HIP(hipStreamSynchronize(st));
@@ -1099,9 +1191,8 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uin
     S.erase(std::unique(S.begin(), S.end()), S.end());
     std::reverse(S.begin(), S.end());
 
-    // out doubles as L1 (latest departure) or F (fastest)
-    uint32_t *l1 = kind == 1 ? out : s->l1;
-    uint32_t *fa = kind == 2 ? out : s->fa;
+    uint32_t *l1 = s->l1;
+    uint32_t *fa = s->fa;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
     if ((rc = fill(st, s->arr, g->n, INF))) return rc;
@@ -1109,23 +1200,21 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uin
     if ((rc = fill(st, fa, g->n, INF))) return rc;
     if ((rc = fill(st, l1, g->n, 0u))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
-    uint32_t round = 0;
-    for (uint32_t sd : S) {
-        const uint4 qp = make_uint4(src, ta, tw, sd);
+    if (!S.empty()) {
+        KAIROS_HIP(hipMemcpy(s->steps, S.data(), S.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        const uint4 qp = make_uint4(src, ta, tw, S[0]);
         TravArgs A;
-        uint32_t r0;
-        if ((rc = start_queries(g, s, s->arr, &qp, 1, true, A, r0))) return rc;
+        uint32_t r = 0;
+        if ((rc = start_queries(g, s, s->arr, &qp, 1, true, A, r))) return rc;
         A.fa = fa;
         A.l1 = l1;
-        // continue the global round numbering so counters rotate consistently
-        (void)r0;
-        uint32_t r = 0;
+        A.steps = s->steps;
+        A.nsteps = (uint32_t)S.size();
         if ((rc = run_rounds<true>(g, s, A, 1, &r))) return rc;
-        round += r;
     }
     prof_begin(g, st, &ev);
-    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out,
-                       l1, fa, g->n, kind, src, tw);
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->arr,
+                       l1, fa, g->perm, g->n, kind, src_caller, tw);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
     KAIROS_HIP(hipStreamSynchronize(st));
@@ -1138,20 +1227,24 @@ int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *e
     int rc = slot_acquire(g, 1, false, &s);
     if (rc) return rc;
     hipStream_t st = s->stream;
-    unsigned long long *d = s->stats + ST_WORDS - 1;
+    unsigned long long *d = s->stats + (size_t)ST_SHARDS * ST_WORDS;  // ST_SHARDS partial sums
     do {
-        if (hipMemsetAsync(d, 0, 8, st) != hipSuccess) { rc = KAIROS_ERR_DEVICE; break; }
+        if (hipMemsetAsync(d, 0, ST_SHARDS * 8, st) != hipSuccess) { rc = KAIROS_ERR_DEVICE; break; }
         if (g->m)
             hipLaunchKernelGGL(count_traversed_kernel, dim3(grid_cap(g->m, 256 * 8, 16384)), dim3(256), 0,
-                               st, g->a_in, g->st_in, g->m, ea, ta, tw, d);
+                               st, g->a_in, g->st_in, g->m, ea, g->inv, ta, tw, d);
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(s->h_pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(s->h_pin, d, ST_SHARDS * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             rc = KAIROS_ERR_DEVICE;
             break;
         }
-        uint64_t v;
-        std::memcpy(&v, s->h_pin, 8);
+        uint64_t v = 0;
+        for (int k = 0; k < ST_SHARDS; ++k) {
+            uint64_t x;
+            std::memcpy(&x, (const char *)s->h_pin + 8 * k, 8);
+            v += x;
+        }
         *count = v;
     } while (0);
     slot_release(g, s);
@@ -1171,6 +1264,7 @@ kairos_tuning default_tuning(const kairos_graph *)
     t.sweep_group = 1;
     t.batch_layout = 2;
     t.tail_limit = 4096;
+    t.dense_frontier = 0;
     return t;
 }
 
@@ -1223,7 +1317,7 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.qflag = ms->cnt + CNT_WORDS;
     A.chunks = ms->chunks;
     A.chunk_cap = (uint32_t)std::min<uint64_t>(ms->chunk_cap, 0xFFFFFFF0u);
-    A.stats = ms->stats;
+    A.stats = g->prof.on ? ms->stats : nullptr;
     A.split = std::max<uint32_t>(g->tuning.split, 1);
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
     A.nq = ms->qcap;
@@ -1242,7 +1336,7 @@ int multi_push_round(kairos_graph *g, MultiState *ms)
     if (ms->stamp_next >= 0xFFFFF000u) {
         int rc = fill(ms->stream, ms->stamp, (uint64_t)ms->qcap * ms->n, 0u);
         if (rc) return rc;
-        ms->stamp_next = 1;
+        ms->stamp_next = 2;
     }
     A.stamp_val = ms->stamp_next++;
     hipEvent_t ev;
@@ -1283,12 +1377,8 @@ int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32
                    uint32_t *out)
 {
     const size_t base = (size_t)q * g->n;
-    if (kind == 0) {
-        KAIROS_HIP(hipMemcpyAsync(out, ms->arr + base, (size_t)g->n * 4, hipMemcpyDeviceToDevice, ms->stream));
-        return KAIROS_OK;
-    }
     hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, ms->stream, out,
-                       ms->l1 + base, ms->fa + base, g->n, kind, src, tw);
+                       ms->arr + base, ms->l1 + base, ms->fa + base, g->perm, g->n, kind, src, tw);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;
 }

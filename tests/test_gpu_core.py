@@ -64,8 +64,14 @@ def print_case(*a):
 def test_index_matches_lexsort(which):
     g, G, _ = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
     print_case("index", which, g.n, g.m)
-    want = O.temporal_csr(g.n, g.src, g.dst, g.t, g.lam)
     ix = {k: K.as_u32(v) for k, v in K.kairos_graph_index(G).items()}
+    # internal ids: decreasing in-degree, ties by caller id
+    perm = ix["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(g.n, dtype=np.uint32))
+    indeg = np.bincount(g.dst, minlength=g.n)
+    order = np.lexsort((np.arange(g.n), -indeg))
+    assert np.array_equal(perm[order], np.arange(g.n, dtype=np.uint32))
+    want = O.temporal_csr(g.n, perm[g.src], perm[g.dst], g.t, g.lam)
     assert np.array_equal(ix["off_out"], want["off_out"].astype(np.uint32))
     assert np.array_equal(ix["off_in"], want["off_in"].astype(np.uint32))
     assert np.array_equal(ix["t_out"], want["t_out"])
@@ -298,3 +304,44 @@ def test_chunk_list_overflow_paths():
         G.free()
     finally:
         del os.environ["KAIROS_TEST_CHUNK_CAP"]
+
+
+def test_autotune_keeps_results():
+    g, G, se = rmat16()
+    srcs, ta, tw = make_queries("rmat20-32m", g, count=8)
+    old = K.kairos_get_tuning(G)
+    try:
+        best = K.kairos_autotune(G, srcs, ta, tw)
+        assert best == K.kairos_get_tuning(G)
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        rows = K.as_u32(out).reshape(len(srcs), g.n)
+        for q in range(len(srcs)):
+            assert np.array_equal(rows[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+        assert np.array_equal(ea_gpu(G, int(srcs[0]), int(ta[0]), int(tw[0])),
+                              O.earliest_arrival(se, srcs[0], ta[0], tw[0]))
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("dense", [0, 1, 4, 1000000])
+def test_dense_frontier_walk(dense):
+    """Dense rounds (every vertex walked, members found by their stamp) give
+    the same bits as queue rounds, also right after pull rounds."""
+    g, G, se = rmat16()
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, dense_frontier=dense, tail_limit=0 if dense == 1000000 else 4096)
+        srcs, ta, tw = make_queries("rmat20-32m", g, count=3)
+        for q in range(len(srcs)):
+            assert np.array_equal(ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q])),
+                                  O.earliest_arrival(se, srcs[q], ta[q], tw[q]))
+        K.kairos_set_tuning(G, pull_alpha=8)
+        assert np.array_equal(ea_gpu(G, int(srcs[0]), int(ta[0]), int(tw[0])),
+                              O.earliest_arrival(se, srcs[0], ta[0], tw[0]))
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        pea, pld, pf = O.profile(se, srcs[1], ta[1], tw[1])
+        K.kairos_latest_departure(G, int(srcs[1]), int(ta[1]), int(tw[1]), out)
+        assert np.array_equal(K.as_u32(out), pld)
+    finally:
+        K.kairos_set_tuning(G, **old)
