@@ -159,6 +159,9 @@ typedef struct kairos_tuning {
     uint32_t dense_frontier; /* single queries: a frontier of at least
                                 n / dense_frontier vertices is expanded by
                                 walking all vertices in id order; 0 disables     */
+    uint32_t arrival_filter; /* 1: a one-byte-per-vertex upper bound of each
+                                arrival rejects edges that cannot improve their
+                                head before the arrival itself is read; 0 off   */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);

@@ -47,7 +47,8 @@ struct Slot {
     uint4 *chunks = nullptr;     // split adjacency ranges {q, start, len, _}
     uint64_t chunk_cap = 0;
     uint4 *qp = nullptr;         // qcap: {src, t_alpha, t_omega, sweep departure}
-    uint32_t *arr = nullptr;     // n: arrival scratch for the sweep queries
+    uint32_t *arr = nullptr;     // qcap*n: arrivals
+    uint8_t *filt = nullptr;     // qcap*n (rounded up to 4): bucketed upper bound of arr, 255 = none
     uint32_t *fa = nullptr;      // n: fastest duration (sweep)
     uint32_t *l1 = nullptr;      // n: latest departure + 1 (sweep), 0 = none
     uint32_t *steps = nullptr;   // sweep departure times, descending (max out-degree)
@@ -119,6 +120,9 @@ struct kairos_graph {
     std::vector<uint32_t> h_perm; // host copy of perm
     uint32_t max_out_degree = 0;
     uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
+    uint32_t max_a = 0;           // largest arrival time
+    uint32_t fshift = 0;          // arrival filter: bucket width 2^fshift, ceil(max_a / 2^fshift) <= 254
+                                  // (up to 25, so bound * width needs 64 bits)
     uint64_t index_bytes = 0;
     hipStream_t stream = nullptr; // caller's stream, or nullptr
     int device = 0;
@@ -161,6 +165,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
 struct MultiState {
     uint32_t qcap = 0, n = 0;
     uint32_t *arr = nullptr, *done = nullptr, *stamp = nullptr, *fa = nullptr, *l1 = nullptr;
+    uint8_t *filt = nullptr;                  // qcap*n bucketed arrival bounds (see Slot)
     uint32_t *queue[2] = {nullptr, nullptr};  // queue[0] feeds the next round
     uint32_t *cnt = nullptr;                  // CNT_WORDS counters, then qcap activity flags
     uint4 *chunks = nullptr, *qp = nullptr;

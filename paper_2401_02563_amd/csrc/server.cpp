@@ -77,7 +77,7 @@ size_t pin_words(uint32_t max_slots)
 
 uint64_t slot_bytes(kairos_server *s)
 {
-    return (uint64_t)s->g->n * 4 * 7 + s->per_slot_chunks * sizeof(uint4) + sizeof(uint4) + 4;
+    return (uint64_t)s->g->n * (4 * 7 + 1) + s->per_slot_chunks * sizeof(uint4) + sizeof(uint4) + 4;
 }
 
 bool free_bytes_ok(kairos_server *s, uint64_t need)
@@ -94,6 +94,7 @@ bool free_bytes_ok(kairos_server *s, uint64_t need)
 void free_state(MultiState &m)
 {
     dev_free(m.arr);
+    dev_free(m.filt);
     dev_free(m.done);
     dev_free(m.stamp);
     dev_free(m.fa);
@@ -124,6 +125,7 @@ bool grow(kairos_server *s, uint32_t ncap)
     nm.stream = s->ms.stream;
     nm.chunk_cap = s->per_slot_chunks * ncap;
     nm.arr = (uint32_t *)dev_alloc(qn * 4, nullptr);
+    nm.filt = (uint8_t *)dev_alloc((qn + 3) / 4 * 4, nullptr);
     nm.done = (uint32_t *)dev_alloc(qn * 4, nullptr);
     nm.stamp = (uint32_t *)dev_alloc(qn * 4, nullptr);
     nm.fa = (uint32_t *)dev_alloc(qn * 4, nullptr);
@@ -135,7 +137,7 @@ bool grow(kairos_server *s, uint32_t ncap)
     nm.qp = (uint4 *)dev_alloc((size_t)ncap * sizeof(uint4), nullptr);
     nm.stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, nullptr);
     hipStream_t st = s->ms.stream;
-    bool ok = nm.arr && nm.done && nm.stamp && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
+    bool ok = nm.arr && nm.filt && nm.done && nm.stamp && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
               nm.chunks && nm.qp && nm.stats;
     ok = ok && hipMemsetAsync(nm.stamp, 0, qn * 4, st) == hipSuccess &&
          hipMemsetAsync(nm.cnt, 0, (CNT_WORDS + (size_t)ncap) * 4, st) == hipSuccess &&
@@ -143,6 +145,7 @@ bool grow(kairos_server *s, uint32_t ncap)
     if (ok && s->cap) {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
         ok = hipMemcpyAsync(nm.arr, s->ms.arr, on * 4, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.filt, s->ms.filt, on, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.done, s->ms.done, on * 4, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.stamp, s->ms.stamp, on * 4, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.fa, s->ms.fa, on * 4, k, st) == hipSuccess &&

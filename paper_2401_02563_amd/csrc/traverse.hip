@@ -77,6 +77,8 @@ struct TravArgs {
     uint32_t nsteps;
     uint32_t dense;          // 1: walk all vertices, members have stamp == front_stamp
     uint32_t front_stamp;    // stamp value that marked the current frontier
+    uint8_t *filt;           // bucketed upper bounds of arr (null: no filter)
+    uint32_t fshift;         // bucket width 2^fshift
 };
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t lo,
@@ -121,8 +123,20 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
     for (int k = 0; k < UNR; ++k) {
         G.ok[k] = G.ok[k] && G.a[k] <= G.tw[k];
         sv[k] = (size_t)G.q[k] * A.n + G.v[k];
-        G.cur[k] = A.arr[G.ok[k] ? sv[k] : 0];
     }
+    if (A.filt) {
+        // filt[v] = f promises arr[v] <= f * 2^fshift (f = 255: no promise),
+        // so an edge arriving at or after that bound cannot improve v; the
+        // filter is a quarter of arr's size and stays in cache far better
+        uint32_t f[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) f[k] = A.filt[G.ok[k] ? sv[k] : 0];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k)  // the bound can exceed 32 bits (fshift up to 25)
+            G.ok[k] = G.ok[k] && (f[k] == 255u || (uint64_t)G.a[k] < ((uint64_t)f[k] << A.fshift));
+    }
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) G.cur[k] = A.arr[G.ok[k] ? sv[k] : 0];
     uint32_t old[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
@@ -136,6 +150,14 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         G.ok[k] = G.ok[k] && G.a[k] < old[k];
         nrelax += G.ok[k] ? 1ull : 0ull;
         if (G.ok[k]) st[k] = atomicExch(&A.stamp[sv[k]], A.stamp_val);
+    }
+    if (A.filt) {
+        // a plain byte store: a racing store of a later improvement's bound
+        // may win, which leaves a looser (still valid) bound
+#pragma unroll
+        for (int k = 0; k < UNR; ++k)
+            if (G.ok[k])
+                A.filt[sv[k]] = (uint8_t)(((uint64_t)G.a[k] + (1ull << A.fshift) - 1ull) >> A.fshift);
     }
     if (SWEEP) {
 #pragma unroll
@@ -751,6 +773,14 @@ int fill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t value)
     return KAIROS_OK;
 }
 
+// Arrival filter of `count` vertices: every byte 255 (no bound yet).  Done
+// whether or not the filter is switched on, so switching it on between
+// queries never exposes bounds of an earlier query.
+int fill_filter(kairos_graph *, hipStream_t st, uint8_t *filt, uint64_t count)
+{
+    return fill(st, (uint32_t *)filt, (count + 3) / 4, 0xFFFFFFFFu);
+}
+
 TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
 {
     TravArgs A{};
@@ -776,6 +806,8 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
     A.nq = nq;
     A.track_volume = g->tuning.pull_alpha ? 1u : 0u;
     A.max_t = g->max_t;
+    A.filt = g->tuning.arrival_filter ? s->filt : nullptr;
+    A.fshift = g->fshift;
     return A;
 }
 
@@ -924,13 +956,14 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
     s->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, acct);
     s->arr = (uint32_t *)dev_alloc(qn * 4, acct);
+    s->filt = (uint8_t *)dev_alloc((qn + 3) / 4 * 4, acct);
     if (qcap == 1) {
         s->fa = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->l1 = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->steps = (uint32_t *)dev_alloc((size_t)std::max<uint32_t>(g->max_out_degree, 1) * 4, acct);
     }
     bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt &&
-              s->stats && s->arr && (qcap != 1 || (s->fa && s->l1 && s->steps));
+              s->stats && s->arr && s->filt && (qcap != 1 || (s->fa && s->l1 && s->steps));
     if (ok && hipHostMalloc((void **)&s->h_pin, 1024, hipHostMallocDefault) != hipSuccess) {
         s->h_pin = nullptr;
         ok = false;
@@ -1035,6 +1068,7 @@ void slot_destroy(Slot *s)
     dev_free(s->cnt);
     dev_free(s->stats);
     dev_free(s->arr);
+    dev_free(s->filt);
     dev_free(s->fa);
     dev_free(s->l1);
     dev_free(s->steps);
@@ -1117,6 +1151,7 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
     prof_begin(g, st, &ev);
     if ((rc = fill(st, s->arr, g->n, INF))) return rc;
     if ((rc = fill(st, s->done, g->n, INF))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, g->n))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
     const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
     TravArgs A;
@@ -1141,6 +1176,7 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
     prof_begin(g, st, &ev);
     if ((rc = fill(st, s->arr, qn, INF))) return rc;
     if ((rc = fill(st, s->done, qn, INF))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, qn))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
     std::vector<uint4> hq(q);
     for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], ta[i]);
@@ -1197,6 +1233,7 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
     prof_begin(g, st, &ev);
     if ((rc = fill(st, s->arr, g->n, INF))) return rc;
     if ((rc = fill(st, s->done, g->n, INF))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, g->n))) return rc;
     if ((rc = fill(st, fa, g->n, INF))) return rc;
     if ((rc = fill(st, l1, g->n, 0u))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
@@ -1251,7 +1288,7 @@ int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *e
     return rc;
 }
 
-kairos_tuning default_tuning(const kairos_graph *)
+kairos_tuning default_tuning(const kairos_graph *g)
 {
     kairos_tuning t{};
     t.block = 256;
@@ -1265,6 +1302,9 @@ kairos_tuning default_tuning(const kairos_graph *)
     t.batch_layout = 2;
     t.tail_limit = 4096;
     t.dense_frontier = 0;
+    // the filter pays while its n bytes stay in a 4 MB L2; beyond that the
+    // extra random read costs more than the arrival reads it saves
+    t.arrival_filter = g && g->n <= (1u << 21) ? 1u : 0u;
     return t;
 }
 
@@ -1285,8 +1325,9 @@ __global__ void inject_kernel(TravArgs A, const Inject *__restrict__ list, uint3
 }
 
 // Fresh state for the listed slots: arrival, claims and fastest = INF,
-// latest departure + 1 = 0.  Block (x, y): slot list[y], stride over n.
-__global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list)
+// latest departure + 1 = 0, no arrival bound.  Block (x, y): slot list[y],
+// stride over n.
+__global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list, uint8_t *filt)
 {
     const size_t base = (size_t)list[blockIdx.y] * A.n;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.n; v += gridDim.x * blockDim.x) {
@@ -1294,6 +1335,7 @@ __global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list)
         A.done[base + v] = INF;
         A.fa[base + v] = INF;
         A.l1[base + v] = 0u;
+        filt[base + v] = 255u;
     }
 }
 
@@ -1325,6 +1367,8 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.cur = ms->queue[0];
     A.next = ms->queue[1];
     A.max_t = g->max_t;
+    A.filt = g->tuning.arrival_filter ? ms->filt : nullptr;
+    A.fshift = g->fshift;
     return A;
 }
 
@@ -1368,7 +1412,7 @@ int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinne
     if (!count) return KAIROS_OK;
     TravArgs A = multi_args(g, ms);
     hipLaunchKernelGGL(init_slots_kernel, dim3(grid_cap(g->n, 256 * 4, 256), count), dim3(256), 0,
-                       ms->stream, A, host_pinned);
+                       ms->stream, A, host_pinned, ms->filt);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;
 }

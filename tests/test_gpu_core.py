@@ -109,7 +109,8 @@ def test_ea_skewed(which):
 
 @pytest.mark.parametrize("tuning", [dict(split=64, chunk=64), dict(split=100000, chunk=4096),
                                     dict(rounds_per_sync=4), dict(pull_alpha=1, pull_beta=1000000),
-                                    dict(pull_alpha=8, pull_beta=24)])
+                                    dict(pull_alpha=8, pull_beta=24), dict(arrival_filter=0),
+                                    dict(arrival_filter=0, tail_limit=0)])
 def test_ea_independent_of_tuning(tuning):
     """Results are unique, so every launch configuration must agree bit for bit."""
     g, G, se = rmat16()
@@ -159,6 +160,36 @@ def test_tiny_all_kinds(seed):
         assert np.array_equal(K.as_u32(out), pld)
         K.kairos_fastest(G, s, ta, tw, out)
         assert np.array_equal(K.as_u32(out), pf)
+    G.free()
+
+
+@pytest.mark.parametrize("filt", [0, 1])
+def test_late_timestamps_all_kinds(filt):
+    """Departures near the top of the u32 range: the arrival filter then uses
+    its widest buckets (2^24), where a bound times the bucket width comes
+    closest to overflowing."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    n, m = 300, 4000
+    src = rng.integers(0, n, m, dtype=np.uint32)
+    dst = rng.integers(0, n, m, dtype=np.uint32)
+    t = rng.integers(0xFFFFFFFE - (1 << 26), 0xFFFFFFFE - 200, m, dtype=np.uint64).astype(np.uint32)
+    lam = rng.integers(1, 150, m, dtype=np.uint32)
+    g = Graph(n, src, dst, t, lam, dict(kind="late"))
+    G = K.kairos_graph_build(*dev(g), g.n)
+    K.kairos_set_tuning(G, arrival_filter=filt, tail_limit=0 if filt else 4096)
+    se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    lo = int(t.min())
+    for s in range(0, n, 37):
+        for ta, tw in ((0, 0xFFFFFFFE), (lo + (1 << 24), 0xFFFFFFFE - (1 << 20))):
+            print_case("late", filt, s, ta, tw)
+            pea, pld, pf = O.profile(se, s, ta, tw)
+            K.kairos_earliest_arrival(G, s, ta, tw, out)
+            assert np.array_equal(K.as_u32(out), pea), (s, ta, tw)
+            K.kairos_latest_departure(G, s, ta, tw, out)
+            assert np.array_equal(K.as_u32(out), pld), (s, ta, tw)
+            K.kairos_fastest(G, s, ta, tw, out)
+            assert np.array_equal(K.as_u32(out), pf), (s, ta, tw)
     G.free()
 
 
