@@ -144,7 +144,10 @@ typedef struct kairos_tuning {
     uint32_t pull_beta;      /* back to push when frontier < n / pull_beta          */
     uint32_t rounds_per_sync;/* push rounds queued before the host checks the
                                 frontier (1 = check every round)                    */
-    uint32_t batch_persistent; /* 1: batched queries run in one persistent launch  */
+    uint32_t batch_persistent; /* 1: a lane-dense batch (batch_layout 2) runs all
+                                  its rounds in one cooperative launch with grid
+                                  barriers and stops on the device; 0: one
+                                  launch per phase and a host check per round   */
     uint32_t sweep_group;    /* departure times handled together by the
                                 latest-departure / fastest sweep                     */
     uint32_t batch_layout;   /* 0: one wavefront per frontier vertex, one lane per

@@ -302,7 +302,10 @@ __device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, uns
     stage_append(S, bal, head);
 }
 
-__global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
+// Expansion of one round's F frontier entries by the whole grid (every
+// block calls this; it contains block barriers).  Heads found go to S.
+__device__ __forceinline__ void hpush_phase(const BArgs &A, uint32_t F, BStage &S, unsigned long long &n_edges,
+                                            unsigned long long &n_relax, unsigned long long &n_items)
 {
     __shared__ uint32_t s_ent[BTB];
     __shared__ unsigned long long s_mask[BTB];
@@ -312,20 +315,16 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
     __shared__ uint32_t s_wsum[BTB / 64];
     __shared__ uint32_t s_csum[BTB / 64];
     __shared__ uint32_t s_cb;
-    __shared__ uint32_t s_stage[BTB / 64][SCAP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
     const uint32_t r3 = A.round % 3u;
-    const uint32_t F = A.cnt[CNT_FRONT + r3];
     if (blockIdx.x == 0 && tid == 0) {
         A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
         A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
     }
-    BStage S{s_stage[w], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
-    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
 
     for (uint32_t base = blockIdx.x * BTB; base < F; base += gridDim.x * BTB) {
         // entries of this block and their query counts
@@ -479,6 +478,14 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
             __syncthreads();
         }
     }
+}
+
+__global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
+{
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
+    BStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+    hpush_phase(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
     stage_flush_block<SCAP, BTB / 64>(S);
     unsigned long long v[3] = {n_relax, n_items, n_edges};
     const int slot[3] = {ST_RELAX, ST_ITEMS, ST_EDGES};
@@ -487,13 +494,12 @@ __global__ __launch_bounds__(BTB) void hpush_kernel(BArgs A)
 
 // Chunks of the lane-dense variant: {entry, query bit, start, len}; one
 // wavefront per chunk, HU edges per lane in flight, every lane active.
-__global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
+// The chunks of round A.round, one wavefront per chunk, grid-stride.
+__device__ __forceinline__ void hchunk_phase(const BArgs &A, BStage &S, unsigned long long &n_edges,
+                                             unsigned long long &n_relax)
 {
-    __shared__ uint32_t s_stage[BTB / 64][SCAP];
     const uint32_t r3 = A.round % 3u;
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
-    BStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
-    unsigned long long n_edges = 0, n_relax = 0;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (BTB / 64);
     for (uint32_t c = blockIdx.x * (BTB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
@@ -517,9 +523,69 @@ __global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
             hrelax(A, H, S, n_relax);
         }
     }
+}
+
+__global__ __launch_bounds__(BTB) void hchunk_kernel(BArgs A)
+{
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
+    BStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
+    unsigned long long n_edges = 0, n_relax = 0;
+    hchunk_phase(A, S, n_edges, n_relax);
     stage_flush_block<SCAP, BTB / 64>(S);
     unsigned long long v[2] = {n_relax, n_edges};
     const int slot[2] = {ST_RELAX, ST_CHUNK_EDGES};
+    block_stats<BTB / 64>(A.stats, v, slot);
+}
+
+// All rounds of a lane-dense batch in one cooperative launch: push phase,
+// grid barrier, chunk phase, grid barrier, then every block reads the next
+// frontier size from the same word and stops together when it is zero (or
+// after max_rounds, or when a barrier wait gave up; the host reports both as
+// errors).  Queues and masks alternate by round parity as in the per-round
+// launches.
+enum : int { BCNT_ROUNDS = 13, BCNT_CAPPED = 14 };
+
+__global__ __launch_bounds__(BTB) void hpersist_kernel(BArgs A, uint32_t *q0, uint32_t *q1, unsigned long long *m0,
+                                                       unsigned long long *m1, uint32_t *bar, uint32_t max_rounds,
+                                                       uint32_t spin_limit)
+{
+    __shared__ uint32_t s_stage[BTB / 64][SCAP];
+    __shared__ uint32_t s_F;
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0, n_cedges = 0, n_crelax = 0;
+    uint32_t r = A.round;
+    for (;;) {
+        // the abort word is sampled into the same LDS word: either every
+        // block sees it raised before this round, or every block reaches the
+        // next barrier, whose waits then all end
+        if (threadIdx.x == 0)
+            s_F = grid_aborted(bar) ? 0u
+                                    : __hip_atomic_load(&A.cnt[CNT_FRONT + r % 3u], __ATOMIC_ACQUIRE,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t F = s_F;
+        __syncthreads();
+        if (F == 0 || r - A.round >= max_rounds) break;
+        BArgs B = A;
+        B.round = r;
+        B.cur = (r & 1u) ? q1 : q0;
+        B.next = (r & 1u) ? q0 : q1;
+        B.mask_cur = (r & 1u) ? m1 : m0;
+        B.mask_next = (r & 1u) ? m0 : m1;
+        BStage S{s_stage[threadIdx.x >> 6], 0u, B.next, &A.cnt[CNT_FRONT + (r + 1u) % 3u]};
+        hpush_phase(B, F, S, n_edges, n_relax, n_items);
+        stage_flush_block<SCAP, BTB / 64>(S);
+        grid_barrier(bar, spin_limit);
+        hchunk_phase(B, S, n_cedges, n_crelax);
+        stage_flush_block<SCAP, BTB / 64>(S);
+        grid_barrier(bar, spin_limit);
+        ++r;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.cnt[BCNT_ROUNDS] = r - A.round;
+        A.cnt[BCNT_CAPPED] = (r - A.round >= max_rounds || grid_aborted(bar)) ? 1u : 0u;
+    }
+    unsigned long long v[5] = {n_relax + n_crelax, n_items, n_edges, n_cedges, 0ull};
+    const int slot[5] = {ST_RELAX, ST_ITEMS, ST_EDGES, ST_CHUNK_EDGES, ST_ATTEMPTS};
     block_stats<BTB / 64>(A.stats, v, slot);
 }
 
@@ -593,6 +659,7 @@ struct VBatch {
     uint2 *ranges = nullptr;
     uint64_t chunk_cap = 0, range_cap = 0;
     unsigned long long *stats = nullptr;
+    uint32_t *bar = nullptr;  // grid barrier words of the persistent launch
     uint32_t *h_pin = nullptr;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -613,6 +680,7 @@ void vbatch_destroy(VBatch *b)
     dev_free(b->chunks);
     dev_free(b->ranges);
     dev_free(b->stats);
+    dev_free(b->bar);
     if (b->h_pin) hipHostFree(b->h_pin);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
     delete b;
@@ -646,8 +714,9 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
     b->chunks = (uint4 *)dev_alloc(std::max<uint64_t>(b->chunk_cap, 1) * sizeof(uint4), nullptr);
     b->ranges = (uint2 *)dev_alloc(std::max<uint64_t>(b->range_cap, 1) * 64 * sizeof(uint2), nullptr);
     b->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, nullptr);
+    b->bar = (uint32_t *)dev_alloc(BAR_WORDS * 4, nullptr);
     bool ok = b->arr && b->done && b->queue[0] && b->queue[1] && b->cnt && b->mask[0] && b->mask[1] && b->qw &&
-              b->chunks && b->ranges && b->stats;
+              b->chunks && b->ranges && b->stats && b->bar;
     if (ok && hipHostMalloc((void **)&b->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
         b->h_pin = nullptr;
         ok = false;
@@ -678,6 +747,44 @@ static int bfill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t v)
 {
     hipLaunchKernelGGL(bfill_kernel, dim3(gridc(count, 256 * 8, 16384)), dim3(256), 0, st, p, count, v);
     KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// Runs every round of a lane-dense batch whose first frontier is in place in
+// one cooperative launch.  Returns KAIROS_ERR_BUSY when the runtime refuses
+// the launch (nothing ran; state unchanged).
+static int run_persistent(kairos_graph *g, VBatch *b, BArgs A, hipStream_t st)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, hpersist_kernel, BTB, 0) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    const int grid = g->num_cus * std::min(occ, 4);
+    constexpr uint32_t kMaxRounds = 1u << 22;  // far beyond any batch; a stop for the loop, reported as an error
+    KAIROS_HIP(hipMemsetAsync(b->bar, 0, BAR_WORDS * 4, st));
+    A.round = 0;
+    uint32_t *q0 = b->queue[0], *q1 = b->queue[1];
+    unsigned long long *m0 = b->mask[0], *m1 = b->mask[1];
+    uint32_t *bar = b->bar;
+    uint32_t max_rounds = kMaxRounds;
+    uint32_t spin_limit = 1u << 24;  // about 4 s of polling: far beyond one phase
+    void *args[] = {&A, &q0, &q1, &m0, &m1, &bar, &max_rounds, &spin_limit};
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    const hipError_t e = hipLaunchCooperativeKernel((const void *)hpersist_kernel, dim3(grid), dim3(BTB), args, 0, st);
+    prof_end(g, st, KAIROS_K_PUSH, ev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    KAIROS_HIP(hipMemcpyAsync(b->h_pin, b->cnt, 64, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    if (b->h_pin[BCNT_CAPPED]) return KAIROS_ERR_DEVICE;
+    if (g->prof.on) {
+        std::lock_guard<std::mutex> lk(g->prof.mu);
+        g->prof.rounds += b->h_pin[BCNT_ROUNDS];
+    }
     return KAIROS_OK;
 }
 
@@ -740,6 +847,13 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     const int wave_cap = std::max(1, g->num_cus * 8);
     const bool dense = g->tuning.batch_layout == 2;
     uint32_t r = 0;
+    if (dense && g->tuning.batch_persistent && F > 0) {
+        int prc = run_persistent(g, b, A, st);
+        if (prc == KAIROS_OK) F = 0;  // every round ran on the device
+        else if (prc != KAIROS_ERR_BUSY) return prc;
+        // KAIROS_ERR_BUSY: the launch was refused (no room for every block);
+        // run the same rounds with one launch per phase instead
+    }
     while (F > 0) {
         A.round = r;
         A.cur = b->queue[0];

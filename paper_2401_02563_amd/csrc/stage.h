@@ -124,4 +124,70 @@ __device__ __forceinline__ void block_stats(unsigned long long *stats, unsigned 
     }
 }
 
+// Grid-wide barrier for a cooperative launch (all blocks resident).  Block b
+// arrives on counter b % BAR_GROUPS; the last arrival of a group arrives on
+// the top counter, and the last of those bumps the generation word that the
+// others wait on.  Counters sit BAR_STRIDE words apart, so arrivals of
+// different groups do not queue on one address.  `bar` holds BAR_WORDS
+// zeroed words before the launch.  Every block must call this the same
+// number of times.  The fences make each block's earlier writes visible to
+// every block after the barrier.
+//
+// The wait is bounded: a block that polls more than `spin_limit` times
+// raises the abort word, and every waiting block leaves as soon as it sees
+// it.  Callers stop their round loop once grid_aborted() is true, so the
+// launch always ends; the host reports the abort as an error.
+constexpr uint32_t BAR_GROUPS = 16, BAR_STRIDE = 64;
+constexpr size_t BAR_WORDS = (BAR_GROUPS + 3) * BAR_STRIDE;
+
+__device__ __forceinline__ uint32_t *grid_abort_word(uint32_t *bar) { return bar + (BAR_GROUPS + 2) * BAR_STRIDE; }
+
+__device__ __forceinline__ bool grid_aborted(uint32_t *bar)
+{
+    return __hip_atomic_load(grid_abort_word(bar), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+}
+
+__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t spin_limit)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *top = bar + BAR_GROUPS * BAR_STRIDE;
+        uint32_t *gen = bar + (BAR_GROUPS + 1) * BAR_STRIDE;
+        uint32_t *abort_w = grid_abort_word(bar);
+        const uint32_t nb = gridDim.x;
+        const uint32_t grp = blockIdx.x % BAR_GROUPS;
+        const uint32_t members = (nb - grp + BAR_GROUPS - 1) / BAR_GROUPS;  // blocks b < nb, b % G == grp
+        const uint32_t groups = nb < BAR_GROUPS ? nb : BAR_GROUPS;
+        // read the generation before arriving: it cannot move until we arrive
+        const uint32_t g0 = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();  // release this block's writes; orders the load above before the arrival
+        bool last = false;
+        uint32_t *gc = bar + grp * BAR_STRIDE;
+        if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+            __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == groups - 1) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (last) {
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            // relaxed polls (an acquire per poll would invalidate the cache
+            // each time); the fence below is the acquire
+            uint32_t polls = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0) {
+                if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (++polls > spin_limit) {
+                    __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __threadfence();  // acquire: later reads see every block's writes
+    }
+    __syncthreads();
+}
+
 }  // namespace kairos

@@ -1297,7 +1297,7 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.pull_alpha = 0;
     t.pull_beta = 24;
     t.rounds_per_sync = 1;
-    t.batch_persistent = 0;
+    t.batch_persistent = 1;
     t.sweep_group = 1;
     t.batch_layout = 2;
     t.tail_limit = 4096;

@@ -278,8 +278,8 @@ def test_build_rejects_bad_edges():
     G.free()
 
 
-@pytest.mark.parametrize("layout", [0, 1, 2])
-def test_batch_layouts_ragged_groups(layout):
+@pytest.mark.parametrize("layout,persistent", [(0, 0), (1, 0), (2, 0), (2, 1)])
+def test_batch_layouts_ragged_groups(layout, persistent):
     """100 queries = one full and one ragged group of 64 lanes."""
     g, G, se = rmat16()
     srcs, ta, tw = make_queries("rmat22-256m", g, count=100)  # log-uniform windows on this graph
@@ -287,15 +287,37 @@ def test_batch_layouts_ragged_groups(layout):
     tw = np.maximum(ta, (tw.astype(np.uint64) * ((1 << 30) - 1) // 0xFFFFFFF4).astype(np.uint32))
     old = K.kairos_get_tuning(G)
     try:
-        K.kairos_set_tuning(G, batch_layout=layout)
+        K.kairos_set_tuning(G, batch_layout=layout, batch_persistent=persistent)
         out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
-        print_case("batch layout", layout)
+        print_case("batch layout", layout, "persistent", persistent)
         K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
         rows = K.as_u32(out).reshape(len(srcs), g.n)
         for qi in list(range(0, 100, 7)) + [63, 64, 99]:
             assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
     finally:
         K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("q", [1, 64, 130])
+def test_batch_persistent_matches_per_round(q):
+    """One persistent launch for all rounds equals one launch per phase, bit
+    for bit, and the oracle on sampled rows; repeated calls reuse the state."""
+    g, G, se = uniform()
+    srcs, ta, tw = make_queries("uniform-10k", g, count=q)
+    old = K.kairos_get_tuning(G)
+    outs = []
+    try:
+        for persistent in (0, 1, 1):
+            K.kairos_set_tuning(G, batch_layout=2, batch_persistent=persistent)
+            out = torch.full((q * g.n,), 5, dtype=torch.int32, device="cuda")
+            print_case("persistent", q, persistent)
+            K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+            outs.append(K.as_u32(out).reshape(q, g.n))
+    finally:
+        K.kairos_set_tuning(G, **old)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+    for qi in sorted({0, q // 2, q - 1}):
+        assert np.array_equal(outs[1][qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
 
 
 def test_batch_duplicate_sources():
