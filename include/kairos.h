@@ -165,6 +165,10 @@ typedef struct kairos_tuning {
     uint32_t arrival_filter; /* 1: a one-byte-per-vertex upper bound of each
                                 arrival rejects edges that cannot improve their
                                 head before the arrival itself is read; 0 off   */
+    uint32_t single_persistent; /* 1: single queries run their rounds with more
+                                than tail_limit frontier entries in one
+                                cooperative launch (grid barriers, no host
+                                round trip per round); needs pull_alpha 0      */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);

@@ -54,6 +54,7 @@ struct Slot {
     uint32_t *steps = nullptr;   // sweep departure times, descending (max out-degree)
     uint32_t *cnt = nullptr;     // device counters, see CNT_* below
     unsigned long long *stats = nullptr; // device work counters, see ST_*
+    uint32_t *bar = nullptr;     // grid barrier words of persistent launches
     uint32_t *h_pin = nullptr;   // pinned host mirror for counter read-back
     uint32_t stamp_next = 2;     // next round stamp value (0 = never stamped, 1 = spare)
     hipStream_t stream = nullptr;
@@ -67,7 +68,8 @@ enum : int {
     CNT_CHUNK = 3,   // [3..5] rotating chunk-list sizes
     CNT_STEP = 6,    // next departure step of a latest-departure / fastest sweep
     CNT_PULLVOL = 7, // [7..9] rotating: out-edges of the next frontier (saturating)
-    CNT_TAIL_ROUND = 13, CNT_TAIL_WHICH = 14, CNT_TAIL_ROUNDS = 15,  // left by the tail kernel
+    CNT_ABORT = 10,  // set by a persistent launch whose barrier wait gave up
+    CNT_TAIL_ROUND = 13, CNT_TAIL_WHICH = 14, CNT_TAIL_ROUNDS = 15,  // left by the tail and persistent kernels
     CNT_WORDS = 16
 };
 enum : int {

@@ -213,7 +213,8 @@ using TStage = Stage<SCAP>;
 // prefix-sum load balance, claims of at least `split` edges are cut into
 // chunks for part 2 (one chunk-list reservation per block and pass).
 template <bool SWEEP>
-__global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
+__device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage &S, unsigned long long &n_edges,
+                                           unsigned long long &n_relax, unsigned long long &n_items)
 {
     __shared__ uint32_t s_pref[TB + 1];
     __shared__ uint32_t s_lo[TB];
@@ -223,22 +224,18 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
     __shared__ uint32_t s_wsum[TB / 64];
     __shared__ uint32_t s_csum[TB / 64];
     __shared__ uint32_t s_cb;
-    __shared__ uint32_t s_stage[TB / 64][SCAP];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;
     const uint32_t r3 = A.round % 3u;
-    const uint32_t F = A.cnt[CNT_FRONT + r3];
     if (blockIdx.x == 0 && tid == 0) {
         A.cnt[CNT_FRONT + (A.round + 2u) % 3u] = 0u;
         A.cnt[CNT_PULLVOL + (A.round + 2u) % 3u] = 0u;
         A.cnt[CNT_CHUNK + (A.round + 1u) % 3u] = 0u;
     }
-    TStage S{s_stage[w], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     uint32_t *chunk_cnt = &A.cnt[CNT_CHUNK + r3];
-    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
 
     // sparse rounds walk the frontier queue; dense rounds walk every vertex
     // in id order and expand the members (stamped by the previous round), so
@@ -371,6 +368,15 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
         }
         __syncthreads();
     }
+}
+
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
+{
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
+    push_phase<SWEEP>(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
     stage_flush_block<SCAP, TB / 64>(S);
     unsigned long long v[4] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges};
     const int slot[4] = {ST_RELAX, ST_ATTEMPTS, ST_ITEMS, ST_EDGES};
@@ -380,14 +386,12 @@ __global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
 // Push round, part 2: every wave takes whole chunks (grid-stride over the
 // chunk list) and relaxes their edges UNR per lane at a time.
 template <bool SWEEP>
-__global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
+__device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsigned long long &n_edges,
+                                            unsigned long long &n_relax)
 {
-    __shared__ uint32_t s_stage[TB / 64][SCAP];
     const uint32_t r3 = A.round % 3u;
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
-    TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
-    unsigned long long n_edges = 0, n_relax = 0;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (TB / 64);
     for (uint32_t c = blockIdx.x * (TB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
@@ -413,9 +417,75 @@ __global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
             stage_append(S, bal, item);
         }
     }
+}
+
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
+{
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
+    unsigned long long n_edges = 0, n_relax = 0;
+    chunk_phase<SWEEP>(A, S, n_edges, n_relax);
     stage_flush_block<SCAP, TB / 64>(S);
     unsigned long long v[3] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_edges};
     const int slot[3] = {ST_RELAX, ST_ATTEMPTS, ST_CHUNK_EDGES};
+    block_stats<TB / 64>(A.stats, v, slot);
+}
+
+// Rounds of one query set in a single cooperative launch: push phase, grid
+// barrier, chunk phase, grid barrier, until the frontier holds at most
+// `stop_below` entries (small frontiers go to the one-workgroup kernel) or
+// `max_rounds` rounds ran.  Every block reads the frontier size from the same
+// word after a barrier, so all leave together.  On exit the round, the queue
+// holding the frontier and the number of rounds run are left in cnt as the
+// one-workgroup kernel leaves them; CNT_ABORT is raised if a barrier wait gave
+// up (the launch then ends early and the host reports an error).  Round
+// stamps are stamp_val, stamp_val + 1, ... (the host keeps them clear of
+// wrap-around).
+template <bool SWEEP>
+__global__ __launch_bounds__(TB) void persist_kernel(TravArgs A, uint32_t which0, uint32_t *q0, uint32_t *q1,
+                                                     uint32_t stop_below, uint32_t max_rounds, uint32_t dense_div,
+                                                     uint32_t *bar, uint32_t spin_limit)
+{
+    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    __shared__ uint32_t s_F;
+    unsigned long long n_edges = 0, n_relax = 0, n_items = 0, n_cedges = 0;
+    const uint32_t r0 = A.round;
+    uint32_t r = r0;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_F = grid_aborted(bar) ? 0u
+                                    : __hip_atomic_load(&A.cnt[CNT_FRONT + r % 3u], __ATOMIC_ACQUIRE,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t F = s_F;
+        __syncthreads();
+        if (F <= stop_below || r - r0 >= max_rounds) break;
+        const uint32_t odd = (which0 ^ (r - r0)) & 1u;
+        TravArgs B = A;
+        B.round = r;
+        B.stamp_val = A.stamp_val + (r - r0);
+        B.front_stamp = B.stamp_val - 1u;
+        B.cur = odd ? q1 : q0;
+        B.next = odd ? q0 : q1;
+        B.dense = (A.nq == 1 && dense_div && (uint64_t)F * dense_div >= A.n) ? 1u : 0u;
+        TStage S{s_stage[threadIdx.x >> 6], 0u, B.next, &A.cnt[CNT_FRONT + (r + 1u) % 3u]};
+        push_phase<SWEEP>(B, F, S, n_edges, n_relax, n_items);
+        stage_flush_block<SCAP, TB / 64>(S);
+        grid_barrier(bar, spin_limit);
+        chunk_phase<SWEEP>(B, S, n_cedges, n_relax);
+        stage_flush_block<SCAP, TB / 64>(S);
+        grid_barrier(bar, spin_limit);
+        ++r;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.cnt[CNT_TAIL_ROUND] = r;
+        A.cnt[CNT_TAIL_WHICH] = (which0 ^ (r - r0)) & 1u;
+        A.cnt[CNT_TAIL_ROUNDS] = r - r0;
+        A.cnt[CNT_ABORT] = grid_aborted(bar) ? 1u : 0u;
+    }
+    unsigned long long v[5] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges, n_cedges};
+    const int slot[5] = {ST_RELAX, ST_ATTEMPTS, ST_ITEMS, ST_EDGES, ST_CHUNK_EDGES};
     block_stats<TB / 64>(A.stats, v, slot);
 }
 
@@ -820,6 +890,56 @@ uint32_t next_stamp(Slot *s, int *rc)
     return s->stamp_next++;
 }
 
+// Rounds with more than `stop` frontier entries in one cooperative launch
+// (persist_kernel).  Updates the round, the queue holding the frontier and
+// its size from what the kernel left.  KAIROS_ERR_BUSY: the runtime refused
+// the launch and nothing ran.
+template <bool SWEEP>
+int run_persistent(kairos_graph *g, Slot *s, TravArgs A, uint32_t *r, int *which, uint32_t *F, uint32_t stop)
+{
+    hipStream_t st = s->stream;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, persist_kernel<SWEEP>, TB, 0) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    constexpr uint32_t kMaxRounds = 1u << 16;  // per launch; the host launches again if needed
+    if (s->stamp_next >= 0xFFFFF000u - kMaxRounds) {
+        int rc = fill(st, s->stamp, (uint64_t)s->qcap * s->n, 0u);
+        if (rc) return rc;
+        s->stamp_next = 2;
+    }
+    KAIROS_HIP(hipMemsetAsync(s->bar, 0, BAR_WORDS * 4, st));
+    A.round = *r;
+    A.stamp_val = s->stamp_next;
+    uint32_t which0 = (uint32_t)*which, max_rounds = kMaxRounds, dense_div = g->tuning.dense_frontier;
+    uint32_t spin_limit = 1u << 24;  // about 4 s of polling: far beyond one phase
+    uint32_t *q0 = s->queue[0], *q1 = s->queue[1], *bar = s->bar;
+    void *args[] = {&A, &which0, &q0, &q1, &stop, &max_rounds, &dense_div, &bar, &spin_limit};
+    const int grid = g->num_cus * std::min(occ, 4);
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    const hipError_t e = hipLaunchCooperativeKernel((const void *)persist_kernel<SWEEP>, dim3(grid), dim3(TB), args, 0, st);
+    prof_end(g, st, KAIROS_K_PUSH, ev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, CNT_WORDS * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    if (s->h_pin[CNT_ABORT]) return KAIROS_ERR_DEVICE;
+    const uint32_t rounds = s->h_pin[CNT_TAIL_ROUNDS];
+    *r = s->h_pin[CNT_TAIL_ROUND];
+    *which = (int)s->h_pin[CNT_TAIL_WHICH];
+    *F = s->h_pin[CNT_FRONT + *r % 3u];
+    s->stamp_next += rounds;
+    if (g->prof.on) {
+        std::lock_guard<std::mutex> lk(g->prof.mu);
+        g->prof.rounds += rounds;
+    }
+    return KAIROS_OK;
+}
+
 // Runs frontier rounds until the frontier is empty.  The first round's
 // frontier (nq items) is already in s->queue[0] and the counters set for
 // round `r0`.
@@ -839,6 +959,8 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
     const uint64_t total_v = (uint64_t)A.nq * g->n;
     int rc = KAIROS_OK;
     uint32_t step = (SWEEP && A.steps) ? 1u : 0u;  // host mirror of CNT_STEP
+    bool persist = tu.single_persistent != 0;
+    const uint32_t stop = tu.tail_limit;  // persistent launches leave small frontiers to the tail kernel
     for (;;) {
         if (F == 0) {
             if (!SWEEP || !A.steps || step >= A.nsteps) break;
@@ -878,6 +1000,12 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
             if (F == 0) continue;
             if (done_rounds > 0 && F <= tu.tail_limit) continue;  // stopped at max_rounds
             vol = 0;
+        }
+        if (persist && !tu.pull_alpha && F > stop) {
+            int prc = run_persistent<SWEEP>(g, s, A, &r, &which, &F, stop);
+            if (prc == KAIROS_OK) continue;
+            if (prc != KAIROS_ERR_BUSY) return prc;
+            persist = false;  // launch refused: per-round launches from here on
         }
         for (uint32_t k = 0; k < R; ++k) {
             A.round = r;
@@ -954,6 +1082,7 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     s->chunks = (uint4 *)dev_alloc(s->chunk_cap * sizeof(uint4), acct);
     s->qp = (uint4 *)dev_alloc((size_t)qcap * sizeof(uint4), acct);
     s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
+    s->bar = (uint32_t *)dev_alloc(BAR_WORDS * 4, acct);
     s->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, acct);
     s->arr = (uint32_t *)dev_alloc(qn * 4, acct);
     s->filt = (uint8_t *)dev_alloc((qn + 3) / 4 * 4, acct);
@@ -962,7 +1091,7 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
         s->l1 = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->steps = (uint32_t *)dev_alloc((size_t)std::max<uint32_t>(g->max_out_degree, 1) * 4, acct);
     }
-    bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt &&
+    bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt && s->bar &&
               s->stats && s->arr && s->filt && (qcap != 1 || (s->fa && s->l1 && s->steps));
     if (ok && hipHostMalloc((void **)&s->h_pin, 1024, hipHostMallocDefault) != hipSuccess) {
         s->h_pin = nullptr;
@@ -1069,6 +1198,7 @@ void slot_destroy(Slot *s)
     dev_free(s->stats);
     dev_free(s->arr);
     dev_free(s->filt);
+    dev_free(s->bar);
     dev_free(s->fa);
     dev_free(s->l1);
     dev_free(s->steps);
@@ -1296,8 +1426,9 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.split = 128;
     t.pull_alpha = 0;
     t.pull_beta = 24;
-    t.rounds_per_sync = 1;
+    t.rounds_per_sync = 8;  // measured best: queued empty rounds cost less than host checks
     t.batch_persistent = 1;
+    t.single_persistent = 0;  // measured slower: barrier fences cost more than the host round trip
     t.sweep_group = 1;
     t.batch_layout = 2;
     t.tail_limit = 4096;

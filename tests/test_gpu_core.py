@@ -108,9 +108,11 @@ def test_ea_skewed(which):
 
 
 @pytest.mark.parametrize("tuning", [dict(split=64, chunk=64), dict(split=100000, chunk=4096),
-                                    dict(rounds_per_sync=4), dict(pull_alpha=1, pull_beta=1000000),
+                                    dict(rounds_per_sync=4), dict(rounds_per_sync=1), dict(pull_alpha=1, pull_beta=1000000),
                                     dict(pull_alpha=8, pull_beta=24), dict(arrival_filter=0),
-                                    dict(arrival_filter=0, tail_limit=0)])
+                                    dict(arrival_filter=0, tail_limit=0), dict(single_persistent=0),
+                                    dict(single_persistent=1, tail_limit=0),
+                                    dict(single_persistent=1, tail_limit=0, dense_frontier=4)])
 def test_ea_independent_of_tuning(tuning):
     """Results are unique, so every launch configuration must agree bit for bit."""
     g, G, se = rmat16()
@@ -204,6 +206,29 @@ def test_ld_fastest_uniform():
         assert np.array_equal(K.as_u32(out), pld), q
         K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
         assert np.array_equal(K.as_u32(out), pf), q
+
+
+@pytest.mark.parametrize("persistent,tail", [(0, 4096), (1, 0), (1, 64)])
+def test_ld_fastest_launch_modes(persistent, tail):
+    """Sweeps give the same answers with rounds in one cooperative launch,
+    in per-round launches, and with small frontiers in one workgroup."""
+    g, G, se = rmat16()
+    srcs, ta, tw = make_queries("rmat20-32m", g, count=3)
+    old = K.kairos_get_tuning(G)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    try:
+        K.kairos_set_tuning(G, single_persistent=persistent, tail_limit=tail)
+        for q in range(3):
+            print_case("ldf modes", persistent, tail, q)
+            pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
+            K.kairos_earliest_arrival(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+            assert np.array_equal(K.as_u32(out), pea), q
+            K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+            assert np.array_equal(K.as_u32(out), pld), q
+            K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), out)
+            assert np.array_equal(K.as_u32(out), pf), q
+    finally:
+        K.kairos_set_tuning(G, **old)
 
 
 def test_ld_fastest_bursty():
