@@ -13,9 +13,12 @@ tail is reached, departing no earlier than the tail's earliest arrival and
 t_alpha, arriving by t_omega; counted on the GPU from the result) times
 steps, divided by the wall time of the timed steps.
 
-Printed as one JSON line, with the dominant kernel's roofline figures
-measured with HIP events over the timed steps, and the CPU oracle timed on
-a bounded sample of the same workload on this host's cores.
+Printed as one JSON line.  The timed steps run without per-launch events;
+the same steps then run again with every launch bracketed by HIP events on
+its own stream, which give the dominant kernel's average launch duration
+for the roofline figures (that pass's step time is reported beside them).
+The CPU oracle is timed on a bounded sample of the same workload on this
+host's cores.
 """
 from __future__ import annotations
 
@@ -100,20 +103,31 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    K.kairos_profile_enable(G, True)
-    K.kairos_profile_read(G)  # reset
-    torch.cuda.synchronize()
+    # timed steps: `value` (no per-launch events, which cost host time on
+    # short launches)
     t1 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
-    prof = K.kairos_profile_read(G)
-    K.kairos_profile_enable(G, False)
     ms_per_step = elapsed / args.steps * 1e3
     value = etrav_total * args.steps / elapsed
+    # the same steps again with every launch bracketed by HIP events on its
+    # own stream and device work counters on: the roofline figures
+    K.kairos_profile_enable(G, True)
+    K.kairos_profile_read(G)  # reset
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - t2
+    prof = K.kairos_profile_read(G)
+    K.kairos_profile_enable(G, False)
 
-    roofline = roofline_from_profile(prof, args.mode, etrav_total * args.steps, args.workload)
+    tuning = K.kairos_get_tuning(G)
+    roofline = roofline_from_profile(prof, args.mode, etrav_total * args.steps, args.workload, tuning)
+    roofline["profiled_ms_per_step"] = round(prof_elapsed / args.steps * 1e3, 3)
     if os.environ.get("KAIROS_CALIBRATION_COPY"):
         # a plain 256 MiB copy: the counter-calibration kernel of bench_pmc.py
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
@@ -143,7 +157,10 @@ def main():
         "build_ms": round(build_s * 1e3, 2), "build_edges_per_s": g.m / build_s,
         "traversed_edges_per_step": etrav_total,
         "rounds_per_step": prof["rounds"] / args.steps,
-        "roofline": roofline, "cpu_baseline": cpu, **extra,
+        "roofline": roofline, "cpu_baseline": cpu,
+        "tuning": {k: tuning[k] for k in ("batch_layout", "batch_persistent", "single_persistent", "rounds_per_sync",
+                                          "tail_limit", "split", "chunk", "arrival_filter")},
+        **extra,
     }
     print(json.dumps(line), flush=True)
     G.free()
@@ -151,51 +168,67 @@ def main():
 
 # Algorithmic bytes per unit of work (what the method must move, not what the
 # caches do):
-#   single-query kernels (push, chunk, tail): 8 B per out-edge record read
-#   (head, arrival) + 4 B per edge for the head's arrival + 16 B per frontier
-#   entry (two offsets, the tail's arrival, its claim word) + 8 B per improving
-#   relaxation (the new arrival and the enqueued entry);
-#   vertex-major batch kernels (push, chunk): 8 B per edge record read once for
-#   the group + 4 B per (edge, query) check of the head's arrival row + 12 B
-#   per (frontier vertex, query) claim (arrival, claim word read and written)
-#   + 4 B per improving relaxation.
-def roofline_from_profile(prof, mode, pairs, workload):
-    classes = ["push", "chunk"] + (["tail"] if mode == "single" else [])
+#   per-(query, vertex) kernels -- single queries (push, chunk, tail,
+#   persist), the query-major batch, the lane-dense batch (hpush, hchunk,
+#   hpersist): 8 B per scanned out-edge record (head, arrival) + 4 B for the
+#   head's arrival + 16 B per frontier entry (two offsets, the tail's arrival,
+#   its claim word) + 8 B per improving relaxation (the new arrival and the
+#   enqueued entry);
+#   vertex-major batch (bpush, bchunk): 8 B per edge record, read once for
+#   the 64 queries of a group + 4 B per (edge, query) check of the head's
+#   arrival row + 12 B per (frontier vertex, query) claim + 4 B per improving
+#   relaxation.
+def kernel_names(mode, tuning):
+    """Kernel names of the push, chunk and tail classes for this run."""
+    if mode == "single":
+        push = "persist_kernel" if tuning.get("single_persistent") else "push_kernel"
+        return {"push": push, "chunk": "chunk_kernel", "tail": "tail_kernel"}
+    layout = tuning.get("batch_layout", 2)
+    if layout == 2 and tuning.get("batch_persistent"):
+        return {"push": "hpersist_kernel", "chunk": "hchunk_kernel"}
+    return {0: {"push": "bpush_kernel", "chunk": "bchunk_kernel"},
+            1: {"push": "push_kernel", "chunk": "chunk_kernel"},
+            2: {"push": "hpush_kernel", "chunk": "hchunk_kernel"}}[layout]
+
+
+def roofline_from_profile(prof, mode, pairs, workload, tuning):
+    names = kernel_names(mode, tuning)
+    classes = [c for c in ("push", "chunk", "tail") if c in names and prof.get(f"launches_{c}", 0) > 0]
     edges = {"push": prof["edges_scanned"], "chunk": prof["chunk_edges"], "tail": prof.get("tail_edges", 0)}
+    items = {"push": prof["items"], "chunk": 0, "tail": prof.get("tail_items", 0)}
+    if names["push"] in ("hpersist_kernel", "persist_kernel") and prof.get("launches_chunk", 0) == 0:
+        # one launch runs both phases: its edges are the push and chunk counts
+        edges["push"] += edges["chunk"]
+        edges["chunk"] = 0
     tot_edges = max(1, sum(edges[c] for c in classes))
+    vertex_major = mode == "batch" and tuning.get("batch_layout") == 0
     res = {}
     for c in classes:
         share = edges[c] / tot_edges
-        if mode == "single":
-            items = prof["items"] if c == "push" else (prof.get("tail_items", 0) if c == "tail" else 0)
-            b = 12 * edges[c] + 16 * items + 8 * prof["relaxations"] * share
+        if vertex_major:
+            b = 8 * edges[c] + 4 * pairs * share + 12 * items[c] + 4 * prof["relaxations"] * share
         else:
-            items = prof["items"] if c == "push" else 0
-            b = 8 * edges[c] + 4 * pairs * share + 12 * items + 4 * prof["relaxations"] * share
-        n = max(1, prof[f"launches_{c}"])
-        ms = prof[f"ms_{c}"]
-        res[c] = {"bytes": b, "launches": n, "ms": ms}
+            b = 12 * edges[c] + 16 * items[c] + 8 * prof["relaxations"] * share
+        res[c] = {"bytes": b, "launches": max(1, prof[f"launches_{c}"]), "ms": prof[f"ms_{c}"]}
     kern = max(res, key=lambda c: res[c]["ms"])
     r = res[kern]
     avg_ms = r["ms"] / r["launches"]
     per_launch = r["bytes"] / r["launches"]
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    kname = {"push": "push_kernel", "chunk": "chunk_kernel", "tail": "tail_kernel"}[kern]
-    if mode == "batch":
-        kname = "b" + kname.replace("_kernel", "") + "_kernel"
-    out = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(kname, workload),
-           "avg_launch_us": round(avg_ms * 1e3, 2), "launches": r["launches"],
-           "alg_bytes_per_launch": int(per_launch),
-           "per_kernel": {c: {"ms": round(v["ms"], 3), "launches": v["launches"],
-                              "alg_GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for c, v in res.items()}}
-    return out
+    kname = names[kern]
+    return {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(kname, workload, mode),
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": r["launches"],
+            "alg_bytes_per_launch": int(per_launch),
+            "per_kernel": {names[c]: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                                      "alg_GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+                           for c, v in res.items()}}
 
 
-def traffic_for(kname, workload):
+def traffic_for(kname, workload, mode):
     """HBM bytes per launch of `kname` from a stored rocprofv3 counter summary,
     or None when there is none or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{mode}.json")
     if not os.path.exists(path):
         return None
     try:

@@ -1,7 +1,7 @@
 """HBM traffic of the benchmark's kernels from rocprofv3 counters.
 
-    python bench_pmc.py run   [bench args...]   # on the GPU host: three runs
-    python bench_pmc.py summarize OUTDIR        # writes profiles/*.txt|json
+    python bench_pmc.py run [bench args...]             # on the GPU host: three runs
+    python bench_pmc.py summarize OUTDIR WORKLOAD MODE  # writes profiles/*.txt|json
 
 `run` executes bench.py three times under rocprofv3: once with a kernel
 trace and statistics, once collecting FETCH_SIZE and once WRITE_SIZE (each
@@ -12,8 +12,9 @@ moves exactly 256 MiB each way, so the ratio of the counter reading to
 
 `summarize` reads the rocpd databases and writes, per kernel, calls, mean
 duration and the calibrated bytes per launch into
-profiles/traffic_<workload>.json (consumed by bench.py when the kernel
-sources still hash the same) and a text summary next to it.
+profiles/traffic_<workload>_<mode>.json (consumed by bench.py when the
+kernel sources still hash the same) and a text summary
+profiles/kernels_<workload>_<mode>.txt next to it.
 """
 from __future__ import annotations
 
@@ -29,7 +30,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["paper_2401_02563_amd/csrc/traverse.hip", "paper_2401_02563_amd/csrc/batch.hip",
-                  "paper_2401_02563_amd/csrc/build.hip"]
+                  "paper_2401_02563_amd/csrc/build.hip", "paper_2401_02563_amd/csrc/stage.h"]
 COPY_BYTES = 256 << 20
 
 
@@ -49,7 +50,8 @@ def short_name(n: str) -> str:
 
 
 def run(argv):
-    out = os.path.join(ROOT, "gpurun_out", "pmc")
+    mode = argv[argv.index("--mode") + 1] if "--mode" in argv else "batch"
+    out = os.path.join(ROOT, "gpurun_out", "pmc_" + mode)
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
     bench = [sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu", *argv]
@@ -62,8 +64,18 @@ def run(argv):
         with open(os.path.join(out, f"{tag}.log"), "w") as log:
             rc = subprocess.call(cmd, stdout=log, stderr=subprocess.STDOUT, env=env)
         print(f"pass {tag} rc={rc}", flush=True)
+        if rc in (-11, 139) and _bench_line_printed(os.path.join(out, f"{tag}.log")):
+            # rocprofv3 can fault in its own exit handler after a cooperative
+            # launch; the program had finished and the results are complete
+            print(f"pass {tag}: profiler ended with a fault after the program finished; results kept", flush=True)
+            continue
         if rc != 0:
             sys.exit(rc)
+
+
+def _bench_line_printed(log_path):
+    with open(log_path, errors="replace") as f:
+        return any(line.startswith('{"metric"') for line in f)
 
 
 def _db(path):
@@ -73,7 +85,7 @@ def _db(path):
     return sqlite3.connect(dbs[0])
 
 
-def summarize(outdir, workload="rmat20-32m"):
+def summarize(outdir, workload="rmat20-32m", mode="batch"):
     trace = _db(os.path.join(outdir, "trace"))
     stats = collections.defaultdict(lambda: [0, 0.0])
     for name, dur in trace.execute("select name, duration from kernels"):
@@ -107,19 +119,21 @@ def summarize(outdir, workload="rmat20-32m"):
             "fetch_bytes_per_launch": (f[1] / f[0] * 1024.0 / cal["FETCH_SIZE"]) if f else None,
             "write_bytes_per_launch": (w[1] / w[0] * 1024.0 / cal["WRITE_SIZE"]) if w else None,
         }
-    doc = {"workload": workload, "kernel_sources_sha": kernel_source_hash(), "calibration": cal,
+    doc = {"workload": workload, "mode": mode, "kernel_sources_sha": kernel_source_hash(), "calibration": cal,
            "copy_bytes": COPY_BYTES, "kernels": rows}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}_{mode}.json"), "w") as f:
         json.dump(doc, f, indent=1)
-    lines = [f"# rocprofv3 summary: bench.py workload {workload}",
+    b = f"--workload {workload} --mode {mode} --no-cpu --steps 3 --warmup 1"
+    lines = [f"# rocprofv3 summary: bench.py workload {workload}, mode {mode}",
              "",
              "commands (from the repository root, on the GPU host):",
-             "  python bench_pmc.py run --steps 3 --warmup 1   # three rocprofv3 passes:",
-             "    rocprofv3 --kernel-trace --stats -- python bench.py --no-cpu --steps 3 --warmup 1",
-             "    rocprofv3 --pmc FETCH_SIZE       -- python bench.py --no-cpu --steps 3 --warmup 1",
-             "    rocprofv3 --pmc WRITE_SIZE       -- python bench.py --no-cpu --steps 3 --warmup 1",
-             "  python bench_pmc.py summarize gpurun_out/pmc",
+             f"  python bench_pmc.py run --workload {workload} --mode {mode} --steps 3 --warmup 1",
+             "  which makes three rocprofv3 passes, each its own process:",
+             f"    rocprofv3 --kernel-trace --stats -- python bench.py {b}",
+             f"    rocprofv3 --pmc FETCH_SIZE       -- python bench.py {b}",
+             f"    rocprofv3 --pmc WRITE_SIZE       -- python bench.py {b}",
+             f"  python bench_pmc.py summarize gpurun_out/pmc_{mode} {workload} {mode}",
              "",
              f"kernel sources sha256[:16]: {doc['kernel_sources_sha']}",
              f"calibration (counter / true bytes of a {COPY_BYTES >> 20} MiB copy): "
@@ -130,7 +144,7 @@ def summarize(outdir, workload="rmat20-32m"):
         fb = f"{r['fetch_bytes_per_launch'] / 1e6:16.2f}" if r["fetch_bytes_per_launch"] is not None else f"{'-':>16s}"
         wb = f"{r['write_bytes_per_launch'] / 1e6:16.2f}" if r["write_bytes_per_launch"] is not None else f"{'-':>16s}"
         lines.append(f"{k[:34]:34s} {r['calls']:7d} {r['mean_us']:10.2f} {r['total_ms']:10.2f} {fb} {wb}")
-    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}.txt"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"kernels_{workload}_{mode}.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -139,7 +153,7 @@ if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "run":
         run(sys.argv[2:])
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize":
-        summarize(sys.argv[2], *(sys.argv[3:4]))
+        summarize(sys.argv[2], *(sys.argv[3:5]))
     else:
         print(__doc__)
         sys.exit(2)
