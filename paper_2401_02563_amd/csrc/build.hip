@@ -254,12 +254,22 @@ __global__ void finalize_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_
             tk[i] = r.w;
             pair[i] = make_uint2(r.x, r.z);
         }
-        // offsets of the keys in (previous key, key] start here
+        // offsets of the keys in (previous key, key] start here; the keys
+        // after the last one are filled by tail_offsets_kernel
         const uint64_t first = i == 0 ? 0 : (uint64_t)(which == 0 ? e[i - 1].x : e[i - 1].y) + 1;
         for (uint64_t v = first; v <= key; ++v) off[v] = (uint32_t)i;
-        if (i == m - 1)
-            for (uint64_t v = (uint64_t)key + 1; v <= n; ++v) off[v] = (uint32_t)m;
     }
+}
+
+// off[v] = m for every key v after the last record's key (a long run when
+// many vertices have no edge in this direction), grid-stride.
+__global__ void tail_offsets_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t n, int which,
+                                    uint32_t *__restrict__ off)
+{
+    const uint64_t last = which == 0 ? e[m - 1].x : e[m - 1].y;
+    for (uint64_t v = last + 1 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n;
+         v += (uint64_t)gridDim.x * blockDim.x)
+        off[v] = (uint32_t)m;
 }
 
 __global__ void zero_offsets_kernel(uint32_t *off, uint32_t n)
@@ -496,9 +506,11 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         const int fg = grid_for(m, 256, 16384);
         hipLaunchKernelGGL(finalize_kernel, dim3(fg), dim3(256), 0, st, a, m, n, 0, g->off_out,
                            g->t_out, g->da_out);
+        hipLaunchKernelGGL(tail_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256), 0, st, a, m, n, 0, g->off_out);
         if ((rc = run_passes(g, a, b, m, in_p, hist, st)) != KAIROS_OK) break;
         hipLaunchKernelGGL(finalize_kernel, dim3(fg), dim3(256), 0, st, a, m, n, 1, g->off_in,
                            g->a_in, g->st_in);
+        hipLaunchKernelGGL(tail_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256), 0, st, a, m, n, 1, g->off_in);
     } while (0);
     if (rc == KAIROS_OK) {
         uint32_t *d_max = hist + 256 * (size_t)nblocks + 8;
