@@ -162,9 +162,13 @@ typedef struct kairos_tuning {
     uint32_t dense_frontier; /* single queries: a frontier of at least
                                 n / dense_frontier vertices is expanded by
                                 walking all vertices in id order; 0 disables     */
-    uint32_t arrival_filter; /* 1: a one-byte-per-vertex upper bound of each
-                                arrival rejects edges that cannot improve their
-                                head before the arrival itself is read; 0 off   */
+    uint32_t arrival_filter; /* bits (2, 4 or 8) of a per-vertex code that bounds
+                                each arrival from above (the query's reachable
+                                time range cut into 2^bits equal parts); an
+                                edge arriving at or after its head's bound is
+                                dropped before the arrival word is read.
+                                0: off.  Each query keeps the width it started
+                                with                                            */
     uint32_t single_persistent; /* 1: single queries run their rounds with more
                                 than tail_limit frontier entries in one
                                 cooperative launch (grid barriers, no host
@@ -172,6 +176,8 @@ typedef struct kairos_tuning {
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);
+/* KAIROS_ERR_INVALID for a value outside the documented sets.  Call it while
+ * no query, batch or server of g is in flight; results never depend on it. */
 int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in);
 
 /* Grid search over the tuning space on q sample queries (host arrays, as in

@@ -261,7 +261,7 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 16 || in->split < 16 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
-        in->batch_layout > 2 || in->arrival_filter > 1 || in->batch_persistent > 1 || in->single_persistent > 1)
+        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1)
         return KAIROS_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g->pool_mu);
     const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split ||

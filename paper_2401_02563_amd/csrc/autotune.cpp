@@ -90,7 +90,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         {&kairos_tuning::chunk, {128, 256, 512, 2048}},
         {&kairos_tuning::tail_limit, {0, 1024, 4096, 16384}},
         {&kairos_tuning::dense_frontier, {0, 4, 16, 64}},
-        {&kairos_tuning::arrival_filter, {0, 1}},
+        {&kairos_tuning::arrival_filter, {0, 2, 4, 8}},
         {&kairos_tuning::batch_persistent, {0, 1}},
         {&kairos_tuning::single_persistent, {0, 1}},
         {&kairos_tuning::rounds_per_sync, {1, 2, 4}},

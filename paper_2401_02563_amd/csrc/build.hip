@@ -450,8 +450,6 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         const uint32_t max_t = h_stats[1], max_a = h_stats[2], min_l = h_stats[3], max_l = h_stats[4];
         g->max_t = max_t;
         g->max_a = max_a;
-        g->fshift = 0;
-        while (((uint64_t)max_a + (1ull << g->fshift) - 1) >> g->fshift > 254) ++g->fshift;
         const int nb = bits_for(n - 1);
         const int lb = bits_for(max_l - min_l);
         std::vector<Pass> out_p, in_p;

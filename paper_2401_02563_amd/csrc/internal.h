@@ -42,13 +42,13 @@ struct Slot {
     uint32_t qcap = 0;
     uint32_t n = 0;
     uint32_t *done = nullptr;    // qcap*n: lowest claimed out-edge per vertex, INF = unvisited
-    uint32_t *stamp = nullptr;   // qcap*n: round stamp used to enqueue a vertex once per round
     uint32_t *queue[2] = {nullptr, nullptr}; // qcap*n each: frontier items q*n+u
     uint4 *chunks = nullptr;     // split adjacency ranges {q, start, len, _}
     uint64_t chunk_cap = 0;
     uint4 *qp = nullptr;         // qcap: {src, t_alpha, t_omega, sweep departure}
-    uint32_t *arr = nullptr;     // qcap*n: arrivals
-    uint8_t *filt = nullptr;     // qcap*n (rounded up to 4): bucketed upper bound of arr, 255 = none
+    unsigned long long *av = nullptr; // qcap*n: arrival << 32 | stamp of the round that last lowered it
+    uint8_t *filt = nullptr;     // qcap regions of filt_stride(n) bytes: packed arrival codes
+    uint2 *fpar = nullptr;       // qcap: arrival-code parameters {base, shift | bits << 8}
     uint32_t *fa = nullptr;      // n: fastest duration (sweep)
     uint32_t *l1 = nullptr;      // n: latest departure + 1 (sweep), 0 = none
     uint32_t *steps = nullptr;   // sweep departure times, descending (max out-degree)
@@ -61,6 +61,10 @@ struct Slot {
     bool own_stream = false;
     uint64_t bytes = 0;
 };
+
+// Bytes of one query's arrival-code region: room for 8-bit codes, rounded
+// to whole words, so the layout does not depend on the code width.
+inline size_t filt_stride(uint32_t n) { return ((size_t)n + 3) / 4 * 4; }
 
 // Counter layout (uint32 words) in Slot::cnt.
 enum : int {
@@ -123,8 +127,6 @@ struct kairos_graph {
     uint32_t max_out_degree = 0;
     uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
     uint32_t max_a = 0;           // largest arrival time
-    uint32_t fshift = 0;          // arrival filter: bucket width 2^fshift, ceil(max_a / 2^fshift) <= 254
-                                  // (up to 25, so bound * width needs 64 bits)
     uint64_t index_bytes = 0;
     hipStream_t stream = nullptr; // caller's stream, or nullptr
     int device = 0;
@@ -166,8 +168,10 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
 // slots q in [0, qcap), query-major arrays of qcap*n words).
 struct MultiState {
     uint32_t qcap = 0, n = 0;
-    uint32_t *arr = nullptr, *done = nullptr, *stamp = nullptr, *fa = nullptr, *l1 = nullptr;
-    uint8_t *filt = nullptr;                  // qcap*n bucketed arrival bounds (see Slot)
+    unsigned long long *av = nullptr;         // arrival << 32 | round stamp (see Slot)
+    uint32_t *done = nullptr, *fa = nullptr, *l1 = nullptr;
+    uint8_t *filt = nullptr;                  // qcap regions of filt_stride(n) bytes (see Slot)
+    uint2 *fpar = nullptr;                    // qcap arrival-code parameters (see Slot)
     uint32_t *queue[2] = {nullptr, nullptr};  // queue[0] feeds the next round
     uint32_t *cnt = nullptr;                  // CNT_WORDS counters, then qcap activity flags
     uint4 *chunks = nullptr, *qp = nullptr;

@@ -77,7 +77,8 @@ size_t pin_words(uint32_t max_slots)
 
 uint64_t slot_bytes(kairos_server *s)
 {
-    return (uint64_t)s->g->n * (4 * 7 + 1) + s->per_slot_chunks * sizeof(uint4) + sizeof(uint4) + 4;
+    return (uint64_t)s->g->n * (4 * 7) + filt_stride(s->g->n) + s->per_slot_chunks * sizeof(uint4) +
+           sizeof(uint4) + sizeof(uint2) + 4;
 }
 
 bool free_bytes_ok(kairos_server *s, uint64_t need)
@@ -93,10 +94,10 @@ bool free_bytes_ok(kairos_server *s, uint64_t need)
 
 void free_state(MultiState &m)
 {
-    dev_free(m.arr);
+    dev_free(m.av);
     dev_free(m.filt);
+    dev_free(m.fpar);
     dev_free(m.done);
-    dev_free(m.stamp);
     dev_free(m.fa);
     dev_free(m.l1);
     dev_free(m.queue[0]);
@@ -124,10 +125,10 @@ bool grow(kairos_server *s, uint32_t ncap)
     nm.stamp_next = s->ms.stamp_next;
     nm.stream = s->ms.stream;
     nm.chunk_cap = s->per_slot_chunks * ncap;
-    nm.arr = (uint32_t *)dev_alloc(qn * 4, nullptr);
-    nm.filt = (uint8_t *)dev_alloc((qn + 3) / 4 * 4, nullptr);
+    nm.av = (unsigned long long *)dev_alloc(qn * 8, nullptr);
+    nm.filt = (uint8_t *)dev_alloc((size_t)ncap * filt_stride(s->g->n), nullptr);
+    nm.fpar = (uint2 *)dev_alloc((size_t)ncap * sizeof(uint2), nullptr);
     nm.done = (uint32_t *)dev_alloc(qn * 4, nullptr);
-    nm.stamp = (uint32_t *)dev_alloc(qn * 4, nullptr);
     nm.fa = (uint32_t *)dev_alloc(qn * 4, nullptr);
     nm.l1 = (uint32_t *)dev_alloc(qn * 4, nullptr);
     nm.queue[0] = (uint32_t *)dev_alloc(qn * 4 + 64, nullptr);
@@ -137,17 +138,17 @@ bool grow(kairos_server *s, uint32_t ncap)
     nm.qp = (uint4 *)dev_alloc((size_t)ncap * sizeof(uint4), nullptr);
     nm.stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, nullptr);
     hipStream_t st = s->ms.stream;
-    bool ok = nm.arr && nm.filt && nm.done && nm.stamp && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
+    bool ok = nm.av && nm.filt && nm.fpar && nm.done && nm.fa && nm.l1 && nm.queue[0] && nm.queue[1] && nm.cnt &&
               nm.chunks && nm.qp && nm.stats;
-    ok = ok && hipMemsetAsync(nm.stamp, 0, qn * 4, st) == hipSuccess &&
+    ok = ok && hipMemsetAsync(nm.av, 0, qn * 8, st) == hipSuccess &&
          hipMemsetAsync(nm.cnt, 0, (CNT_WORDS + (size_t)ncap) * 4, st) == hipSuccess &&
          hipMemsetAsync(nm.stats, 0, ST_TOTAL_WORDS * 8, st) == hipSuccess;
     if (ok && s->cap) {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-        ok = hipMemcpyAsync(nm.arr, s->ms.arr, on * 4, k, st) == hipSuccess &&
-             hipMemcpyAsync(nm.filt, s->ms.filt, on, k, st) == hipSuccess &&
+        ok = hipMemcpyAsync(nm.av, s->ms.av, on * 8, k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.filt, s->ms.filt, (size_t)s->cap * filt_stride(s->g->n), k, st) == hipSuccess &&
+             hipMemcpyAsync(nm.fpar, s->ms.fpar, (size_t)s->cap * sizeof(uint2), k, st) == hipSuccess &&
              hipMemcpyAsync(nm.done, s->ms.done, on * 4, k, st) == hipSuccess &&
-             hipMemcpyAsync(nm.stamp, s->ms.stamp, on * 4, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.fa, s->ms.fa, on * 4, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.l1, s->ms.l1, on * 4, k, st) == hipSuccess &&
              hipMemcpyAsync(nm.queue[0], s->ms.queue[0], on * 4, k, st) == hipSuccess &&

@@ -17,12 +17,15 @@
 //    on the tail's arrival once it is usable, so every out-edge is read at
 //    most once per query.  Claims are made with atomicMin, so concurrent
 //    claims never overlap.
-//  * writeMin is a device-scope atomicMin on uint32 arrival times.  Arrivals
-//    only decrease, so a stale plain read of arr[v] can only cause a
-//    redundant atomic, never a missed update; the tail's own arrival is read
-//    with an atomic load.
-//  * Each frontier vertex is enqueued at most once per round through a round
-//    stamp.  New entries are collected per wave in LDS and reserved in the
+//  * Each (query, vertex) owns one 64-bit word: its arrival in the high half
+//    and the stamp of the round that last lowered it in the low half.
+//    writeMin is one device-scope 64-bit atomicMin of (arrival, round stamp):
+//    it lowers the arrival and, in the same operation, tells whether this
+//    round already lowered it (then the vertex is already in the next
+//    frontier).  Stamps grow from round to round, so an equal arrival never
+//    replaces a newer stamp.  Arrivals only decrease, so a stale plain read
+//    of the arrival can only cause a redundant atomic, never a missed update.
+//  * New frontier entries are collected per wave in LDS and reserved in the
 //    global frontier with one atomicAdd per flush, since same-address atomics
 //    are serialised at the memory side.
 //  * Work is balanced inside a block by a prefix sum over the claimed range
@@ -54,9 +57,8 @@ struct TravArgs {
     const uint2 *st_in;      // in-edge {tail, departure}
     const uint4 *qp;         // per query {src, t_alpha, t_omega, sweep departure}
     uint32_t n;
-    uint32_t *arr;
+    unsigned long long *av;  // per (query, vertex): arrival << 32 | round stamp
     uint32_t *done;
-    uint32_t *stamp;
     uint32_t *fa;
     uint32_t *l1;
     const uint32_t *cur;
@@ -77,9 +79,45 @@ struct TravArgs {
     uint32_t nsteps;
     uint32_t dense;          // 1: walk all vertices, members have stamp == front_stamp
     uint32_t front_stamp;    // stamp value that marked the current frontier
-    uint8_t *filt;           // bucketed upper bounds of arr (null: no filter)
-    uint32_t fshift;         // bucket width 2^fshift
+    uint8_t *filt;           // packed arrival codes, filt_stride(n) bytes per query (null: none)
+    uint2 *fpar;             // per query: arrival-code parameters {base, shift | bits << 8}
+    uint32_t fbits;          // code width given to queries started by this launch (0: off)
+    uint32_t fstride;        // bytes per query region of filt
+    uint32_t max_a;          // largest arrival time in the graph
 };
+
+__device__ __forceinline__ uint32_t arrival_of(const unsigned long long *av, size_t i)
+{
+    return ((const uint32_t *)av)[2 * i + 1];
+}
+__device__ __forceinline__ uint32_t stamp_of(const unsigned long long *av, size_t i)
+{
+    return ((const uint32_t *)av)[2 * i];
+}
+__device__ __forceinline__ unsigned long long av_word(uint32_t arrival, uint32_t stamp)
+{
+    return ((unsigned long long)arrival << 32) | stamp;
+}
+
+// Arrival codes.  For a query with window [t_alpha, t_omega] and code width
+// B (2, 4 or 8 bits, L = 2^B - 1), code c < L of a vertex promises
+// arr <= t_alpha + (c + 1) * 2^shift, and c = L promises nothing; shift is
+// the smallest with 2^B * 2^shift >= min(t_omega, max arrival) - t_alpha, so
+// the L finite codes split the reachable range into 2^B equal parts.  An
+// edge arriving at or after the promised bound cannot improve its head and is
+// dropped without reading the arrival word.  Codes only decrease, and a code
+// is only ever stored from a real arrival of the vertex or copied from an
+// earlier read of the same byte, so every code read, however stale, is a
+// valid promise.
+__device__ __forceinline__ uint2 filter_params(uint32_t ta, uint32_t tw, uint32_t max_a, uint32_t bits)
+{
+    if (bits == 0) return make_uint2(0u, 0u);
+    const uint32_t hi = min(tw, max_a);
+    const uint64_t range = hi > ta ? (uint64_t)(hi - ta) : 1ull;
+    uint32_t sh = 0;
+    while (((1ull << bits) << sh) < range) ++sh;
+    return make_uint2(ta, sh | (bits << 8));
+}
 
 __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ a, uint32_t lo,
                                                     uint32_t hi, uint32_t key)
@@ -101,6 +139,7 @@ constexpr int UNR = 4;
 
 struct EdgeGroup {
     uint32_t v[UNR], a[UNR], q[UNR], tw[UNR], sd[UNR], cur[UNR];
+    uint32_t fb[UNR], fp[UNR];  // the query's arrival-code parameters
     bool ok[UNR];
 };
 
@@ -124,40 +163,63 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         G.ok[k] = G.ok[k] && G.a[k] <= G.tw[k];
         sv[k] = (size_t)G.q[k] * A.n + G.v[k];
     }
+    size_t fbyte[UNR];
+    uint32_t fsh[UNR];
     if (A.filt) {
-        // filt[v] = f promises arr[v] <= f * 2^fshift (f = 255: no promise),
-        // so an edge arriving at or after that bound cannot improve v; the
-        // filter is a quarter of arr's size and stays in cache far better
+        // the head's arrival code (see filter_params); at 2 bits per vertex
+        // the codes of 2^24 vertices take 4 MB and stay in L2, where the
+        // arrival words themselves (64 MB) do not
         uint32_t f[UNR];
 #pragma unroll
-        for (int k = 0; k < UNR; ++k) f[k] = A.filt[G.ok[k] ? sv[k] : 0];
+        for (int k = 0; k < UNR; ++k) {
+            const uint32_t bits = G.fp[k] >> 8;
+            const uint64_t bit = (uint64_t)G.q[k] * A.fstride * 8u + (uint64_t)G.v[k] * bits;
+            fbyte[k] = (size_t)(bit >> 3);
+            fsh[k] = (uint32_t)(bit & 7u);
+            f[k] = A.filt[G.ok[k] ? fbyte[k] : 0];
+        }
 #pragma unroll
-        for (int k = 0; k < UNR; ++k)  // the bound can exceed 32 bits (fshift up to 25)
-            G.ok[k] = G.ok[k] && (f[k] == 255u || (uint64_t)G.a[k] < ((uint64_t)f[k] << A.fshift));
+        for (int k = 0; k < UNR; ++k) {
+            const uint32_t L = (1u << (G.fp[k] >> 8)) - 1u;  // 0 when the query has no codes
+            const uint32_t c = (f[k] >> fsh[k]) & L;
+            // the bound can exceed 32 bits (c + 1 <= 255, shift <= 31)
+            const uint64_t bound = (uint64_t)G.fb[k] + ((uint64_t)(c + 1u) << (G.fp[k] & 31u));
+            G.ok[k] = G.ok[k] && (c == L || (uint64_t)G.a[k] < bound);
+        }
     }
 #pragma unroll
-    for (int k = 0; k < UNR; ++k) G.cur[k] = A.arr[G.ok[k] ? sv[k] : 0];
-    uint32_t old[UNR];
+    for (int k = 0; k < UNR; ++k) G.cur[k] = arrival_of(A.av, G.ok[k] ? sv[k] : 0);
+    unsigned long long old[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         G.ok[k] = G.ok[k] && G.a[k] < G.cur[k];
-        if (G.ok[k]) old[k] = atomicMin(&A.arr[sv[k]], G.a[k]);
+        if (G.ok[k]) old[k] = atomicMin(&A.av[sv[k]], av_word(G.a[k], A.stamp_val));
     }
     uint32_t st[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         nrelax += G.ok[k] ? (1ull << 32) : 0ull;  // high half: atomic attempts
-        G.ok[k] = G.ok[k] && G.a[k] < old[k];
+        G.ok[k] = G.ok[k] && G.a[k] < (uint32_t)(old[k] >> 32);
         nrelax += G.ok[k] ? 1ull : 0ull;
-        if (G.ok[k]) st[k] = atomicExch(&A.stamp[sv[k]], A.stamp_val);
+        if (G.ok[k]) st[k] = (uint32_t)old[k];  // stamp of the round that last lowered it
     }
     if (A.filt) {
-        // a plain byte store: a racing store of a later improvement's bound
-        // may win, which leaves a looser (still valid) bound
+        // plain byte read-modify-write: a racing store may put back an older
+        // (looser) code of this or a neighbouring vertex, which stays valid
 #pragma unroll
-        for (int k = 0; k < UNR; ++k)
-            if (G.ok[k])
-                A.filt[sv[k]] = (uint8_t)(((uint64_t)G.a[k] + (1ull << A.fshift) - 1ull) >> A.fshift);
+        for (int k = 0; k < UNR; ++k) {
+            const uint32_t bits = G.fp[k] >> 8;
+            if (G.ok[k] && bits) {
+                const uint32_t L = (1u << bits) - 1u, sh = G.fp[k] & 31u;
+                const uint64_t d = G.a[k] > G.fb[k] ? (uint64_t)(G.a[k] - G.fb[k]) : 0ull;
+                const uint32_t c = d ? (uint32_t)(((d + (1ull << sh) - 1ull) >> sh) - 1ull) : 0u;
+                if (c < L) {
+                    const uint32_t cur = A.filt[fbyte[k]];
+                    if (c < ((cur >> fsh[k]) & L))
+                        A.filt[fbyte[k]] = (uint8_t)((cur & ~(L << fsh[k])) | (c << fsh[k]));
+                }
+            }
+        }
     }
     if (SWEEP) {
 #pragma unroll
@@ -221,6 +283,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     __shared__ uint32_t s_q[TB];
     __shared__ uint32_t s_tw[TB];
     __shared__ uint32_t s_sd[TB];
+    __shared__ uint2 s_fp[TB];
     __shared__ uint32_t s_wsum[TB / 64];
     __shared__ uint32_t s_csum[TB / 64];
     __shared__ uint32_t s_cb;
@@ -244,19 +307,21 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     for (uint32_t base = blockIdx.x * TB; base < span; base += gridDim.x * TB) {
         const uint32_t i = base + tid;
         uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, nch = 0;
-        if (i < span && (!A.dense || A.stamp[i] == A.front_stamp)) {
+        uint2 fpq = make_uint2(0u, 0u);
+        if (i < span && (!A.dense || stamp_of(A.av, i) == A.front_stamp)) {
             ++n_items;
             const uint32_t item = A.dense ? i : A.cur[i];
             q = item / A.n;
             const uint32_t u = item - q * A.n;
             const uint4 p = A.qp[q];
+            fpq = A.fpar[q];
             tw = p.z;
             sd = p.w;
             const size_t su = (size_t)q * A.n + u;
             // Each (query, vertex) is expanded by one thread per round (round
             // stamps), and rounds are separate launches, so the tail's
             // arrival and its claim word need no atomics here.
-            const uint32_t r = A.arr[su];
+            const uint32_t r = arrival_of(A.av, su);
             const uint32_t b = A.off[u], e = A.off[u + 1];
             const uint32_t old = A.done[su];
             lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), r);
@@ -288,6 +353,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
         s_q[tid] = q;
         s_tw[tid] = tw;
         s_sd[tid] = sd;
+        s_fp[tid] = fpq;
         __syncthreads();
         uint32_t woff = 0, total = 0, coff = 0, ctotal = 0;
         for (int w2 = 0; w2 < TB / 64; ++w2) {
@@ -339,6 +405,9 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
                 G.q[k] = s_q[lo_k];
                 G.tw[k] = s_tw[lo_k];
                 G.sd[k] = s_sd[lo_k];
+                const uint2 f = s_fp[lo_k];
+                G.fb[k] = f.x;
+                G.fp[k] = f.y;
             }
             unsigned long long bal[UNR];
             uint32_t item[UNR];
@@ -360,6 +429,8 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
                 G.q[k] = q;
                 G.tw[k] = tw;
                 G.sd[k] = sd;
+                G.fb[k] = fpq.x;
+                G.fp[k] = fpq.y;
             }
             unsigned long long bal[UNR];
             uint32_t item[UNR];
@@ -397,6 +468,7 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
     for (uint32_t c = blockIdx.x * (TB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
         const uint4 ch = A.chunks[c];
         const uint4 p = A.qp[ch.x];
+        const uint2 fpq = A.fpar[ch.x];
         if (lane == 0) n_edges += ch.z;
         for (uint32_t k0 = 0; k0 < ch.z; k0 += 64 * UNR) {
             EdgeGroup G;
@@ -410,6 +482,8 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
                 G.q[k] = ch.x;
                 G.tw[k] = p.z;
                 G.sd[k] = p.w;
+                G.fb[k] = fpq.x;
+                G.fp[k] = fpq.y;
             }
             unsigned long long bal[UNR];
             uint32_t item[UNR];
@@ -510,6 +584,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
     __shared__ uint32_t s_q[TT];
     __shared__ uint32_t s_tw[TT];
     __shared__ uint32_t s_sd[TT];
+    __shared__ uint2 s_fp[TT];
     __shared__ uint32_t s_wsum[TT / 64];
     __shared__ uint32_t s_next;
     __shared__ uint32_t s_F;
@@ -536,8 +611,8 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                 const uint32_t sd = A.steps[s_step];
                 const uint32_t src = A.qp[0].x;
                 ((uint4 *)A.qp)[0].w = sd;
-                atomicMin(&A.arr[src], sd);
-                A.stamp[src] = A.stamp_val + rounds - 1u;  // mark of the coming round's frontier
+                // no relaxation runs now; the stamp marks the coming round's frontier
+                A.av[src] = av_word(min(arrival_of(A.av, src), sd), A.stamp_val + rounds - 1u);
                 (which ? q1 : q0)[0] = src;
                 s_sdep = sd;
                 s_step += 1;
@@ -576,16 +651,19 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
         for (uint32_t base = 0; base < F; base += TT) {
             const uint32_t i = base + tid;
             uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0;
+            uint2 fpq = make_uint2(0u, 0u);
             if (i < F) {
                 ++n_items;
                 const uint32_t item = B.cur[i];
                 q = item / A.n;
                 const uint32_t u = item - q * A.n;
                 const uint4 p = A.qp[q];
+                fpq = A.fpar[q];
                 tw = p.z;
                 sd = SWEEP ? s_sdep : p.w;
                 const size_t su = (size_t)q * A.n + u;
-                const uint32_t ru = __hip_atomic_load(&A.arr[su], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t ru = __hip_atomic_load((const uint32_t *)A.av + 2 * su + 1, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t b = A.off[u], e = A.off[u + 1];
                 const uint32_t old = A.done[su];
                 lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), ru);
@@ -606,6 +684,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
             s_q[tid] = q;
             s_tw[tid] = tw;
             s_sd[tid] = sd;
+            s_fp[tid] = fpq;
             __syncthreads();
             uint32_t woff = 0, total = 0;
             for (int w2 = 0; w2 < TT / 64; ++w2) {
@@ -637,6 +716,9 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                     G.q[k] = s_q[lo_k];
                     G.tw[k] = s_tw[lo_k];
                     G.sd[k] = s_sd[lo_k];
+                    const uint2 f = s_fp[lo_k];
+                    G.fb[k] = f.x;
+                    G.fp[k] = f.y;
                 }
                 unsigned long long bal[UNR];
                 uint32_t item[UNR];
@@ -700,16 +782,17 @@ __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
             if (v != p.x) {
                 ++n_verts;
                 const size_t sv = (size_t)q * A.n + v;
-                const uint32_t rv = A.arr[sv];
+                const uint32_t rv = arrival_of(A.av, sv);
                 const uint32_t lim = min(rv, p.z + 1u);
                 const uint32_t b = A.off_in[v], e = A.off_in[v + 1];
                 const uint32_t ub = lower_bound_u32(A.a_in, b, e, lim);
                 for (uint32_t k = b; k < ub; ++k) {
                     ++n_edges;
                     const uint2 st = A.st_in[k];
-                    if (st.y >= p.y && A.arr[(size_t)q * A.n + st.x] <= st.y) {
+                    if (st.y >= p.y && arrival_of(A.av, (size_t)q * A.n + st.x) <= st.y) {
                         const uint32_t a = A.a_in[k];
-                        A.arr[sv] = a;
+                        // single writer; the stamp gives frontier membership for dense rounds
+                        A.av[sv] = av_word(a, A.stamp_val);
                         ++n_relax;
                         if (SWEEP && p.w != INF) {
                             A.fa[sv] = min(A.fa[sv], a - p.w);
@@ -717,7 +800,6 @@ __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
                         }
                         push = true;
                         item = (uint32_t)sv;
-                        A.stamp[sv] = A.stamp_val;  // frontier membership for dense rounds
                         break;
                     }
                 }
@@ -746,8 +828,7 @@ __global__ void step_kernel(TravArgs A, uint32_t *queue)
     const uint32_t sd = A.steps[idx];
     const uint32_t src = A.qp[0].x;
     ((uint4 *)A.qp)[0].w = sd;
-    atomicMin(&A.arr[src], sd);
-    A.stamp[src] = A.front_stamp;
+    A.av[src] = av_word(min(arrival_of(A.av, src), sd), A.front_stamp);
     queue[0] = src;
     A.cnt[CNT_FRONT + A.round % 3u] = 1u;
     A.cnt[CNT_STEP] = idx + 1u;
@@ -760,9 +841,10 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const uint4 p = host_qp[q];
         ((uint4 *)A.qp)[q] = p;
+        A.fpar[q] = filter_params(p.y, p.z, A.max_a, A.fbits);
         const size_t ss = (size_t)q * A.n + p.x;
-        A.arr[ss] = src_arrival_from_w ? p.w : p.y;
-        A.stamp[ss] = A.front_stamp;  // a dense first round finds the source
+        // the stamp lets a dense first round find the source
+        A.av[ss] = av_word(src_arrival_from_w ? p.w : p.y, A.front_stamp);
         A.next[q] = (uint32_t)ss;  // `next` names the buffer read by the first round here
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -778,7 +860,8 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
 // Results back in caller ids: out[v] for caller vertex v from internal slot
 // perm[v].  kind 0 copies arrivals, 1 turns latest departure + 1 into latest
 // departure, 2 copies fastest durations; the source gets its convention.
-__global__ void finalize_sweep_kernel(uint32_t *out, const uint32_t *__restrict__ arr, const uint32_t *__restrict__ l1,
+__global__ void finalize_sweep_kernel(uint32_t *out, const unsigned long long *__restrict__ av,
+                                      const uint32_t *__restrict__ l1,
                                       const uint32_t *__restrict__ fa, const uint32_t *__restrict__ perm, uint32_t n,
                                       int kind, uint32_t src, uint32_t tw)
 {
@@ -786,7 +869,7 @@ __global__ void finalize_sweep_kernel(uint32_t *out, const uint32_t *__restrict_
         const uint32_t x = perm[v];
         uint32_t r;
         if (kind == 0)
-            r = arr[x];
+            r = arrival_of(av, x);
         else if (v == src)
             r = kind == 1 ? tw : 0u;
         else if (kind == 1)
@@ -843,15 +926,48 @@ int fill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t value)
     return KAIROS_OK;
 }
 
-// Arrival filter of `count` vertices: every byte 255 (no bound yet).  Done
-// whether or not the filter is switched on, so switching it on between
-// queries never exposes bounds of an earlier query.
-int fill_filter(kairos_graph *, hipStream_t st, uint8_t *filt, uint64_t count)
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t count, unsigned long long value)
 {
-    return fill(st, (uint32_t *)filt, (count + 3) / 4, 0xFFFFFFFFu);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
 }
 
-TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
+__global__ void clear_stamps_kernel(unsigned long long *p, uint64_t count)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] &= 0xFFFFFFFF00000000ull;
+}
+
+// Every arrival unreached (INF), every stamp 0 (older than any round).
+int fill_arrivals(hipStream_t st, unsigned long long *av, uint64_t count)
+{
+    if (!count) return KAIROS_OK;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_cap(count, 256 * 4, 8192)), dim3(256), 0, st, av, count,
+                       (unsigned long long)INF << 32);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// Stamps back to 0 with the arrivals kept (the stamp counter wrapped).
+int clear_stamps(hipStream_t st, unsigned long long *av, uint64_t count)
+{
+    if (!count) return KAIROS_OK;
+    hipLaunchKernelGGL(clear_stamps_kernel, dim3(grid_cap(count, 256 * 4, 8192)), dim3(256), 0, st, av, count);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// Arrival codes of `nq` query regions: every bit set (no bound yet).  Done
+// whether or not codes are switched on, so switching them on between queries
+// never exposes codes of an earlier query.
+int fill_filter(kairos_graph *g, hipStream_t st, uint8_t *filt, uint64_t nq)
+{
+    return fill(st, (uint32_t *)filt, nq * filt_stride(g->n) / 4, 0xFFFFFFFFu);
+}
+
+TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
 {
     TravArgs A{};
     A.off = g->off_out;
@@ -862,9 +978,8 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
     A.st_in = g->st_in;
     A.qp = s->qp;
     A.n = g->n;
-    A.arr = arr;
+    A.av = s->av;
     A.done = s->done;
-    A.stamp = s->stamp;
     A.fa = s->fa;
     A.l1 = s->l1;
     A.cnt = s->cnt;
@@ -876,15 +991,20 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t *arr, uint32_t nq)
     A.nq = nq;
     A.track_volume = g->tuning.pull_alpha ? 1u : 0u;
     A.max_t = g->max_t;
+    // skipping the codes is always valid: a query started with codes on
+    // finds them again, possibly looser, when they are switched back on
     A.filt = g->tuning.arrival_filter ? s->filt : nullptr;
-    A.fshift = g->fshift;
+    A.fpar = s->fpar;
+    A.fbits = g->tuning.arrival_filter;
+    A.fstride = (uint32_t)filt_stride(g->n);
+    A.max_a = g->max_a;
     return A;
 }
 
 uint32_t next_stamp(Slot *s, int *rc)
 {
     if (s->stamp_next >= 0xFFFFF000u) {
-        *rc = fill(s->stream, s->stamp, (uint64_t)s->qcap * s->n, 0u);
+        *rc = clear_stamps(s->stream, s->av, (uint64_t)s->qcap * s->n);
         s->stamp_next = 2;
     }
     return s->stamp_next++;
@@ -905,7 +1025,7 @@ int run_persistent(kairos_graph *g, Slot *s, TravArgs A, uint32_t *r, int *which
     }
     constexpr uint32_t kMaxRounds = 1u << 16;  // per launch; the host launches again if needed
     if (s->stamp_next >= 0xFFFFF000u - kMaxRounds) {
-        int rc = fill(st, s->stamp, (uint64_t)s->qcap * s->n, 0u);
+        int rc = clear_stamps(st, s->av, (uint64_t)s->qcap * s->n);
         if (rc) return rc;
         s->stamp_next = 2;
     }
@@ -974,7 +1094,7 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
         if (tu.tail_limit && F <= tu.tail_limit && !pulling) {
             constexpr uint32_t kMaxTail = 4096;
             if (s->stamp_next >= 0xFFFFF000u - kMaxTail) {
-                if ((rc = fill(st, s->stamp, (uint64_t)s->qcap * s->n, 0u))) return rc;
+                if ((rc = clear_stamps(st, s->av, (uint64_t)s->qcap * s->n))) return rc;
                 s->stamp_next = 2;
             }
             A.round = r;
@@ -1069,7 +1189,6 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     const size_t qn = (size_t)qcap * g->n;
     uint64_t *acct = &s->bytes;
     s->done = (uint32_t *)dev_alloc(qn * 4, acct);
-    s->stamp = (uint32_t *)dev_alloc(qn * 4, acct);
     s->queue[0] = (uint32_t *)dev_alloc(std::max<size_t>(qn, qcap) * 4, acct);
     s->queue[1] = (uint32_t *)dev_alloc(std::max<size_t>(qn, qcap) * 4, acct);
     const uint64_t per_q = g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
@@ -1084,15 +1203,16 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     s->cnt = (uint32_t *)dev_alloc(CNT_WORDS * 4, acct);
     s->bar = (uint32_t *)dev_alloc(BAR_WORDS * 4, acct);
     s->stats = (unsigned long long *)dev_alloc(ST_TOTAL_WORDS * 8, acct);
-    s->arr = (uint32_t *)dev_alloc(qn * 4, acct);
-    s->filt = (uint8_t *)dev_alloc((qn + 3) / 4 * 4, acct);
+    s->av = (unsigned long long *)dev_alloc(qn * 8, acct);
+    s->filt = (uint8_t *)dev_alloc((size_t)qcap * filt_stride(g->n), acct);
+    s->fpar = (uint2 *)dev_alloc((size_t)qcap * sizeof(uint2), acct);
     if (qcap == 1) {
         s->fa = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->l1 = (uint32_t *)dev_alloc((size_t)g->n * 4, acct);
         s->steps = (uint32_t *)dev_alloc((size_t)std::max<uint32_t>(g->max_out_degree, 1) * 4, acct);
     }
-    bool ok = s->done && s->stamp && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt && s->bar &&
-              s->stats && s->arr && s->filt && (qcap != 1 || (s->fa && s->l1 && s->steps));
+    bool ok = s->done && s->av && s->queue[0] && s->queue[1] && s->chunks && s->qp && s->cnt && s->bar &&
+              s->stats && s->filt && s->fpar && (qcap != 1 || (s->fa && s->l1 && s->steps));
     if (ok && hipHostMalloc((void **)&s->h_pin, 1024, hipHostMallocDefault) != hipSuccess) {
         s->h_pin = nullptr;
         ok = false;
@@ -1107,7 +1227,7 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
         }
     }
     if (ok) {
-        ok = hipMemsetAsync(s->stamp, 0, qn * 4, s->stream) == hipSuccess &&
+        ok = hipMemsetAsync(s->av, 0, qn * 8, s->stream) == hipSuccess &&
              hipMemsetAsync(s->cnt, 0, CNT_WORDS * 4, s->stream) == hipSuccess &&
              hipMemsetAsync(s->stats, 0, ST_TOTAL_WORDS * 8, s->stream) == hipSuccess &&
              hipStreamSynchronize(s->stream) == hipSuccess;
@@ -1189,15 +1309,15 @@ void slot_destroy(Slot *s)
     if (!s) return;
     if (s->stream) hipStreamSynchronize(s->stream);
     dev_free(s->done);
-    dev_free(s->stamp);
     dev_free(s->queue[0]);
     dev_free(s->queue[1]);
     dev_free(s->chunks);
     dev_free(s->qp);
     dev_free(s->cnt);
     dev_free(s->stats);
-    dev_free(s->arr);
+    dev_free(s->av);
     dev_free(s->filt);
+    dev_free(s->fpar);
     dev_free(s->bar);
     dev_free(s->fa);
     dev_free(s->l1);
@@ -1235,11 +1355,11 @@ void slot_release(kairos_graph *g, Slot *s)
 }
 
 // -------------------------------------------------------------- queries --
-static int start_queries(kairos_graph *g, Slot *s, uint32_t *arr, const uint4 *hqp, uint32_t nq,
-                         bool from_w, TravArgs &A, uint32_t &round)
+static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq, bool from_w, TravArgs &A,
+                         uint32_t &round)
 {
     hipStream_t st = s->stream;
-    A = make_args(g, s, arr, nq);
+    A = make_args(g, s, nq);
     round = 0;
     A.round = 0;
     A.next = s->queue[0];
@@ -1279,17 +1399,17 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
     int rc;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
-    if ((rc = fill(st, s->arr, g->n, INF))) return rc;
+    if ((rc = fill_arrivals(st, s->av, g->n))) return rc;
     if ((rc = fill(st, s->done, g->n, INF))) return rc;
-    if ((rc = fill_filter(g, st, s->filt, g->n))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, 1))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
     const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, s->arr, &qp, 1, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, &qp, 1, false, A, round))) return rc;
     if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
     prof_begin(g, st, &ev);
-    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->arr,
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->av,
                        s->l1, s->fa, g->perm, g->n, 0, src, tw);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
@@ -1304,20 +1424,20 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
     const uint64_t qn = (uint64_t)q * g->n;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
-    if ((rc = fill(st, s->arr, qn, INF))) return rc;
+    if ((rc = fill_arrivals(st, s->av, qn))) return rc;
     if ((rc = fill(st, s->done, qn, INF))) return rc;
-    if ((rc = fill_filter(g, st, s->filt, qn))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, q))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
     std::vector<uint4> hq(q);
     for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], ta[i]);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, s->arr, hq.data(), q, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, hq.data(), q, false, A, round))) return rc;
     if ((rc = run_rounds<false>(g, s, A, q, &round))) return rc;
     prof_begin(g, st, &ev);
     for (uint32_t i = 0; i < q; ++i)
         hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st,
-                           out + (size_t)i * g->n, s->arr + (size_t)i * g->n, s->l1, s->fa, g->perm, g->n, 0,
+                           out + (size_t)i * g->n, s->av + (size_t)i * g->n, s->l1, s->fa, g->perm, g->n, 0,
                            src[i], tw[i]);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
@@ -1361,9 +1481,9 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
     uint32_t *fa = s->fa;
     hipEvent_t ev;
     prof_begin(g, st, &ev);
-    if ((rc = fill(st, s->arr, g->n, INF))) return rc;
+    if ((rc = fill_arrivals(st, s->av, g->n))) return rc;
     if ((rc = fill(st, s->done, g->n, INF))) return rc;
-    if ((rc = fill_filter(g, st, s->filt, g->n))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, 1))) return rc;
     if ((rc = fill(st, fa, g->n, INF))) return rc;
     if ((rc = fill(st, l1, g->n, 0u))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
@@ -1372,7 +1492,7 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
         const uint4 qp = make_uint4(src, ta, tw, S[0]);
         TravArgs A;
         uint32_t r = 0;
-        if ((rc = start_queries(g, s, s->arr, &qp, 1, true, A, r))) return rc;
+        if ((rc = start_queries(g, s, &qp, 1, true, A, r))) return rc;
         A.fa = fa;
         A.l1 = l1;
         A.steps = s->steps;
@@ -1380,7 +1500,7 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
         if ((rc = run_rounds<true>(g, s, A, 1, &r))) return rc;
     }
     prof_begin(g, st, &ev);
-    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->arr,
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->av,
                        l1, fa, g->perm, g->n, kind, src_caller, tw);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
@@ -1436,9 +1556,12 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.batch_layout = g && g->m >= (1u << 22) ? 2u : 1u;
     t.tail_limit = 4096;
     t.dense_frontier = 0;
-    // the filter pays while its n bytes stay in a 4 MB L2; beyond that the
-    // extra random read costs more than the arrival reads it saves
-    t.arrival_filter = g && g->n <= (1u << 21) ? 1u : 0u;
+    // arrival codes add a dependent read in front of the arrival read; they
+    // only break even while the arrival words themselves nearly fit in L2
+    // (2^20 vertices: 0.866 against 0.870 ms per query); at 2^22 and 2^24
+    // vertices every width measured slower than none (2, 4, 8 bits:
+    // 5.88, 5.78, 5.75 ms against 5.13 ms per query at 2^24)
+    t.arrival_filter = g && g->n <= (1u << 21) ? 8u : 0u;
     return t;
 }
 
@@ -1451,8 +1574,11 @@ __global__ void inject_kernel(TravArgs A, const Inject *__restrict__ list, uint3
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         const Inject in = list[i];
         ((uint4 *)A.qp)[in.q] = make_uint4(in.src, in.ta, in.tw, in.sdep);
+        A.fpar[in.q] = filter_params(in.ta, in.tw, A.max_a, A.fbits);
         const size_t ss = (size_t)in.q * A.n + in.src;
-        A.arr[ss] = in.sdep == INF ? in.ta : in.sdep;
+        // stamp 0: older than every round's stamp, so the source's first
+        // improvement (a sweep step) still enqueues it
+        A.av[ss] = av_word(in.sdep == INF ? in.ta : in.sdep, 0u);
         const uint32_t pos = atomicAdd(&A.cnt[CNT_FRONT + A.round % 3u], 1u);
         A.next[pos] = (uint32_t)ss;  // `next` names the queue of the coming round here
     }
@@ -1465,12 +1591,14 @@ __global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list,
 {
     const size_t base = (size_t)list[blockIdx.y] * A.n;
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.n; v += gridDim.x * blockDim.x) {
-        A.arr[base + v] = INF;
+        A.av[base + v] = av_word(INF, 0u);
         A.done[base + v] = INF;
         A.fa[base + v] = INF;
         A.l1[base + v] = 0u;
-        filt[base + v] = 255u;
     }
+    uint32_t *fw = (uint32_t *)(filt + (size_t)list[blockIdx.y] * A.fstride);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < A.fstride / 4; i += gridDim.x * blockDim.x)
+        fw[i] = 0xFFFFFFFFu;
 }
 
 TravArgs multi_args(kairos_graph *g, MultiState *ms)
@@ -1484,9 +1612,8 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.st_in = g->st_in;
     A.qp = ms->qp;
     A.n = g->n;
-    A.arr = ms->arr;
+    A.av = ms->av;
     A.done = ms->done;
-    A.stamp = ms->stamp;
     A.fa = ms->fa;
     A.l1 = ms->l1;
     A.cnt = ms->cnt;
@@ -1501,8 +1628,13 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.cur = ms->queue[0];
     A.next = ms->queue[1];
     A.max_t = g->max_t;
+    // skipping the codes is always valid: a query started with codes on
+    // finds them again, possibly looser, when they are switched back on
     A.filt = g->tuning.arrival_filter ? ms->filt : nullptr;
-    A.fshift = g->fshift;
+    A.fpar = ms->fpar;
+    A.fbits = g->tuning.arrival_filter;
+    A.fstride = (uint32_t)filt_stride(g->n);
+    A.max_a = g->max_a;
     return A;
 }
 
@@ -1512,7 +1644,7 @@ int multi_push_round(kairos_graph *g, MultiState *ms)
 {
     TravArgs A = multi_args(g, ms);
     if (ms->stamp_next >= 0xFFFFF000u) {
-        int rc = fill(ms->stream, ms->stamp, (uint64_t)ms->qcap * ms->n, 0u);
+        int rc = clear_stamps(ms->stream, ms->av, (uint64_t)ms->qcap * ms->n);
         if (rc) return rc;
         ms->stamp_next = 2;
     }
@@ -1556,7 +1688,7 @@ int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32
 {
     const size_t base = (size_t)q * g->n;
     hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, ms->stream, out,
-                       ms->arr + base, ms->l1 + base, ms->fa + base, g->perm, g->n, kind, src, tw);
+                       ms->av + base, ms->l1 + base, ms->fa + base, g->perm, g->n, kind, src, tw);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;
 }

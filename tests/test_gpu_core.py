@@ -110,7 +110,10 @@ def test_ea_skewed(which):
 @pytest.mark.parametrize("tuning", [dict(split=64, chunk=64), dict(split=100000, chunk=4096),
                                     dict(rounds_per_sync=4), dict(rounds_per_sync=1), dict(pull_alpha=1, pull_beta=1000000),
                                     dict(pull_alpha=8, pull_beta=24), dict(arrival_filter=0),
-                                    dict(arrival_filter=0, tail_limit=0), dict(single_persistent=0),
+                                    dict(arrival_filter=0, tail_limit=0), dict(arrival_filter=2),
+                                    dict(arrival_filter=4), dict(arrival_filter=8, tail_limit=0),
+                                    dict(arrival_filter=2, tail_limit=0, dense_frontier=4),
+                                    dict(single_persistent=0),
                                     dict(single_persistent=1, tail_limit=0),
                                     dict(single_persistent=1, tail_limit=0, dense_frontier=4)])
 def test_ea_independent_of_tuning(tuning):
@@ -165,11 +168,11 @@ def test_tiny_all_kinds(seed):
     G.free()
 
 
-@pytest.mark.parametrize("filt", [0, 1])
+@pytest.mark.parametrize("filt", [0, 2, 4, 8])
 def test_late_timestamps_all_kinds(filt):
-    """Departures near the top of the u32 range: the arrival filter then uses
-    its widest buckets (2^24), where a bound times the bucket width comes
-    closest to overflowing."""
+    """Departures near the top of the u32 range and windows up to the whole
+    range: the arrival codes then use their widest parts (up to 2^31), where
+    a code's bound comes closest to overflowing 32 bits."""
     rng = np.random.Generator(np.random.PCG64(77))
     n, m = 300, 4000
     src = rng.integers(0, n, m, dtype=np.uint32)

@@ -55,10 +55,21 @@ def expected(se, kind, s, a, w):
     return (ea, ld, fa)[kind]
 
 
-@pytest.mark.parametrize("name,shift,t_lo,t_hi", [("uniform-10k", 0, 0, 99_999),
-                                                   ("rmat20-32m", 6, 0, (1 << 30) - 1)])
-def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi):
+@pytest.mark.parametrize("name,shift,t_lo,t_hi,codes", [("uniform-10k", 0, 0, 99_999, None),
+                                                         ("rmat20-32m", 6, 0, (1 << 30) - 1, None),
+                                                         ("rmat20-32m", 6, 0, (1 << 30) - 1, 2)])
+def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi, codes):
     g, G, se = graph(name, shift)
+    old = K.kairos_get_tuning(G)
+    if codes is not None:
+        K.kairos_set_tuning(G, arrival_filter=codes)
+    try:
+        _mixed_stream(g, G, se, t_lo, t_hi)
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+def _mixed_stream(g, G, se, t_lo, t_hi):
     count = 120
     src, ta, tw, kinds = mixed_queries(g, count, 7, t_lo, t_hi)
     outs = torch.full((count, g.n), 7, dtype=torch.int32, device="cuda")
