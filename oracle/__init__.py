@@ -16,6 +16,9 @@ Contents (each function names the passage of the paper it follows):
 * ``brute_force``            -- enumeration of all time-respecting walks
                                 (pure Python, tiny inputs only).
 * ``temporal_csr``           -- expected out/in temporal CSR (numpy lexsort).
+* ``paths.ea_predecessors``  -- last edge of an earliest-arrival path (numpy).
+* ``paths.min_hops``         -- temporal BFS: fewest edges within the window.
+* ``paths.brute_force_walks``-- enumeration pinning the two above.
 
 Reading of the paper used throughout (its text leaves these open or
 garbled; each is listed with its reason in the design notes):
