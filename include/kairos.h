@@ -115,6 +115,30 @@ int kairos_latest_departure(kairos_graph *g, uint32_t src, uint32_t t_alpha, uin
 int kairos_fastest(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
                    uint32_t *out);
 
+/* Earliest-arrival paths (the minimal temporal paths of §2.3 with the edge
+ * that realises each arrival).  out_arrival is as kairos_earliest_arrival.
+ * For every vertex v other than src with a finite arrival, the last edge
+ * (u, v, t, lambda) of an earliest-arrival path: among the usable edges into
+ * v with t + lambda = arrival[v] and arrival[u] <= t, the latest departure
+ * t, then the smallest u (edges equal in (u, v, t, lambda) are the same
+ * choice).  out_pred_tail[v] = u, out_pred_departure[v] = t; both INF for
+ * src and unreached vertices.  Following tails from any reached vertex ends
+ * at src (arrivals strictly decrease along them).
+ *   out_arrival, out_pred_tail, out_pred_departure  device, n uint32 each.
+ * Errors: INVALID (a null pointer), RANGE, NOMEM, DEVICE. */
+int kairos_earliest_arrival_path(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                                 uint32_t *out_arrival, uint32_t *out_pred_tail,
+                                 uint32_t *out_pred_departure);
+
+/* Temporal BFS (Table 4's T. BFS, restricted to the query interval as §6.1
+ * does for BFS): out_hops[v] = the fewest edges of a time-respecting path
+ * from src to v within [t_alpha, t_omega]; 0 for src, INF if unreachable.
+ * The rounds are level-synchronous: round r expands the frontier from the
+ * arrivals it had when r began, so the round that first reaches v is v's
+ * hop count.  out_hops: device, n uint32.  Errors as above. */
+int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                        uint32_t *out_hops);
+
 /* q earliest-arrival queries answered together.
  *   src, t_alpha, t_omega  host, q entries each.
  *   out                    device, q*n uint32, query-major (row i = query i).

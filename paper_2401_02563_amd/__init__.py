@@ -82,8 +82,9 @@ _sig("kairos_graph_build", _i32, _p, _p, _p, _p, _u64, _u32, _p, ctypes.POINTER(
 _sig("kairos_graph_free", None, _p)
 _sig("kairos_graph_stats", _i32, _p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
 _sig("kairos_graph_index", _i32, _p, ctypes.POINTER(kairos_index_view))
-for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest"):
+for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs"):
     _sig(_n, _i32, _p, _u32, _u32, _u32, _p)
+_sig("kairos_earliest_arrival_path", _i32, _p, _u32, _u32, _u32, _p, _p, _p)
 _sig("kairos_earliest_arrival_batch", _i32, _p, _u32, _p, _p, _p, _p)
 _sig("kairos_traversed_edges", _i32, _p, _u32, _u32, _p, ctypes.POINTER(_u64))
 _sig("kairos_get_tuning", _i32, _p, ctypes.POINTER(kairos_tuning))
@@ -223,6 +224,20 @@ def kairos_latest_departure(g: Graph, src: int, t_alpha: int, t_omega: int, out:
 
 def kairos_fastest(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
     return _single("kairos_fastest", g, src, t_alpha, t_omega, out)
+
+
+def kairos_temporal_bfs(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
+    return _single("kairos_temporal_bfs", g, src, t_alpha, t_omega, out)
+
+
+def kairos_earliest_arrival_path(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor,
+                                 pred_tail: torch.Tensor, pred_departure: torch.Tensor):
+    p = [_dev_ptr(x, g.n, w) for x, w in ((out, "out"), (pred_tail, "pred_tail"),
+                                          (pred_departure, "pred_departure"))]
+    _sync()
+    _check(_L.kairos_earliest_arrival_path(g.handle, int(src), int(t_alpha), int(t_omega), *p),
+           "kairos_earliest_arrival_path")
+    return out, pred_tail, pred_departure
 
 
 def _host_u32(a):

@@ -156,15 +156,23 @@ static int check_query(const kairos_graph *g, uint32_t src, uint32_t ta, uint32_
     return KAIROS_OK;
 }
 
-static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+// kind 0 earliest arrival, 1 latest departure, 2 fastest, 3 earliest
+// arrival with predecessors (out2, out3), 4 temporal BFS hop counts
+static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                        uint32_t *out2 = nullptr, uint32_t *out3 = nullptr)
 {
-    if (!g || !out) return KAIROS_ERR_INVALID;
+    if (!g || !out || (kind == 3 && (!out2 || !out3))) return KAIROS_ERR_INVALID;
     (void)hipGetLastError();  // errors of unrelated earlier calls on this thread are not ours
     int rc = check_query(g, src, ta, tw);
     if (rc) return rc;
     Slot *s = nullptr;
-    if ((rc = slot_acquire(g, 1, kind != 0, &s))) return rc;
-    rc = kind == 0 ? run_earliest_arrival(g, s, src, ta, tw, out) : run_sweep(g, s, kind, src, ta, tw, out);
+    if ((rc = slot_acquire(g, 1, kind == 1 || kind == 2, &s))) return rc;
+    switch (kind) {
+    case 0: rc = run_earliest_arrival(g, s, src, ta, tw, out); break;
+    case 3: rc = run_earliest_arrival_path(g, s, src, ta, tw, out, out2, out3); break;
+    case 4: rc = run_temporal_bfs(g, s, src, ta, tw, out); break;
+    default: rc = run_sweep(g, s, kind, src, ta, tw, out); break;
+    }
     if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
     if (rc == KAIROS_OK) {
         slot_release(g, s);
@@ -188,6 +196,17 @@ int kairos_latest_departure(kairos_graph *g, uint32_t src, uint32_t t_alpha, uin
 int kairos_fastest(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out)
 {
     return single_query(g, 2, src, t_alpha, t_omega, out);
+}
+
+int kairos_earliest_arrival_path(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                                 uint32_t *out_arrival, uint32_t *out_pred_tail, uint32_t *out_pred_departure)
+{
+    return single_query(g, 3, src, t_alpha, t_omega, out_arrival, out_pred_tail, out_pred_departure);
+}
+
+int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out_hops)
+{
+    return single_query(g, 4, src, t_alpha, t_omega, out_hops);
 }
 
 int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,

@@ -153,6 +153,9 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
                          uint32_t *out);
 int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uint32_t tw,
               uint32_t *out);
+int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                              uint32_t *pred_tail, uint32_t *pred_dep);
+int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out);
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
               const uint32_t *tw, uint32_t *out);
 int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);

@@ -84,6 +84,11 @@ struct TravArgs {
     uint32_t fbits;          // code width given to queries started by this launch (0: off)
     uint32_t fstride;        // bytes per query region of filt
     uint32_t max_a;          // largest arrival time in the graph
+    // level-synchronous rounds (temporal BFS): the tails of round r expand
+    // from their arrivals at the start of r, snap[i] for frontier entry i,
+    // and a vertex first reached in round r gets hop[v] = r + 1
+    uint32_t *snap;
+    uint32_t *hop;
 };
 
 __device__ __forceinline__ uint32_t arrival_of(const unsigned long long *av, size_t i)
@@ -202,6 +207,8 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         G.ok[k] = G.ok[k] && G.a[k] < (uint32_t)(old[k] >> 32);
         nrelax += G.ok[k] ? 1ull : 0ull;
         if (G.ok[k]) st[k] = (uint32_t)old[k];  // stamp of the round that last lowered it
+        // the one atomic that finds the vertex unreached sets its level
+        if (A.hop && G.ok[k] && (uint32_t)(old[k] >> 32) == INF) A.hop[sv[k]] = A.round + 1u;
     }
     if (A.filt) {
         // plain byte read-modify-write: a racing store may put back an older
@@ -321,7 +328,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             // Each (query, vertex) is expanded by one thread per round (round
             // stamps), and rounds are separate launches, so the tail's
             // arrival and its claim word need no atomics here.
-            const uint32_t r = arrival_of(A.av, su);
+            const uint32_t r = A.snap ? A.snap[i] : arrival_of(A.av, su);
             const uint32_t b = A.off[u], e = A.off[u + 1];
             const uint32_t old = A.done[su];
             lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), r);
@@ -646,6 +653,13 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
         B.round = r;
         B.stamp_val = A.stamp_val + rounds;
         B.track_volume = 0;
+        if (A.snap) {
+            // level-synchronous rounds: arrivals of the frontier before any
+            // relaxation of this round
+            for (uint32_t i = tid; i < F; i += TT)
+                A.snap[i] = __hip_atomic_load((const uint32_t *)A.av + 2 * (size_t)B.cur[i] + 1, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (tid == 0) s_next = 0;
         __syncthreads();
         for (uint32_t base = 0; base < F; base += TT) {
@@ -662,8 +676,9 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                 tw = p.z;
                 sd = SWEEP ? s_sdep : p.w;
                 const size_t su = (size_t)q * A.n + u;
-                const uint32_t ru = __hip_atomic_load((const uint32_t *)A.av + 2 * su + 1, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t ru = A.snap ? A.snap[i]
+                                           : __hip_atomic_load((const uint32_t *)A.av + 2 * su + 1, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t b = A.off[u], e = A.off[u + 1];
                 const uint32_t old = A.done[su];
                 lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), ru);
@@ -859,7 +874,8 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
 
 // Results back in caller ids: out[v] for caller vertex v from internal slot
 // perm[v].  kind 0 copies arrivals, 1 turns latest departure + 1 into latest
-// departure, 2 copies fastest durations; the source gets its convention.
+// departure, 2 copies fastest durations, 3 copies hop counts (kept in the
+// fastest array); the source gets its convention.
 __global__ void finalize_sweep_kernel(uint32_t *out, const unsigned long long *__restrict__ av,
                                       const uint32_t *__restrict__ l1,
                                       const uint32_t *__restrict__ fa, const uint32_t *__restrict__ perm, uint32_t n,
@@ -871,12 +887,59 @@ __global__ void finalize_sweep_kernel(uint32_t *out, const unsigned long long *_
         if (kind == 0)
             r = arrival_of(av, x);
         else if (v == src)
-            r = kind == 1 ? tw : 0u;
+            r = kind == 1 ? tw : 0u;  // hops of the source: 0
         else if (kind == 1)
             r = l1[x] ? l1[x] - 1u : INF;
         else
             r = fa[x];
         out[v] = r;
+    }
+}
+
+// Level-synchronous rounds: the frontier's arrivals before the round starts.
+__global__ void snapshot_kernel(TravArgs A)
+{
+    const uint32_t F = A.cnt[CNT_FRONT + A.round % 3u];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < F; i += gridDim.x * blockDim.x)
+        A.snap[i] = arrival_of(A.av, A.cur[i]);
+}
+
+// Last edge of an earliest-arrival path into every vertex, from finished
+// arrivals.  The in-edges of x arriving exactly at its arrival are one block
+// of the in-index (ordered by arrival, then departure), found by binary
+// search; scanning it from the latest departure down, the first edge whose
+// tail had arrived by its departure fixes the departure, and among the edges
+// leaving at that time the smallest caller tail id is taken.  Results are in
+// caller ids; INF for the source and unreached vertices.
+__global__ void predecessor_kernel(const unsigned long long *__restrict__ av, const uint32_t *__restrict__ off_in,
+                                   const uint32_t *__restrict__ a_in, const uint2 *__restrict__ st_in,
+                                   const uint32_t *__restrict__ inv, uint32_t n, uint32_t src, uint32_t ta,
+                                   uint32_t *pred_tail, uint32_t *pred_dep)
+{
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) {
+        const uint32_t a = arrival_of(av, x);
+        uint32_t bt = INF, bc = INF;
+        if (a != INF && x != src) {
+            const uint32_t b = off_in[x], e = off_in[x + 1];
+            const uint32_t lo = lower_bound_u32(a_in, b, e, a);
+            const uint32_t hi = lower_bound_u32(a_in, lo, e, a + 1u);  // a <= TMAX: no wrap
+            for (uint32_t k = hi; k > lo; --k) {
+                const uint2 st = st_in[k - 1];
+                if (bt != INF && st.y < bt) break;
+                if (st.y >= ta && arrival_of(av, st.x) <= st.y) {
+                    const uint32_t cu = inv[st.x];
+                    if (bt == INF) {
+                        bt = st.y;
+                        bc = cu;
+                    } else {
+                        bc = min(bc, cu);
+                    }
+                }
+            }
+        }
+        const uint32_t c = inv[x];
+        pred_tail[c] = bc;
+        pred_dep[c] = bt;
     }
 }
 
@@ -1079,7 +1142,11 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
     const uint64_t total_v = (uint64_t)A.nq * g->n;
     int rc = KAIROS_OK;
     uint32_t step = (SWEEP && A.steps) ? 1u : 0u;  // host mirror of CNT_STEP
-    bool persist = tu.single_persistent != 0;
+    // level-synchronous rounds take a snapshot between rounds, so they run
+    // one push and one chunk launch per round (no pull, no dense walk, no
+    // rounds inside one cooperative launch)
+    const bool levels = A.snap != nullptr;
+    bool persist = tu.single_persistent != 0 && !levels;
     const uint32_t stop = tu.tail_limit;  // persistent launches leave small frontiers to the tail kernel
     for (;;) {
         if (F == 0) {
@@ -1134,7 +1201,7 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
             A.cur = s->queue[which];
             A.next = s->queue[which ^ 1];
             hipEvent_t ev;
-            if (k == 0 && tu.pull_alpha) {
+            if (k == 0 && tu.pull_alpha && !levels) {
                 // direction choice from the last read-back
                 if (!pulling && vol > (uint64_t)g->m * A.nq / tu.pull_alpha) pulling = true;
                 else if (pulling && (uint64_t)F * std::max<uint32_t>(tu.pull_beta, 1) < total_v) pulling = false;
@@ -1146,11 +1213,14 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
                 prof_end(g, st, KAIROS_K_PULL, ev);
             } else {
                 // dense walk when the frontier is a large share of the vertices
-                A.dense = (A.nq == 1 && tu.dense_frontier && k == 0 &&
+                A.dense = (A.nq == 1 && tu.dense_frontier && k == 0 && !levels &&
                            (uint64_t)F * tu.dense_frontier >= g->n) ? 1u : 0u;
                 A.front_stamp = A.stamp_val - 1u;
                 const int pg = A.dense ? grid_cap(g->n, TB, spec_grid)
                                        : (k == 0 ? grid_cap(F, TB, spec_grid) : spec_grid);
+                if (levels)
+                    hipLaunchKernelGGL(snapshot_kernel, dim3(k == 0 ? grid_cap(F, 256, spec_grid) : chunk_grid),
+                                       dim3(256), 0, st, A);
                 prof_begin(g, st, &ev);
                 hipLaunchKernelGGL(push_kernel<SWEEP>, dim3(pg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_PUSH, ev);
@@ -1411,6 +1481,49 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
     prof_begin(g, st, &ev);
     hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->av,
                        s->l1, s->fa, g->perm, g->n, 0, src, tw);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    return read_stats(g, s);
+}
+
+int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                              uint32_t *pred_tail, uint32_t *pred_dep)
+{
+    int rc = run_earliest_arrival(g, s, src, ta, tw, out);
+    if (rc) return rc;
+    hipEvent_t ev;
+    prof_begin(g, s->stream, &ev);
+    hipLaunchKernelGGL(predecessor_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, s->stream, s->av,
+                       g->off_in, g->a_in, g->st_in, g->inv, g->n, g->h_perm[src], ta, pred_tail, pred_dep);
+    prof_end(g, s->stream, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// Temporal BFS: level-synchronous rounds from the source; the round that
+// first reaches a vertex gives its hop count (kept in the slot's fastest
+// array; the latest-departure array holds the frontier snapshots).
+int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+{
+    hipStream_t st = s->stream;
+    int rc;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = fill_arrivals(st, s->av, g->n))) return rc;
+    if ((rc = fill(st, s->done, g->n, INF))) return rc;
+    if ((rc = fill_filter(g, st, s->filt, 1))) return rc;
+    if ((rc = fill(st, s->fa, g->n, INF))) return rc;
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
+    TravArgs A;
+    uint32_t round;
+    if ((rc = start_queries(g, s, &qp, 1, false, A, round))) return rc;
+    A.hop = s->fa;
+    A.snap = s->l1;
+    if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->av,
+                       s->l1, s->fa, g->perm, g->n, 3, src, tw);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
     return read_stats(g, s);
