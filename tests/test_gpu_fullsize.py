@@ -68,6 +68,27 @@ def test_rmat20_single_and_sweeps():
         assert np.array_equal(K.as_u32(one), pf), q
 
 
+def test_rmat20_paths_and_hops():
+    """Predecessors and temporal BFS hop counts on the full scale-20 graph
+    (two queries; the level-by-level hop oracle takes seconds per query)."""
+    from oracle import paths as P
+    g, G, se = load("rmat20-32m")
+    srcs, ta, tw = make_queries("rmat20-32m", g)
+    out, pt, pd = (torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(3))
+    for q in (0, 5):
+        s, a, w = int(srcs[q]), int(ta[q]), int(tw[q])
+        print("case: paths", q, flush=True)
+        K.kairos_earliest_arrival_path(G, s, a, w, out, pt, pd)
+        want = O.earliest_arrival(se, s, a, w)
+        assert np.array_equal(K.as_u32(out), want)
+        wt, wd = P.ea_predecessors(g.n, g.src, g.dst, g.t, g.lam, s, a, w, want)
+        assert np.array_equal(K.as_u32(pt), wt) and np.array_equal(K.as_u32(pd), wd)
+        print("case: hops", q, flush=True)
+        K.kairos_temporal_bfs(G, s, a, w, out)
+        wh, _ = P.min_hops(g.n, g.src, g.dst, g.t, g.lam, s, a, w)
+        assert np.array_equal(K.as_u32(out), wh)
+
+
 @pytest.mark.skipif(not FULL, reason="set KAIROS_FULL_SIZE=1 (minutes of host time)")
 @pytest.mark.parametrize("name,kind", [("rmat22-256m", "batch"), ("rmat24-512m", "single"),
                                        ("bursty22-1b", "single")])

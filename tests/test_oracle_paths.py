@@ -41,7 +41,7 @@ def rule_pick(pairs):
 @given(tiny_cases())
 def test_predecessors_and_hops_match_enumeration(case):
     n, edges, s, ta, tw = case
-    bea, last, bhops = P.brute_force_walks(n, edges, s, ta, tw)
+    bea, last, bhops, _, _ = P.brute_force_walks(n, edges, s, ta, tw)
     src, dst, t, lam = arrays(edges)
     se = O.sort_by_departure(n, src, dst, t, lam)
     ea = O.earliest_arrival(se, s, ta, tw)
@@ -129,6 +129,9 @@ MUTATIONS = [
      "nxt = cur\n        np.minimum.at(nxt, dst[ok], a[ok])\n        cur = cur.copy()"),  # same-level chaining
     ("hops[new] = h", "hops[new] = h + 1"),                              # off by one
     ("(a <= t_omega)", "(a < t_omega)"),                                  # open window end
+    ("(src == source) | (not strict)", "(not strict)"),                   # strict first edge
+    ("cur[src] <= t, cur[src] < t)", "cur[src] <= t, cur[src] <= t)"),    # strictness ignored
+    ("ld[r] = s", "ld[r] = np.maximum(ld[r], s)"),                        # INF taken as a departure
 ]
 
 
@@ -152,13 +155,49 @@ def test_planted_mutations_are_caught(old, new):
                   int(rng.integers(1, 4))) for _ in range(m)]
         s, ta = int(rng.integers(0, n)), int(rng.integers(0, 4))
         tw = int(rng.integers(ta, 14))
-        bea, last, bhops = P.brute_force_walks(n, edges, s, ta, tw)
+        bea, last, bhops, _, _ = P.brute_force_walks(n, edges, s, ta, tw)
+        sea, _, shops, sld, sfa = P.brute_force_walks(n, edges, s, ta, tw, strict=True)
         src, dst, t, lam = arrays(edges)
         ea = np.array(bea, np.uint32)
         pt, pd = mod.ea_predecessors(n, src, dst, t, lam, s, ta, tw, ea)
         hops, hea = mod.min_hops(n, src, dst, t, lam, s, ta, tw)
+        h2, e2 = mod.min_hops(n, src, dst, t, lam, s, ta, tw, True)
+        l2, f2 = mod.strict_sweep(n, src, dst, t, lam, s, ta, tw, True)
         if any((int(pt[v]), int(pd[v])) != rule_pick(last[v]) for v in range(n)) or \
-                list(hops) != bhops or list(hea) != bea:
+                list(hops) != bhops or list(hea) != bea or list(h2) != shops or list(e2) != sea or \
+                list(l2) != sld or list(f2) != sfa:
             caught = True
             break
     assert caught
+
+
+@settings(max_examples=1000, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_cases(), st.booleans())
+def test_succession_predicates_match_enumeration(case, strict):
+    """Both predicates of §2.2: earliest arrival and hops from the level
+    iteration, latest departure and fastest from the cross-route sweep, all
+    against walk enumeration; without strictness also against the C profile
+    scan (an independent route)."""
+    n, edges, s, ta, tw = case
+    bea, _, bhops, bld, bfa = P.brute_force_walks(n, edges, s, ta, tw, strict)
+    src, dst, t, lam = arrays(edges)
+    hops, ea = P.min_hops(n, src, dst, t, lam, s, ta, tw, strict)
+    assert list(ea) == bea and list(hops) == bhops
+    ld, fa = P.strict_sweep(n, src, dst, t, lam, s, ta, tw, strict)
+    assert list(ld) == bld and list(fa) == bfa
+    if not strict:
+        pea, pld, pf = O.profile(O.sort_by_departure(n, src, dst, t, lam), s, ta, tw)
+        assert list(pld) == bld and list(pf) == bfa
+
+
+def test_strict_hand_worked():
+    # 0 -(t=1, a=2)-> 1 -(t=2, a=3)-> 2 and 1 -(t=3, a=5)-> 2; window [1, 10].
+    # Succeeds: 2 at 3 over the edge leaving at 1's arrival.  Strictly
+    # succeeds: that edge is too early, 2 at 5.  The source's edge leaving at
+    # t_alpha = 1 is usable under both.
+    n, edges = 3, [(0, 1, 1, 1), (1, 2, 2, 1), (1, 2, 3, 2)]
+    src, dst, t, lam = arrays(edges)
+    assert P.min_hops(n, src, dst, t, lam, 0, 1, 10)[1].tolist() == [1, 2, 3]
+    assert P.min_hops(n, src, dst, t, lam, 0, 1, 10, strict=True)[1].tolist() == [1, 2, 5]
+    ld, fa = P.strict_sweep(n, src, dst, t, lam, 0, 1, 10, strict=True)
+    assert ld.tolist() == [10, 1, 1] and fa.tolist() == [0, 1, 4]
