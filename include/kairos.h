@@ -139,6 +139,28 @@ int kairos_earliest_arrival_path(kairos_graph *g, uint32_t src, uint32_t t_alpha
 int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
                         uint32_t *out_hops);
 
+/* One single-source query of a given kind under a chosen succession
+ * predicate (§2.2: TemporalEdgeMap takes the predicate as a parameter).
+ *   kind   KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST
+ *          or KAIROS_TEMPORAL_BFS; out as for the matching call above.
+ *   flags  0: consecutive edges "Succeeds" (next departure >= previous
+ *          arrival), as every other call here; KAIROS_STRICT: "Strictly
+ *          succeeds" (next departure > previous arrival).  Under both, the
+ *          first edge of a path (it has no predecessor) needs only
+ *          t >= t_alpha, or t >= s when a latest-departure / fastest sweep
+ *          starts the source at s.
+ * Errors: INVALID (unknown kind or flag bit, null pointer), RANGE, NOMEM,
+ * DEVICE. */
+enum {
+    KAIROS_EARLIEST_ARRIVAL = 0,
+    KAIROS_LATEST_DEPARTURE = 1,
+    KAIROS_FASTEST = 2,
+    KAIROS_TEMPORAL_BFS = 3
+};
+#define KAIROS_STRICT 1u
+int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha,
+                 uint32_t t_omega, uint32_t *out);
+
 /* q earliest-arrival queries answered together.
  *   src, t_alpha, t_omega  host, q entries each.
  *   out                    device, q*n uint32, query-major (row i = query i).

@@ -85,6 +85,9 @@ _sig("kairos_graph_index", _i32, _p, ctypes.POINTER(kairos_index_view))
 for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs"):
     _sig(_n, _i32, _p, _u32, _u32, _u32, _p)
 _sig("kairos_earliest_arrival_path", _i32, _p, _u32, _u32, _u32, _p, _p, _p)
+_sig("kairos_query", _i32, _p, _i32, _u32, _u32, _u32, _u32, _p)
+KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST, KAIROS_TEMPORAL_BFS = 0, 1, 2, 3
+KAIROS_STRICT = 1
 _sig("kairos_earliest_arrival_batch", _i32, _p, _u32, _p, _p, _p, _p)
 _sig("kairos_traversed_edges", _i32, _p, _u32, _u32, _p, ctypes.POINTER(_u64))
 _sig("kairos_get_tuning", _i32, _p, ctypes.POINTER(kairos_tuning))
@@ -228,6 +231,15 @@ def kairos_fastest(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Te
 
 def kairos_temporal_bfs(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
     return _single("kairos_temporal_bfs", g, src, t_alpha, t_omega, out)
+
+
+def kairos_query(g: Graph, kind: int, src: int, t_alpha: int, t_omega: int, out: torch.Tensor,
+                 strict: bool = False):
+    p = _dev_ptr(out, g.n, "out")
+    _sync()
+    _check(_L.kairos_query(g.handle, int(kind), KAIROS_STRICT if strict else 0, int(src), int(t_alpha),
+                           int(t_omega), p), "kairos_query")
+    return out
 
 
 def kairos_earliest_arrival_path(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor,

@@ -159,7 +159,7 @@ static int check_query(const kairos_graph *g, uint32_t src, uint32_t ta, uint32_
 // kind 0 earliest arrival, 1 latest departure, 2 fastest, 3 earliest
 // arrival with predecessors (out2, out3), 4 temporal BFS hop counts
 static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
-                        uint32_t *out2 = nullptr, uint32_t *out3 = nullptr)
+                        uint32_t *out2 = nullptr, uint32_t *out3 = nullptr, bool strict = false)
 {
     if (!g || !out || (kind == 3 && (!out2 || !out3))) return KAIROS_ERR_INVALID;
     (void)hipGetLastError();  // errors of unrelated earlier calls on this thread are not ours
@@ -168,10 +168,10 @@ static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, ui
     Slot *s = nullptr;
     if ((rc = slot_acquire(g, 1, kind == 1 || kind == 2, &s))) return rc;
     switch (kind) {
-    case 0: rc = run_earliest_arrival(g, s, src, ta, tw, out); break;
+    case 0: rc = run_earliest_arrival(g, s, src, ta, tw, out, strict); break;
     case 3: rc = run_earliest_arrival_path(g, s, src, ta, tw, out, out2, out3); break;
-    case 4: rc = run_temporal_bfs(g, s, src, ta, tw, out); break;
-    default: rc = run_sweep(g, s, kind, src, ta, tw, out); break;
+    case 4: rc = run_temporal_bfs(g, s, src, ta, tw, out, strict); break;
+    default: rc = run_sweep(g, s, kind, src, ta, tw, out, strict); break;
     }
     if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
     if (rc == KAIROS_OK) {
@@ -207,6 +207,16 @@ int kairos_earliest_arrival_path(kairos_graph *g, uint32_t src, uint32_t t_alpha
 int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out_hops)
 {
     return single_query(g, 4, src, t_alpha, t_omega, out_hops);
+}
+
+int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                 uint32_t *out)
+{
+    if ((flags & ~(uint32_t)KAIROS_STRICT) != 0) return KAIROS_ERR_INVALID;
+    static const int internal[] = {0, 1, 2, 4};  // EA, LD, F, temporal BFS
+    if (kind < KAIROS_EARLIEST_ARRIVAL || kind > KAIROS_TEMPORAL_BFS) return KAIROS_ERR_INVALID;
+    return single_query(g, internal[kind], src, t_alpha, t_omega, out, nullptr, nullptr,
+                        (flags & KAIROS_STRICT) != 0);
 }
 
 int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,

@@ -149,13 +149,16 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
 int slot_acquire(kairos_graph *g, uint32_t qcap, bool sweep, Slot **out);
 void slot_release(kairos_graph *g, Slot *s);
 void slot_destroy(Slot *s);
+// strict: consecutive edges follow "Strictly succeeds" (§2.2) instead of
+// "Succeeds"
 int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw,
-                         uint32_t *out);
+                         uint32_t *out, bool strict = false);
 int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src, uint32_t ta, uint32_t tw,
-              uint32_t *out);
+              uint32_t *out, bool strict = false);
 int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
                               uint32_t *pred_tail, uint32_t *pred_dep);
-int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out);
+int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                     bool strict = false);
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
               const uint32_t *tw, uint32_t *out);
 int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);

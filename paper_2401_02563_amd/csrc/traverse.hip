@@ -89,7 +89,23 @@ struct TravArgs {
     // and a vertex first reached in round r gets hop[v] = r + 1
     uint32_t *snap;
     uint32_t *hop;
+    uint32_t strict;         // succession of queries started by this launch (1: "Strictly succeeds")
 };
+
+// Per-query parameter word fpar.y: code shift (bits 0-7), code width (bits
+// 8-15), strict succession (bit 16).
+__device__ __forceinline__ uint32_t fp_bits(uint32_t fp) { return (fp >> 8) & 0xFFu; }
+__device__ __forceinline__ uint32_t fp_strict(uint32_t fp) { return (fp >> 16) & 1u; }
+
+// Key of the binary search for the first usable out-edge of tail u reached
+// at r: "Succeeds" allows departures at r, "Strictly succeeds" from r + 1.
+// The source's own edges need only t >= its start under either predicate
+// (the first edge of a path has no predecessor).  r <= TMAX, so r + 1 does
+// not wrap.
+__device__ __forceinline__ uint32_t departure_key(uint32_t r, uint32_t fp, uint32_t u, uint32_t src)
+{
+    return r + (fp_strict(fp) && u != src ? 1u : 0u);
+}
 
 __device__ __forceinline__ uint32_t arrival_of(const unsigned long long *av, size_t i)
 {
@@ -177,7 +193,7 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         uint32_t f[UNR];
 #pragma unroll
         for (int k = 0; k < UNR; ++k) {
-            const uint32_t bits = G.fp[k] >> 8;
+            const uint32_t bits = fp_bits(G.fp[k]);
             const uint64_t bit = (uint64_t)G.q[k] * A.fstride * 8u + (uint64_t)G.v[k] * bits;
             fbyte[k] = (size_t)(bit >> 3);
             fsh[k] = (uint32_t)(bit & 7u);
@@ -185,7 +201,7 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         }
 #pragma unroll
         for (int k = 0; k < UNR; ++k) {
-            const uint32_t L = (1u << (G.fp[k] >> 8)) - 1u;  // 0 when the query has no codes
+            const uint32_t L = (1u << fp_bits(G.fp[k])) - 1u;  // 0 when the query has no codes
             const uint32_t c = (f[k] >> fsh[k]) & L;
             // the bound can exceed 32 bits (c + 1 <= 255, shift <= 31)
             const uint64_t bound = (uint64_t)G.fb[k] + ((uint64_t)(c + 1u) << (G.fp[k] & 31u));
@@ -215,7 +231,7 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
         // (looser) code of this or a neighbouring vertex, which stays valid
 #pragma unroll
         for (int k = 0; k < UNR; ++k) {
-            const uint32_t bits = G.fp[k] >> 8;
+            const uint32_t bits = fp_bits(G.fp[k]);
             if (G.ok[k] && bits) {
                 const uint32_t L = (1u << bits) - 1u, sh = G.fp[k] & 31u;
                 const uint64_t d = G.a[k] > G.fb[k] ? (uint64_t)(G.a[k] - G.fb[k]) : 0ull;
@@ -331,7 +347,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             const uint32_t r = A.snap ? A.snap[i] : arrival_of(A.av, su);
             const uint32_t b = A.off[u], e = A.off[u + 1];
             const uint32_t old = A.done[su];
-            lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), r);
+            lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), departure_key(r, fpq.y, u, p.x));
             uint32_t end = old;
             if (old == INF) end = tw > A.max_t ? e : lower_bound_u32(A.tt, lo, e, tw);
             if (lo < end) {
@@ -681,7 +697,7 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
                                                                __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t b = A.off[u], e = A.off[u + 1];
                 const uint32_t old = A.done[su];
-                lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), ru);
+                lo = lower_bound_u32(A.tt, b, old == INF ? e : min(old, e), departure_key(ru, fpq.y, u, p.x));
                 uint32_t end = old;
                 if (old == INF) end = tw > A.max_t ? e : lower_bound_u32(A.tt, lo, e, tw);
                 if (lo < end) {
@@ -794,6 +810,7 @@ __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
             const uint32_t q = (uint32_t)(idx / A.n);
             v = (uint32_t)(idx - (uint64_t)q * A.n);
             const uint4 p = A.qp[q];
+            const uint32_t strict = fp_strict(A.fpar[q].y);
             if (v != p.x) {
                 ++n_verts;
                 const size_t sv = (size_t)q * A.n + v;
@@ -804,7 +821,8 @@ __global__ __launch_bounds__(TB) void pull_kernel(TravArgs A)
                 for (uint32_t k = b; k < ub; ++k) {
                     ++n_edges;
                     const uint2 st = A.st_in[k];
-                    if (st.y >= p.y && arrival_of(A.av, (size_t)q * A.n + st.x) <= st.y) {
+                    const uint32_t ru = arrival_of(A.av, (size_t)q * A.n + st.x);
+                    if (st.y >= p.y && (strict && st.x != p.x ? ru < st.y : ru <= st.y)) {
                         const uint32_t a = A.a_in[k];
                         // single writer; the stamp gives frontier membership for dense rounds
                         A.av[sv] = av_word(a, A.stamp_val);
@@ -856,7 +874,9 @@ __global__ void init_queries_kernel(TravArgs A, const uint4 *__restrict__ host_q
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
         const uint4 p = host_qp[q];
         ((uint4 *)A.qp)[q] = p;
-        A.fpar[q] = filter_params(p.y, p.z, A.max_a, A.fbits);
+        uint2 fp = filter_params(p.y, p.z, A.max_a, A.fbits);
+        fp.y |= A.strict << 16;
+        A.fpar[q] = fp;
         const size_t ss = (size_t)q * A.n + p.x;
         // the stamp lets a dense first round find the source
         A.av[ss] = av_word(src_arrival_from_w ? p.w : p.y, A.front_stamp);
@@ -1426,10 +1446,11 @@ void slot_release(kairos_graph *g, Slot *s)
 
 // -------------------------------------------------------------- queries --
 static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq, bool from_w, TravArgs &A,
-                         uint32_t &round)
+                         uint32_t &round, bool strict = false)
 {
     hipStream_t st = s->stream;
     A = make_args(g, s, nq);
+    A.strict = strict ? 1u : 0u;
     round = 0;
     A.round = 0;
     A.next = s->queue[0];
@@ -1463,7 +1484,8 @@ static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq
     return KAIROS_OK;
 }
 
-int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                         bool strict)
 {
     hipStream_t st = s->stream;
     int rc;
@@ -1476,7 +1498,7 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
     const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, &qp, 1, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, &qp, 1, false, A, round, strict))) return rc;
     if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
     prof_begin(g, st, &ev);
     hipLaunchKernelGGL(finalize_sweep_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, out, s->av,
@@ -1489,7 +1511,7 @@ int run_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, ui
 int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
                               uint32_t *pred_tail, uint32_t *pred_dep)
 {
-    int rc = run_earliest_arrival(g, s, src, ta, tw, out);
+    int rc = run_earliest_arrival(g, s, src, ta, tw, out, false);
     if (rc) return rc;
     hipEvent_t ev;
     prof_begin(g, s->stream, &ev);
@@ -1503,7 +1525,7 @@ int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t t
 // Temporal BFS: level-synchronous rounds from the source; the round that
 // first reaches a vertex gives its hop count (kept in the slot's fastest
 // array; the latest-departure array holds the frontier snapshots).
-int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out)
+int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out, bool strict)
 {
     hipStream_t st = s->stream;
     int rc;
@@ -1517,7 +1539,7 @@ int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32
     const uint4 qp = make_uint4(g->h_perm[src], ta, tw, ta);
     TravArgs A;
     uint32_t round;
-    if ((rc = start_queries(g, s, &qp, 1, false, A, round))) return rc;
+    if ((rc = start_queries(g, s, &qp, 1, false, A, round, strict))) return rc;
     A.hop = s->fa;
     A.snap = s->l1;
     if ((rc = run_rounds<false>(g, s, A, 1, &round))) return rc;
@@ -1566,7 +1588,8 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
 // at their fixpoint), so each improvement updates
 //   F[v] = min(F[v], a - s)   and   L1[v] = max(L1[v], s + 1),
 // the latter giving LD[v] = L1[v] - 1, with 0 meaning unreachable.
-int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t ta, uint32_t tw, uint32_t *out)
+int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t ta, uint32_t tw, uint32_t *out,
+              bool strict)
 {
     hipStream_t st = s->stream;
     int rc;
@@ -1605,7 +1628,7 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
         const uint4 qp = make_uint4(src, ta, tw, S[0]);
         TravArgs A;
         uint32_t r = 0;
-        if ((rc = start_queries(g, s, &qp, 1, true, A, r))) return rc;
+        if ((rc = start_queries(g, s, &qp, 1, true, A, r, strict))) return rc;
         A.fa = fa;
         A.l1 = l1;
         A.steps = s->steps;
