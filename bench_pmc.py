@@ -54,6 +54,8 @@ def run(argv):
     out = os.path.join(ROOT, "gpurun_out", "pmc_" + mode)
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
+    with open(os.path.join(out, "args.json"), "w") as f:
+        json.dump(argv, f)  # the summary quotes the exact command
     bench = [sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu", *argv]
     passes = [("trace", ["--kernel-trace", "--stats"]), ("fetch", ["--pmc", "FETCH_SIZE"]),
               ("write", ["--pmc", "WRITE_SIZE"])]
@@ -124,11 +126,14 @@ def summarize(outdir, workload="rmat20-32m", mode="batch"):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"traffic_{workload}_{mode}.json"), "w") as f:
         json.dump(doc, f, indent=1)
-    b = f"--workload {workload} --mode {mode} --no-cpu --steps 3 --warmup 1"
+    argv = ["--workload", workload, "--mode", mode, "--steps", "3", "--warmup", "1"]
+    if os.path.exists(os.path.join(outdir, "args.json")):
+        argv = json.load(open(os.path.join(outdir, "args.json")))
+    b = " ".join(["--no-cpu", *argv])
     lines = [f"# rocprofv3 summary: bench.py workload {workload}, mode {mode}",
              "",
              "commands (from the repository root, on the GPU host):",
-             f"  python bench_pmc.py run --workload {workload} --mode {mode} --steps 3 --warmup 1",
+             f"  python bench_pmc.py run {' '.join(argv)}",
              "  which makes three rocprofv3 passes, each its own process:",
              f"    rocprofv3 --kernel-trace --stats -- python bench.py {b}",
              f"    rocprofv3 --pmc FETCH_SIZE       -- python bench.py {b}",
