@@ -24,6 +24,16 @@ function writes out a definition directly (no blocking, no reordering):
   times S: LD[v] = max{s in S : v reachable when the source starts at s},
   F[v] = min over s in S of (EA_s[v] - s), with EA_s from ``min_hops``.
 
+* ``latest_departure_to`` -- single-target latest departure (the
+  single-target reading of the latest-departure path of §2.3): for every
+  vertex u, the latest departure from u of a time-respecting path that ends
+  at the target within [t_alpha, t_omega]; t_omega for the target itself.
+  Computed level by level: L_0 has only the target (at t_omega);
+  L_{h+1}[u] is the largest of L_h[u] and the departure t of every usable
+  edge (u, v, t, a) whose arrival lets the path continue from v, a <= L_h[v]
+  (a < L_h[v] strictly; the target itself accepts a <= t_omega under either
+  predicate, as the end of a path has no successor).
+
 Succession (§2.2): "Succeeds" lets the next edge leave at the previous
 arrival (t >= arrival); "Strictly succeeds" needs t > arrival.  The first
 edge of a path has no predecessor, so under either predicate it only needs
@@ -115,6 +125,54 @@ def strict_sweep(n, src, dst, t, lam, source, t_alpha, t_omega, strict=False):
     ld[source] = t_omega
     fa[source] = 0
     return ld.astype(np.uint32), fa.astype(np.uint32)
+
+
+def latest_departure_to(n, src, dst, t, lam, target, t_alpha, t_omega, strict=False):
+    """Latest departure towards ``target`` by the level iteration above."""
+    src, dst, t, a = _edges(src, dst, t, lam)
+    usable = (t >= t_alpha) & (a <= t_omega)
+    src, dst, t, a = src[usable], dst[usable], t[usable], a[usable]
+    NONE = -1
+    cur = np.full(n, NONE, np.int64)
+    cur[target] = t_omega
+    into_target = dst == target
+    while True:
+        lv = cur[dst]
+        ok = (lv != NONE) & np.where(into_target | (not strict), a <= lv, a < lv)
+        nxt = cur.copy()
+        np.maximum.at(nxt, src[ok], t[ok])
+        nxt[target] = t_omega
+        if np.array_equal(nxt, cur):
+            break
+        cur = nxt
+    cur[cur == NONE] = INF
+    return cur.astype(np.uint32)
+
+
+def brute_force_to(n, edges, target, t_alpha, t_omega, strict=False):
+    """Latest departure towards ``target`` by enumerating every walk from
+    every vertex (tiny inputs only)."""
+    out = [[] for _ in range(n)]
+    for (u, v, t, lam) in edges:
+        if t >= t_alpha and t + lam <= t_omega:
+            out[u].append((v, t, t + lam))
+    best = [INF] * n
+    best[target] = t_omega
+
+    def walk(start, u, now, first):
+        for (v, t, a) in out[u]:
+            if first is not None and (t < now or (strict and t == now)):
+                continue
+            d = t if first is None else first
+            if v == target and d != INF:
+                if v != start and (best[start] == INF or d > best[start]):
+                    best[start] = d
+            walk(start, v, a, d)
+
+    for s0 in range(n):
+        if s0 != target:
+            walk(s0, s0, t_alpha, None)
+    return best
 
 
 def brute_force_walks(n, edges, source, t_alpha, t_omega, strict=False):

@@ -132,6 +132,9 @@ MUTATIONS = [
     ("(src == source) | (not strict)", "(not strict)"),                   # strict first edge
     ("cur[src] <= t, cur[src] < t)", "cur[src] <= t, cur[src] <= t)"),    # strictness ignored
     ("ld[r] = s", "ld[r] = np.maximum(ld[r], s)"),                        # INF taken as a departure
+    ("into_target | (not strict)", "(not strict)"),                       # strict at the path's end
+    ("np.maximum.at(nxt, src[ok], t[ok])", "np.maximum.at(nxt, src[ok], a[ok])"),  # arrival for departure
+    ("a <= lv, a < lv)", "a < lv, a < lv)"),                              # strictness everywhere
 ]
 
 
@@ -163,9 +166,13 @@ def test_planted_mutations_are_caught(old, new):
         hops, hea = mod.min_hops(n, src, dst, t, lam, s, ta, tw)
         h2, e2 = mod.min_hops(n, src, dst, t, lam, s, ta, tw, True)
         l2, f2 = mod.strict_sweep(n, src, dst, t, lam, s, ta, tw, True)
+        to = mod.latest_departure_to(n, src, dst, t, lam, s, ta, tw)
+        to2 = mod.latest_departure_to(n, src, dst, t, lam, s, ta, tw, True)
         if any((int(pt[v]), int(pd[v])) != rule_pick(last[v]) for v in range(n)) or \
                 list(hops) != bhops or list(hea) != bea or list(h2) != shops or list(e2) != sea or \
-                list(l2) != sld or list(f2) != sfa:
+                list(l2) != sld or list(f2) != sfa or \
+                list(to) != P.brute_force_to(n, edges, s, ta, tw) or \
+                list(to2) != P.brute_force_to(n, edges, s, ta, tw, True):
             caught = True
             break
     assert caught
@@ -201,3 +208,53 @@ def test_strict_hand_worked():
     assert P.min_hops(n, src, dst, t, lam, 0, 1, 10, strict=True)[1].tolist() == [1, 2, 5]
     ld, fa = P.strict_sweep(n, src, dst, t, lam, 0, 1, 10, strict=True)
     assert ld.tolist() == [10, 1, 1] and fa.tolist() == [0, 1, 4]
+
+
+TMAX = 0xFFFFFFFE
+
+
+def reversed_edges(src, dst, t, lam):
+    """Each edge (u, v, t, lam) becomes (v, u, TMAX - (t + lam), lam): the
+    time axis read backwards."""
+    a = t.astype(np.int64) + lam
+    return dst, src, (TMAX - a).astype(np.uint32), lam
+
+
+@settings(max_examples=800, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_cases(), st.booleans())
+def test_latest_departure_to_matches_enumeration(case, strict):
+    n, edges, target, ta, tw = case
+    want = P.brute_force_to(n, edges, target, ta, tw, strict)
+    src, dst, t, lam = arrays(edges)
+    got = P.latest_departure_to(n, src, dst, t, lam, target, ta, tw, strict)
+    assert list(got) == want
+
+
+@settings(max_examples=500, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(tiny_cases(), st.booleans())
+def test_latest_departure_to_is_earliest_arrival_backwards(case, strict):
+    """Latest departure towards a target equals TMAX minus the earliest
+    arrival from that target on the time-reversed graph, with the window
+    reversed too: an independent route (the C scan without strictness)."""
+    n, edges, target, ta, tw = case
+    src, dst, t, lam = arrays(edges)
+    got = P.latest_departure_to(n, src, dst, t, lam, target, ta, tw, strict)
+    rs, rd, rt, rl = reversed_edges(src, dst, t, lam)
+    if strict:
+        _, ea = P.min_hops(n, rs, rd, rt, rl, target, TMAX - tw, TMAX - ta, True)
+    else:
+        ea = O.earliest_arrival(O.sort_by_departure(n, rs, rd, rt, rl), target, TMAX - tw, TMAX - ta)
+    back = np.where(ea == INF, INF, TMAX - ea.astype(np.int64))
+    assert got.tolist() == back.tolist()
+
+
+def test_latest_departure_to_hand_worked():
+    # 0 -(t=1,a=2)-> 1 -(t=2,a=3)-> 2 (target) and 0 -(t=4,a=9)-> 2; window [0, 10].
+    # From 0 the latest departure that still reaches 2 is 4 (direct edge);
+    # from 1 it is 2.  With the window ending at 8 the direct edge is gone.
+    n, edges = 3, [(0, 1, 1, 1), (1, 2, 2, 1), (0, 2, 4, 5)]
+    src, dst, t, lam = arrays(edges)
+    assert P.latest_departure_to(n, src, dst, t, lam, 2, 0, 10).tolist() == [4, 2, 10]
+    assert P.latest_departure_to(n, src, dst, t, lam, 2, 0, 8).tolist() == [1, 2, 8]
+    # strictly succeeds: 0 -> 1 arrives at 2 and 1 leaves at 2, too early
+    assert P.latest_departure_to(n, src, dst, t, lam, 2, 0, 8, strict=True).tolist() == [INF, 2, 8]
