@@ -155,11 +155,27 @@ enum {
     KAIROS_EARLIEST_ARRIVAL = 0,
     KAIROS_LATEST_DEPARTURE = 1,
     KAIROS_FASTEST = 2,
-    KAIROS_TEMPORAL_BFS = 3
+    KAIROS_TEMPORAL_BFS = 3,
+    KAIROS_LATEST_DEPARTURE_TO = 4  /* src names the target; see below */
 };
 #define KAIROS_STRICT 1u
 int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha,
                  uint32_t t_omega, uint32_t *out);
+
+/* Single-target latest departure (the single-target reading of §2.3's
+ * latest-departure path): out[u] = the latest departure from u of a
+ * time-respecting path that ends at `target` within [t_alpha, t_omega];
+ * t_omega for the target, INF if u cannot reach it.  Answered on the
+ * time-reversed graph (edge (u, v, t, lambda) read as (v, u, TMAX - t -
+ * lambda, lambda)), which g builds from its own index on the first call and
+ * keeps (another index's worth of device memory, counted by
+ * kairos_graph_stats; it follows kairos_set_tuning).  KAIROS_STRICT in
+ * kairos_query applies "Strictly succeeds" between consecutive edges; the
+ * last edge into the target needs only an arrival by t_omega.
+ *   out: device, n uint32.  Errors: INVALID, RANGE (target >= n, window),
+ *   NOMEM, DEVICE. */
+int kairos_latest_departure_to(kairos_graph *g, uint32_t target, uint32_t t_alpha, uint32_t t_omega,
+                               uint32_t *out);
 
 /* q earliest-arrival queries answered together.
  *   src, t_alpha, t_omega  host, q entries each.

@@ -82,11 +82,13 @@ _sig("kairos_graph_build", _i32, _p, _p, _p, _p, _u64, _u32, _p, ctypes.POINTER(
 _sig("kairos_graph_free", None, _p)
 _sig("kairos_graph_stats", _i32, _p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
 _sig("kairos_graph_index", _i32, _p, ctypes.POINTER(kairos_index_view))
-for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs"):
+for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs",
+           "kairos_latest_departure_to"):
     _sig(_n, _i32, _p, _u32, _u32, _u32, _p)
 _sig("kairos_earliest_arrival_path", _i32, _p, _u32, _u32, _u32, _p, _p, _p)
 _sig("kairos_query", _i32, _p, _i32, _u32, _u32, _u32, _u32, _p)
 KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST, KAIROS_TEMPORAL_BFS = 0, 1, 2, 3
+KAIROS_LATEST_DEPARTURE_TO = 4
 KAIROS_STRICT = 1
 _sig("kairos_earliest_arrival_batch", _i32, _p, _u32, _p, _p, _p, _p)
 _sig("kairos_traversed_edges", _i32, _p, _u32, _u32, _p, ctypes.POINTER(_u64))
@@ -227,6 +229,10 @@ def kairos_latest_departure(g: Graph, src: int, t_alpha: int, t_omega: int, out:
 
 def kairos_fastest(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
     return _single("kairos_fastest", g, src, t_alpha, t_omega, out)
+
+
+def kairos_latest_departure_to(g: Graph, target: int, t_alpha: int, t_omega: int, out: torch.Tensor):
+    return _single("kairos_latest_departure_to", g, target, t_alpha, t_omega, out)
 
 
 def kairos_temporal_bfs(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):

@@ -1,6 +1,7 @@
 // C entry points of libkairos: argument checks, handle lifetime, dispatch.
 #include "internal.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -56,6 +57,7 @@ const char *kairos_status_string(int status)
 static void graph_release(kairos_graph *g)
 {
     if (!g) return;
+    graph_release(g->rev);
     for (Slot *s : g->free_slots) slot_destroy(s);
     for (Slot *s : g->batch_slots) slot_destroy(s);
     for (VBatch *b : g->vbatches) vbatch_destroy(b);
@@ -133,7 +135,37 @@ int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t
     if (!g) return KAIROS_ERR_INVALID;
     if (n) *n = g->n;
     if (m) *m = g->m;
-    if (device_bytes) *device_bytes = g->index_bytes;
+    if (device_bytes) *device_bytes = g->index_bytes + (g->rev ? g->rev->index_bytes : 0);
+    return KAIROS_OK;
+}
+
+// The time-reversed graph of g, built once from g's own in-index on the
+// first call (guarded: concurrent first calls build it once).
+static int ensure_reverse(kairos_graph *g, kairos_graph **out)
+{
+    std::lock_guard<std::mutex> lk(g->rev_mu);
+    if (!g->rev) {
+        const size_t words = std::max<uint64_t>(g->m, 1);
+        uint32_t *buf[4] = {nullptr, nullptr, nullptr, nullptr};
+        bool ok = true;
+        for (auto &b : buf) ok = ok && (b = (uint32_t *)dev_alloc(words * 4, nullptr)) != nullptr;
+        int rc = ok ? KAIROS_OK : KAIROS_ERR_NOMEM;
+        hipStream_t st = nullptr;
+        if (rc == KAIROS_OK && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            st = nullptr;
+            rc = KAIROS_ERR_DEVICE;
+        }
+        if (rc == KAIROS_OK) rc = reverse_edge_list(g, st, buf[0], buf[1], buf[2], buf[3]);
+        if (rc == KAIROS_OK && hipStreamSynchronize(st) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+        kairos_graph *r = nullptr;
+        if (rc == KAIROS_OK) rc = kairos_graph_build(buf[0], buf[1], buf[2], buf[3], g->m, g->n, g->stream, &r);
+        if (st) hipStreamDestroy(st);
+        for (auto b : buf) dev_free(b);
+        if (rc != KAIROS_OK) return rc;
+        r->tuning = g->tuning;
+        g->rev = r;
+    }
+    *out = g->rev;
     return KAIROS_OK;
 }
 
@@ -209,11 +241,41 @@ int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_
     return single_query(g, 4, src, t_alpha, t_omega, out_hops);
 }
 
+static int latest_departure_to(kairos_graph *g, uint32_t target, uint32_t ta, uint32_t tw, uint32_t *out,
+                               bool strict)
+{
+    if (!g || !out) return KAIROS_ERR_INVALID;
+    (void)hipGetLastError();
+    int rc = check_query(g, target, ta, tw);
+    if (rc) return rc;
+    kairos_graph *rev = nullptr;
+    if ((rc = ensure_reverse(g, &rev))) return rc;
+    Slot *s = nullptr;
+    if ((rc = slot_acquire(rev, 1, false, &s))) return rc;
+    rc = run_latest_departure_to(rev, s, target, ta, tw, out, strict);
+    if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    if (rc == KAIROS_OK) {
+        slot_release(rev, s);
+    } else {
+        hipStreamSynchronize(s->stream);
+        slot_destroy(s);
+    }
+    return rc;
+}
+
+int kairos_latest_departure_to(kairos_graph *g, uint32_t target, uint32_t t_alpha, uint32_t t_omega,
+                               uint32_t *out)
+{
+    return latest_departure_to(g, target, t_alpha, t_omega, out, false);
+}
+
 int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
                  uint32_t *out)
 {
     if ((flags & ~(uint32_t)KAIROS_STRICT) != 0) return KAIROS_ERR_INVALID;
     static const int internal[] = {0, 1, 2, 4};  // EA, LD, F, temporal BFS
+    if (kind == KAIROS_LATEST_DEPARTURE_TO)
+        return latest_departure_to(g, src, t_alpha, t_omega, out, (flags & KAIROS_STRICT) != 0);
     if (kind < KAIROS_EARLIEST_ARRIVAL || kind > KAIROS_TEMPORAL_BFS) return KAIROS_ERR_INVALID;
     return single_query(g, internal[kind], src, t_alpha, t_omega, out, nullptr, nullptr,
                         (flags & KAIROS_STRICT) != 0);
@@ -292,6 +354,14 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
         in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1)
         return KAIROS_ERR_INVALID;
+    {
+        // the reversed graph (if built) runs with the same parameters
+        std::lock_guard<std::mutex> lr(g->rev_mu);
+        if (g->rev) {
+            int rc = kairos_set_tuning(g->rev, in);
+            if (rc) return rc;
+        }
+    }
     std::lock_guard<std::mutex> lk(g->pool_mu);
     const bool resize = in->chunk < g->tuning.chunk || in->split < g->tuning.split ||
                         in->batch_layout != g->tuning.batch_layout;

@@ -137,6 +137,10 @@ struct kairos_graph {
     std::vector<kairos::Slot *> batch_slots;  // batch slots (any qcap)
     std::vector<kairos::VBatch *> vbatches;   // vertex-major batch state
     kairos::ProfileAcc prof;
+    // the time-reversed graph (edge (u, v, t, lambda) -> (v, u, TMAX - t -
+    // lambda, lambda)), built on the first single-target query
+    kairos_graph *rev = nullptr;
+    std::mutex rev_mu;
 };
 
 namespace kairos {
@@ -159,6 +163,14 @@ int run_earliest_arrival_path(kairos_graph *g, Slot *s, uint32_t src, uint32_t t
                               uint32_t *pred_tail, uint32_t *pred_dep);
 int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
                      bool strict = false);
+// Edge list of the time-reversed graph of g, in caller ids, into four device
+// arrays of g->m words.
+int reverse_edge_list(kairos_graph *g, hipStream_t st, uint32_t *src, uint32_t *dst, uint32_t *t, uint32_t *lam);
+// Latest departure towards `target` on g, answered on its time-reversed
+// graph `rev` (slot s of rev): earliest arrival from the target over the
+// reversed window, read back as TMAX - arrival.
+int run_latest_departure_to(kairos_graph *rev, Slot *s, uint32_t target, uint32_t ta, uint32_t tw, uint32_t *out,
+                            bool strict);
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
               const uint32_t *tw, uint32_t *out);
 int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);

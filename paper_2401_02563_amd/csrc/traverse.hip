@@ -963,6 +963,38 @@ __global__ void predecessor_kernel(const unsigned long long *__restrict__ av, co
     }
 }
 
+// Time-reversed edge list from the in-index: in-edge e of head x, (u, x, t,
+// a), becomes (x, u, TMAX - a, a - t), all in caller ids.  The head is the
+// last x with off_in[x] <= e.
+__global__ void reverse_edges_kernel(const uint32_t *__restrict__ off_in, const uint32_t *__restrict__ a_in,
+                                     const uint2 *__restrict__ st_in, const uint32_t *__restrict__ inv, uint32_t n,
+                                     uint64_t m, uint32_t *src, uint32_t *dst, uint32_t *t, uint32_t *lam)
+{
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+            if (off_in[mid] <= e)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint2 st = st_in[e];
+        const uint32_t a = a_in[e];
+        src[e] = inv[lo];
+        dst[e] = inv[st.x];
+        t[e] = TMAX - a;
+        lam[e] = a - st.y;
+    }
+}
+
+// Arrivals on the time-reversed graph back to departure times.
+__global__ void flip_times_kernel(uint32_t *out, uint32_t n)
+{
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        if (out[v] != INF) out[v] = TMAX - out[v];
+}
+
 __global__ void count_traversed_kernel(const uint32_t *__restrict__ a_in, const uint2 *__restrict__ st_in,
                                        uint64_t m, const uint32_t *__restrict__ ea, const uint32_t *__restrict__ inv,
                                        uint32_t ta, uint32_t tw, unsigned long long *out)
@@ -1549,6 +1581,30 @@ int run_temporal_bfs(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
     return read_stats(g, s);
+}
+
+int reverse_edge_list(kairos_graph *g, hipStream_t st, uint32_t *src, uint32_t *dst, uint32_t *t, uint32_t *lam)
+{
+    if (!g->m) return KAIROS_OK;
+    hipLaunchKernelGGL(reverse_edges_kernel, dim3(grid_cap(g->m, 256 * 4, 16384)), dim3(256), 0, st, g->off_in,
+                       g->a_in, g->st_in, g->inv, g->n, g->m, src, dst, t, lam);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+// A path from u to the target within [ta, tw] read backwards is a path from
+// the target to u on the reversed graph within [TMAX - tw, TMAX - ta] (the
+// succession predicates carry over: a1 <= t2 becomes a2' <= t1'), and its
+// first departure t is TMAX minus its reversed last arrival.  So the latest
+// departure is TMAX - (earliest reversed arrival); the target gets tw.
+int run_latest_departure_to(kairos_graph *rev, Slot *s, uint32_t target, uint32_t ta, uint32_t tw, uint32_t *out,
+                            bool strict)
+{
+    int rc = run_earliest_arrival(rev, s, target, TMAX - tw, TMAX - ta, out, strict);
+    if (rc) return rc;
+    hipLaunchKernelGGL(flip_times_kernel, dim3(grid_cap(rev->n, 256, 4096)), dim3(256), 0, s->stream, out, rev->n);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
 }
 
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,

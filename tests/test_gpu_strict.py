@@ -137,3 +137,80 @@ def test_non_strict_query_equals_named_calls():
     with pytest.raises(K.KairosError) as ei:
         K._check(K._L.kairos_query(G.handle, 0, 2, 0, 0, 5, out.data_ptr()), "kairos_query")
     assert ei.value.status == 1
+
+
+LDT = K.KAIROS_LATEST_DEPARTURE_TO
+
+
+def ldt(G, target, a, w, strict):
+    out = torch.full((G.n,), 7, dtype=torch.int32, device="cuda")
+    K.kairos_query(G, LDT, target, a, w, out, strict=strict)
+    return K.as_u32(out)
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat16", "bursty16"])
+def test_latest_departure_to(which):
+    """Single-target latest departure through the time-reversed index,
+    against the level-iteration oracle, under both predicates."""
+    name, shift = {"uniform": ("uniform-10k", 0), "rmat16": ("rmat20-32m", 4), "bursty16": ("bursty22-1b", 6)}[which]
+    g, G = built(which, lambda: make_graph(name, scale_shift=shift))
+    targets, ta, tw = make_queries(name, g, count=4)
+    for i in range(len(targets)):
+        s, a, w = int(targets[i]), int(ta[i]), int(tw[i])
+        for strict in (False, True):
+            print("case: ld-to", which, s, a, w, strict, flush=True)
+            want = P.latest_departure_to(g.n, g.src, g.dst, g.t, g.lam, s, a, w, strict)
+            assert np.array_equal(ldt(G, s, a, w, strict), want)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_latest_departure_to_tiny(seed):
+    g = tiny_graph(seed + 100, n=7, m=14, t_max=6, lam_max=2)
+    G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist(), g.lam.tolist()))
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for s in range(g.n):
+        for strict in (False, True):
+            a, w = seed % 3, 5 + seed % 6
+            print("case: ld-to tiny", seed, s, strict, flush=True)
+            assert ldt(G, s, a, w, strict).tolist() == P.brute_force_to(g.n, edges, s, a, w, strict)
+        K.kairos_latest_departure_to(G, s, 0, 9, out)
+        assert K.as_u32(out).tolist() == P.brute_force_to(g.n, edges, s, 0, 9)
+    G.free()
+
+
+def test_latest_departure_to_reverse_index_lifecycle():
+    """The reversed index is built once, counted in the graph's device bytes,
+    follows later tuning changes and survives repeated calls."""
+    g = make_graph("uniform-10k")
+    G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    _, _, b0 = K.kairos_graph_stats(G)
+    targets, ta, tw = make_queries("uniform-10k", g, count=3)
+    want = [P.latest_departure_to(g.n, g.src, g.dst, g.t, g.lam, int(targets[i]), int(ta[i]), int(tw[i]))
+            for i in range(3)]
+    assert np.array_equal(ldt(G, int(targets[0]), int(ta[0]), int(tw[0]), False), want[0])
+    _, _, b1 = K.kairos_graph_stats(G)
+    assert b1 > b0
+    K.kairos_set_tuning(G, tail_limit=0, arrival_filter=0)
+    for i in range(3):
+        assert np.array_equal(ldt(G, int(targets[i]), int(ta[i]), int(tw[i]), False), want[i])
+    _, _, b2 = K.kairos_graph_stats(G)
+    assert b2 == b1
+    G.free()
+
+
+def test_latest_departure_to_ties_near_top():
+    rng = np.random.Generator(np.random.PCG64(23))
+    n, m = 120, 2500
+    src = rng.integers(0, n, m, dtype=np.uint32)
+    dst = rng.integers(0, n, m, dtype=np.uint32)
+    t = (0xFFFFFFFE - 400 + rng.integers(0, 40, m) * 8).astype(np.uint32)
+    lam = rng.integers(1, 4, m, dtype=np.uint32) * 8
+    g = Graph(n, src, dst, t, lam, dict(kind="ties"))
+    G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    for s in range(0, n, 17):
+        for strict in (False, True):
+            for a, w in ((0, 0xFFFFFFFE), (0xFFFFFFFE - 300, 0xFFFFFFFE - 90)):
+                want = P.latest_departure_to(n, g.src, g.dst, g.t, g.lam, s, a, w, strict)
+                assert np.array_equal(ldt(G, s, a, w, strict), want), (s, a, w, strict)
+    G.free()
