@@ -267,14 +267,17 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         res[kind] = {"ms_per_query": dt / k * 1e3, "queries": k}
-    # earliest-arrival paths (predecessor pass) and temporal BFS (level-
-    # synchronous rounds), one query per call
+    # earliest-arrival paths (predecessor pass), temporal BFS (level-
+    # synchronous rounds) and single-target latest departure (reversed index,
+    # built by the untimed first call), one query per call
     k = min(8, q)
     pt = torch.empty_like(one)
     pd = torch.empty_like(one)
     for kind, call in (("earliest_arrival_path",
                         lambda i: K.kairos_earliest_arrival_path(G, int(srcs[i]), int(ta[i]), int(tw[i]), one, pt, pd)),
-                       ("temporal_bfs", lambda i: K.kairos_temporal_bfs(G, int(srcs[i]), int(ta[i]), int(tw[i]), one))):
+                       ("temporal_bfs", lambda i: K.kairos_temporal_bfs(G, int(srcs[i]), int(ta[i]), int(tw[i]), one)),
+                       ("latest_departure_to",
+                        lambda i: K.kairos_latest_departure_to(G, int(srcs[i]), int(ta[i]), int(tw[i]), one))):
         call(0)
         torch.cuda.synchronize()
         t = time.perf_counter()
