@@ -164,6 +164,42 @@ struct EdgeGroup {
     bool ok[UNR];
 };
 
+// Lanes of a wavefront that hold edges into the same (query, vertex) slot
+// in a row -- a burst of one tail's adjacency -- need one atomic between
+// them: a segmented minimum over each run leaves the run's least arrival in
+// its last lane and drops the others' edges (none of them can beat it).
+// `key` is the slot; a lane without an edge is a run of its own.  Every lane
+// of the wavefront must call this (it shuffles); without runs longer than
+// one lane it returns after one ballot.
+__device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t kk = ok ? key : ~(uint64_t)lane;
+    // shuffles run with every lane active: a shuffle inside a short-circuit
+    // (lane == 0 || ...) would read a lane switched off for it
+    const uint64_t up = __shfl_up(kk, 1);
+    const uint64_t dn = __shfl_down(kk, 1);
+    const bool head = lane == 0 || up != kk;
+    if (__ballot(!head) == 0ull) return;
+    uint32_t mv = ok ? a : INF;
+    int f = head ? 1 : 0;  // the scan has reached the run's first lane
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t mo = __shfl_up(mv, o);
+        const int fo = __shfl_up(f, o);
+        if (lane >= (uint32_t)o && !f) {
+            mv = min(mv, mo);
+            f = fo;
+        }
+    }
+    const bool last = lane == 63 || dn != kk;
+    if (ok) {
+        if (last)
+            a = mv;
+        else
+            ok = false;
+    }
+}
+
 // Relax a group of UNR edges per lane.  The arrival reads, the atomic
 // minima and the stamp exchanges of the group are each issued together (they
 // are independent), so a lane waits for one round trip per stage instead of
@@ -210,12 +246,15 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
     }
 #pragma unroll
     for (int k = 0; k < UNR; ++k) G.cur[k] = arrival_of(A.av, G.ok[k] ? sv[k] : 0);
-    unsigned long long old[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         G.ok[k] = G.ok[k] && G.a[k] < G.cur[k];
-        if (G.ok[k]) old[k] = atomicMin(&A.av[sv[k]], av_word(G.a[k], A.stamp_val));
+        dedupe_runs(G.ok[k], G.a[k], (uint64_t)sv[k]);
     }
+    unsigned long long old[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k)
+        if (G.ok[k]) old[k] = atomicMin(&A.av[sv[k]], av_word(G.a[k], A.stamp_val));
     uint32_t st[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
