@@ -235,6 +235,11 @@ typedef struct kairos_tuning {
                                 than tail_limit frontier entries in one
                                 cooperative launch (grid barriers, no host
                                 round trip per round); needs pull_alpha 0      */
+    uint32_t run_dedupe;     /* 1: lanes of a wavefront holding consecutive
+                                edges into the same vertex (bursts of one
+                                pair's contacts) issue one atomic per run; on
+                                by default when more than 1/32 of the
+                                out-edges repeat the previous edge's head     */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);

@@ -41,7 +41,8 @@ _u32, _u64, _i32, _p = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_
 class kairos_tuning(ctypes.Structure):
     _fields_ = [(k, _u32) for k in ("block", "chunk", "split", "pull_alpha", "pull_beta",
                                     "rounds_per_sync", "batch_persistent", "sweep_group", "batch_layout",
-                                    "tail_limit", "dense_frontier", "arrival_filter", "single_persistent")]
+                                    "tail_limit", "dense_frontier", "arrival_filter", "single_persistent",
+                                    "run_dedupe")]
 
 
 class kairos_profile(ctypes.Structure):

@@ -117,6 +117,7 @@ int kairos_graph_build(const uint32_t *src, const uint32_t *dst, const uint32_t 
     int rc = build_index(g, src, dst, t, lambda, st);
     hipStreamSynchronize(st);
     if (own) hipStreamDestroy(st);
+    g->tuning = default_tuning(g);  // again: some defaults depend on index statistics
     if (rc != KAIROS_OK) {
         graph_release(g);
         return rc;
@@ -352,7 +353,7 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 16 || in->split < 16 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
-        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1)
+        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1 || in->run_dedupe > 1)
         return KAIROS_ERR_INVALID;
     {
         // the reversed graph (if built) runs with the same parameters

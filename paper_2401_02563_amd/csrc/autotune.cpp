@@ -93,6 +93,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         {&kairos_tuning::arrival_filter, {0, 2, 4, 8}},
         {&kairos_tuning::batch_persistent, {0, 1}},
         {&kairos_tuning::single_persistent, {0, 1}},
+        {&kairos_tuning::run_dedupe, {0, 1}},
         {&kairos_tuning::rounds_per_sync, {1, 2, 4}},
         {&kairos_tuning::pull_alpha, {0, 4, 14}},
         {&kairos_tuning::pull_beta, {8, 24, 64}},

@@ -59,6 +59,7 @@ struct BArgs {
     uint32_t split;
     uint32_t chunk;
     uint32_t max_t;                  // largest departure time in the graph
+    uint32_t dedupe;                 // one atomic per run of lanes into the same slot
 };
 
 enum : int { BCNT_RANGE = 10 };  // [10..12] rotating range-table sizes
@@ -283,8 +284,11 @@ __device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, uns
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] < cur[k];
-        if (H.ok[k]) old[k] = atomicMin(&A.arr[idx[k]], H.a[k]);
+        if (A.dedupe) dedupe_runs(H.ok[k], H.a[k], (uint64_t)idx[k]);  // one atomic per run of equal slots
     }
+#pragma unroll
+    for (int k = 0; k < HU; ++k)
+        if (H.ok[k]) old[k] = atomicMin(&A.arr[idx[k]], H.a[k]);
     unsigned long long om[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
@@ -829,6 +833,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     A.split = std::max<uint32_t>(g->tuning.split, 16);
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 16);
     A.max_t = g->max_t;
+    A.dedupe = g->tuning.run_dedupe;
     A.round = 0;
     A.mask_cur = b->mask[0];
     A.mask_next = b->mask[1];

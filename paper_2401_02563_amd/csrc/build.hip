@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 namespace kairos {
@@ -289,6 +290,18 @@ __global__ void max_degree_kernel(const uint32_t *__restrict__ off, uint32_t n, 
     if ((threadIdx.x & 63) == 0) atomicMax(out, best);
 }
 
+// Out-edges whose head equals the previous out-edge's head (runs of one
+// pair's edges in a time-sorted adjacency, as in bursty contact data).
+__global__ void repeat_heads_kernel(const uint2 *__restrict__ da, uint64_t m, unsigned long long *out)
+{
+    unsigned long long c = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        c += da[e].x == da[e - 1].x;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 // Vertex relabelling: new ids in order of decreasing in-degree (ties by id),
 // so the arrival words of the most-targeted heads share cache lines.
 __global__ void indegree_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t *deg)
@@ -511,16 +524,27 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         hipLaunchKernelGGL(tail_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256), 0, st, a, m, n, 1, g->off_in);
     } while (0);
     if (rc == KAIROS_OK) {
+        // the 64 bytes past the histograms: max out-degree at byte 32, the
+        // repeat count (8-byte aligned) at byte 40
         uint32_t *d_max = hist + 256 * (size_t)nblocks + 8;
+        unsigned long long *d_rep = (unsigned long long *)(hist + 256 * (size_t)nblocks + 10);
         hipMemsetAsync(d_max, 0, 4, st);
+        hipMemsetAsync(d_rep, 0, 8, st);
         hipLaunchKernelGGL(max_degree_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st,
                            g->off_out, n, d_max);
+        hipLaunchKernelGGL(repeat_heads_kernel, dim3(grid_for(m, 256 * 8, 8192)), dim3(256), 0, st, g->da_out, m,
+                           d_rep);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(h_stats, d_max, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
+            hipMemcpyAsync(h_stats + 2, d_rep, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
             rc = KAIROS_ERR_DEVICE;
-        else
+        } else {
             g->max_out_degree = h_stats[0];
+            uint64_t rep;
+            std::memcpy(&rep, h_stats + 2, 8);
+            g->repeat_heads = rep;
+        }
     }
     if (rc == KAIROS_OK) {
         g->h_perm.resize(n);

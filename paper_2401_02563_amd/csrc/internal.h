@@ -127,6 +127,7 @@ struct kairos_graph {
     uint32_t max_out_degree = 0;
     uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
     uint32_t max_a = 0;           // largest arrival time
+    uint64_t repeat_heads = 0;    // out-edges whose head repeats the previous out-edge's
     uint64_t index_bytes = 0;
     hipStream_t stream = nullptr; // caller's stream, or nullptr
     int device = 0;

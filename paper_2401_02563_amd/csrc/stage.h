@@ -31,6 +31,43 @@ __device__ __forceinline__ uint64_t lanes_below()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Lanes of a wavefront that hold edges into the same (query, vertex) slot
+// in a row -- a burst of one tail's adjacency -- need one atomic between
+// them: a segmented minimum over each run leaves the run's least arrival in
+// its last lane and drops the others' edges (none of them can beat it).
+// `key` is the slot; a lane without an edge is a run of its own.  Every lane
+// of the wavefront must call this (it shuffles); without runs longer than
+// one lane it returns after one ballot.
+__device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t kk = ok ? key : ~(uint64_t)lane;
+    // shuffles run with every lane active: a shuffle inside a short-circuit
+    // (lane == 0 || ...) would read a lane switched off for it
+    const uint64_t up = __shfl_up(kk, 1);
+    const uint64_t dn = __shfl_down(kk, 1);
+    const bool head = lane == 0 || up != kk;
+    if (__ballot(!head) == 0ull) return;
+    uint32_t mv = ok ? a : 0xFFFFFFFFu;
+    int f = head ? 1 : 0;  // the scan has reached the run's first lane
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t mo = __shfl_up(mv, o);
+        const int fo = __shfl_up(f, o);
+        if (lane >= (uint32_t)o && !f) {
+            mv = min(mv, mo);
+            f = fo;
+        }
+    }
+    const bool last = lane == 63 || dn != kk;
+    if (ok) {
+        if (last)
+            a = mv;
+        else
+            ok = false;
+    }
+}
+
+
 // Per-wavefront output buffer of CAP entries in LDS.  `n` is wave-uniform.
 template <int CAP>
 struct Stage {

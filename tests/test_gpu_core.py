@@ -113,7 +113,7 @@ def test_ea_skewed(which):
                                     dict(arrival_filter=0, tail_limit=0), dict(arrival_filter=2),
                                     dict(arrival_filter=4), dict(arrival_filter=8, tail_limit=0),
                                     dict(arrival_filter=2, tail_limit=0, dense_frontier=4),
-                                    dict(single_persistent=0),
+                                    dict(single_persistent=0), dict(run_dedupe=1),
                                     dict(single_persistent=1, tail_limit=0),
                                     dict(single_persistent=1, tail_limit=0, dense_frontier=4)])
 def test_ea_independent_of_tuning(tuning):
@@ -258,6 +258,26 @@ def test_batch_rows_equal_single(which):
     rows = K.as_u32(out).reshape(len(srcs), g.n)
     for q in range(len(srcs)):
         assert np.array_equal(rows[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+
+
+@pytest.mark.parametrize("layout,persistent,dedupe", [(1, 0, 1), (2, 0, 1), (2, 1, 1), (2, 1, 0), (0, 0, 1)])
+def test_batch_bursty_runs(layout, persistent, dedupe):
+    """Bursty pairs put runs of edges into one head next to each other: the
+    batch kernels with and without one atomic per run agree with the oracle."""
+    g, G, se = bursty16()
+    assert K.kairos_get_tuning(G)["run_dedupe"] == 1  # default from the index statistics
+    srcs, ta, tw = make_queries("bursty22-1b", g, count=70)
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, batch_layout=layout, batch_persistent=persistent, run_dedupe=dedupe)
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        print_case("bursty batch", layout, persistent, dedupe)
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        rows = K.as_u32(out).reshape(len(srcs), g.n)
+        for qi in list(range(0, 70, 9)) + [63, 64, 69]:
+            assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
+    finally:
+        K.kairos_set_tuning(G, **old)
 
 
 def test_edge_cases():

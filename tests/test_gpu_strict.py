@@ -85,7 +85,8 @@ def test_skewed_strict(which):
 
 @pytest.mark.parametrize("tuning", [dict(tail_limit=0), dict(pull_alpha=1, pull_beta=1000000, tail_limit=0),
                                     dict(single_persistent=1, tail_limit=0),
-                                    dict(dense_frontier=1, tail_limit=0), dict(arrival_filter=4)])
+                                    dict(dense_frontier=1, tail_limit=0), dict(arrival_filter=4),
+                                    dict(run_dedupe=0), dict(run_dedupe=0, tail_limit=0)])
 def test_strict_independent_of_tuning(tuning):
     g, G = built("bursty16", lambda: make_graph("bursty22-1b", scale_shift=6))
     old = K.kairos_get_tuning(G)
