@@ -211,7 +211,10 @@ typedef struct kairos_tuning {
                                   barriers and stops on the device; 0: one
                                   launch per phase and a host check per round   */
     uint32_t sweep_group;    /* departure times handled together by the
-                                latest-departure / fastest sweep                     */
+                                latest-departure / fastest sweep (1..64): each
+                                group runs as that many queries warm-started
+                                from the previous group's last one; 1 = one
+                                departure time after the other                */
     uint32_t batch_layout;   /* 0: one wavefront per frontier vertex, one lane per
                                 query, arrivals stored vertex-major (edges read
                                 once per 64 queries); 1: one thread per query

@@ -967,6 +967,42 @@ __global__ void predecessor_kernel(const unsigned long long *__restrict__ av, co
     }
 }
 
+// Grouped latest-departure / fastest sweep: every slot but `from` takes slot
+// `from`'s arrivals (with their stamps) and claims, the warm start of the
+// next group of departure times.
+__global__ void warm_slots_kernel(unsigned long long *av, uint32_t *done, uint32_t n, uint32_t nslots, uint32_t from)
+{
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const unsigned long long w = av[(size_t)from * n + v];
+        const uint32_t d = done[(size_t)from * n + v];
+        for (uint32_t j = 0; j < nslots; ++j) {
+            if (j == from) continue;
+            av[(size_t)j * n + v] = w;
+            done[(size_t)j * n + v] = d;
+        }
+    }
+}
+
+// After a group: slot j holds the earliest arrivals for the source leaving
+// at dep[j], so F[v] = min(F[v], EA_j[v] - dep[j]) and, where v is reached,
+// L1[v] = max(L1[v], dep[j] + 1) (latest departure + 1, 0 = none).
+__global__ void sweep_reduce_kernel(const unsigned long long *__restrict__ av, const uint32_t *__restrict__ dep,
+                                    uint32_t n, uint32_t nslots, uint32_t *fa, uint32_t *l1)
+{
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint32_t f = fa[v], l = l1[v];
+        for (uint32_t j = 0; j < nslots; ++j) {
+            const uint32_t a = arrival_of(av, (size_t)j * n + v);
+            if (a != INF) {
+                f = min(f, a - dep[j]);
+                l = max(l, dep[j] + 1u);
+            }
+        }
+        fa[v] = f;
+        l1[v] = l;
+    }
+}
+
 // Time-reversed edge list from the in-index: in-edge e of head x, (u, x, t,
 // a), becomes (x, u, TMAX - a, a - t), all in caller ids.  The head is the
 // last x with off_in[x] <= e.
@@ -1640,6 +1676,69 @@ int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const u
     return read_stats(g, s);
 }
 
+// Grouped sweep (tuning sweep_group = G > 1): the departure times S
+// (descending) are taken G at a time, each group as G queries answered
+// together, query j with the source leaving at its own time s_j.  Every
+// query of a group starts from the arrivals and claims of the previous
+// group's last query (the earliest arrivals for a later departure bound
+// those for s_j from above, and its claims record edges already relaxed
+// for them), so each ends with the earliest arrivals EA_j for leaving at
+// s_j.  F and LD then follow from their cross-route definitions,
+// F[v] = min_j (EA_j[v] - s_j) and LD[v] = max{s_j : EA_j[v] finite}
+// (`sweep_reduce_kernel`).  Queries of one group also explore paths that
+// leave at later times of the same group; that is redundant work, not an
+// error.  fa / l1 / steps live in the single-query slot s.
+int run_sweep_groups(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw,
+                     const std::vector<uint32_t> &S, uint32_t G, bool strict)
+{
+    Slot *b = nullptr;
+    int rc = slot_acquire(g, G, false, &b);
+    if (rc) return rc;
+    const hipStream_t st = b->stream;
+    hipEvent_t ev;
+    // s's fills and step upload precede this stream's work
+    if (b->stream != s->stream) {
+        if (hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    }
+    uint32_t last = INF;  // slot holding the previous group's last query
+    for (size_t g0 = 0; g0 < S.size() && rc == KAIROS_OK; g0 += G) {
+        const uint32_t q = (uint32_t)std::min<size_t>(G, S.size() - g0);
+        prof_begin(g, st, &ev);
+        if (last == INF) {
+            if ((rc = fill_arrivals(st, b->av, (uint64_t)q * g->n))) break;
+            if ((rc = fill(st, b->done, (uint64_t)q * g->n, INF))) break;
+        } else {
+            // slots [0, q) take slot `last`'s state (`last` itself, if it is
+            // one of them, keeps it)
+            hipLaunchKernelGGL(warm_slots_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, b->av, b->done,
+                               g->n, q, last);
+            if (hipGetLastError() != hipSuccess) { rc = KAIROS_ERR_DEVICE; break; }
+        }
+        if ((rc = fill_filter(g, st, b->filt, q))) break;
+        prof_end(g, st, KAIROS_K_INIT, ev);
+        std::vector<uint4> hq(q);
+        for (uint32_t j = 0; j < q; ++j) hq[j] = make_uint4(src, ta, tw, S[g0 + j]);
+        TravArgs A;
+        uint32_t r = 0;
+        if ((rc = start_queries(g, b, hq.data(), q, true, A, r, strict))) break;
+        if ((rc = run_rounds<false>(g, b, A, q, &r))) break;
+        prof_begin(g, st, &ev);
+        hipLaunchKernelGGL(sweep_reduce_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, st, b->av,
+                           s->steps + g0, g->n, q, s->fa, s->l1);
+        prof_end(g, st, KAIROS_K_INIT, ev);
+        if (hipGetLastError() != hipSuccess) { rc = KAIROS_ERR_DEVICE; break; }
+        last = q - 1;
+    }
+    if (rc == KAIROS_OK && hipStreamSynchronize(st) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    if (rc == KAIROS_OK && (rc = read_stats(g, b)) == KAIROS_OK) {
+        slot_release(g, b);
+    } else {
+        hipStreamSynchronize(st);
+        slot_destroy(b);
+    }
+    return rc;
+}
+
 // Latest departure / fastest (kind 1 / 2).  The departure times S of the
 // source's usable out-edges are taken in descending order; for each s the
 // source is set to s and push rounds run to a fixpoint, warm-started from
@@ -1684,7 +1783,12 @@ int run_sweep(kairos_graph *g, Slot *s, int kind, uint32_t src_caller, uint32_t 
     if ((rc = fill(st, fa, g->n, INF))) return rc;
     if ((rc = fill(st, l1, g->n, 0u))) return rc;
     prof_end(g, st, KAIROS_K_INIT, ev);
-    if (!S.empty()) {
+    const uint32_t G = std::min<uint32_t>(std::max<uint32_t>(g->tuning.sweep_group, 1), (uint32_t)S.size());
+    if (G > 1) {
+        KAIROS_HIP(hipMemcpy(s->steps, S.data(), S.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        rc = run_sweep_groups(g, s, src, ta, tw, S, G, strict);
+        if (rc) return rc;
+    } else if (!S.empty()) {
         KAIROS_HIP(hipMemcpy(s->steps, S.data(), S.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         const uint4 qp = make_uint4(src, ta, tw, S[0]);
         TravArgs A;
@@ -1746,7 +1850,11 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.rounds_per_sync = 8;  // measured best: queued empty rounds cost less than host checks
     t.batch_persistent = 1;
     t.single_persistent = 0;  // measured slower: barrier fences cost more than the host round trip
-    t.sweep_group = 1;
+    // departure times per group of a latest-departure / fastest sweep
+    // (first 8 queries of the 2^20-vertex graph: 1, 2, 4, 8, 16 -> 9.1, 7.2,
+    // 5.5, 4.2, 4.4 ms; first 4 of the 2^24-vertex graph: 50, 48, 47, 52,
+    // 62 ms -- each group copies and reduces G arrival arrays of n words)
+    t.sweep_group = g && g->n <= (1u << 21) ? 8u : 4u;
     // lane-dense rows for graphs with real work per round; on small graphs
     // the query-major layout wins, since it hands small frontiers to the
     // one-workgroup kernel (10^5 edges, 16 queries: 0.59 ms against 1.9 ms)

@@ -215,3 +215,57 @@ def test_latest_departure_to_ties_near_top():
                 want = P.latest_departure_to(n, g.src, g.dst, g.t, g.lam, s, a, w, strict)
                 assert np.array_equal(ldt(G, s, a, w, strict), want), (s, a, w, strict)
     G.free()
+
+
+@pytest.mark.parametrize("group", [2, 5, 8])
+def test_grouped_sweeps(group):
+    """Latest departure and fastest with the departure times taken `group`
+    at a time (each group answered as a query set warm-started from the
+    previous group's last query): the same bits as the oracle, under both
+    predicates, on graphs with ragged last groups."""
+    g, G = built("uniform", lambda: make_graph("uniform-10k"))
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, sweep_group=group)
+        srcs, ta, tw = make_queries("uniform-10k", g)
+        for i in range(0, len(srcs), 3):
+            for strict in (False, True):
+                s, a, w = int(srcs[i]), int(ta[i]), int(tw[i])
+                print("case: grouped", group, i, strict, flush=True)
+                ld, fa = P.strict_sweep(g.n, g.src, g.dst, g.t, g.lam, s, a, w, strict)
+                assert np.array_equal(q(G, LD, s, a, w, strict), ld)
+                assert np.array_equal(q(G, F, s, a, w, strict), fa)
+    finally:
+        K.kairos_set_tuning(G, **old)
+    for which, (name, shift) in (("rmat16", ("rmat20-32m", 4)), ("bursty16", ("bursty22-1b", 6))):
+        g, G = built(which, lambda: make_graph(name, scale_shift=shift))
+        old = K.kairos_get_tuning(G)
+        try:
+            K.kairos_set_tuning(G, sweep_group=group)
+            srcs, ta, tw = make_queries(name, g, count=6)
+            deg = g.out_degree()
+            for i in range(len(srcs)):
+                s = int(srcs[i])
+                if deg[s] > 40:
+                    continue
+                print("case: grouped", which, group, i, flush=True)
+                ld, fa = P.strict_sweep(g.n, g.src, g.dst, g.t, g.lam, s, int(ta[i]), int(tw[i]))
+                assert np.array_equal(q(G, LD, s, int(ta[i]), int(tw[i]), False), ld)
+                assert np.array_equal(q(G, F, s, int(ta[i]), int(tw[i]), False), fa)
+        finally:
+            K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_grouped_sweeps_tiny(seed):
+    g = tiny_graph(seed + 200, n=7, m=16, t_max=6, lam_max=2)
+    G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    K.kairos_set_tuning(G, sweep_group=2 + seed % 3)
+    edges = list(zip(g.src.tolist(), g.dst.tolist(), g.t.tolist(), g.lam.tolist()))
+    for s in range(g.n):
+        for strict in (False, True):
+            _, _, _, bld, bfa = P.brute_force_walks(g.n, edges, s, 0, 9, strict)
+            print("case: grouped tiny", seed, s, strict, flush=True)
+            assert q(G, LD, s, 0, 9, strict).tolist() == bld
+            assert q(G, F, s, 0, 9, strict).tolist() == bfa
+    G.free()
