@@ -51,7 +51,8 @@ def short_name(n: str) -> str:
 
 def run(argv):
     mode = argv[argv.index("--mode") + 1] if "--mode" in argv else "batch"
-    out = os.path.join(ROOT, "gpurun_out", "pmc_" + mode)
+    workload = argv[argv.index("--workload") + 1] if "--workload" in argv else "rmat20-32m"
+    out = os.path.join(ROOT, "gpurun_out", f"pmc_{workload}_{mode}")
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
     with open(os.path.join(out, "args.json"), "w") as f:
@@ -138,7 +139,7 @@ def summarize(outdir, workload="rmat20-32m", mode="batch"):
              f"    rocprofv3 --kernel-trace --stats -- python bench.py {b}",
              f"    rocprofv3 --pmc FETCH_SIZE       -- python bench.py {b}",
              f"    rocprofv3 --pmc WRITE_SIZE       -- python bench.py {b}",
-             f"  python bench_pmc.py summarize gpurun_out/pmc_{mode} {workload} {mode}",
+             f"  python bench_pmc.py summarize gpurun_out/pmc_{workload}_{mode} {workload} {mode}",
              "",
              f"kernel sources sha256[:16]: {doc['kernel_sources_sha']}",
              f"calibration (counter / true bytes of a {COPY_BYTES >> 20} MiB copy): "
