@@ -1850,11 +1850,14 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.rounds_per_sync = 8;  // measured best: queued empty rounds cost less than host checks
     t.batch_persistent = 1;
     t.single_persistent = 0;  // measured slower: barrier fences cost more than the host round trip
-    // departure times per group of a latest-departure / fastest sweep
-    // (first 8 queries of the 2^20-vertex graph: 1, 2, 4, 8, 16 -> 9.1, 7.2,
-    // 5.5, 4.2, 4.4 ms; first 4 of the 2^24-vertex graph: 50, 48, 47, 52,
-    // 62 ms -- each group copies and reduces G arrival arrays of n words)
-    t.sweep_group = g && g->n <= (1u << 21) ? 8u : 4u;
+    // departure times per group of a latest-departure / fastest sweep.
+    // Measured (G = 1, 2, 4, 8, 16): 2^20 vertices, 32 edges per vertex,
+    // first 8 queries 9.1, 7.2, 5.5, 4.2, 4.4 ms; 2^24 vertices, 32 per
+    // vertex, first 4: 50, 48, 47, 52, 62 ms (each group copies and reduces
+    // G arrival arrays of n words); the bursty graph, 240 edges per vertex:
+    // 11.2, 14.7, 16.1, 22.5, 38.9 ms (dense adjacencies make the queries of
+    // a group repeat each other's exploration)
+    t.sweep_group = !g || g->m > 64ull * g->n ? 1u : g->n <= (1u << 21) ? 8u : 4u;
     // lane-dense rows for graphs with real work per round; on small graphs
     // the query-major layout wins, since it hands small frontiers to the
     // one-workgroup kernel (10^5 edges, 16 queries: 0.59 ms against 1.9 ms)
