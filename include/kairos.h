@@ -214,7 +214,9 @@ typedef struct kairos_tuning {
                                 latest-departure / fastest sweep (1..64): each
                                 group runs as that many queries warm-started
                                 from the previous group's last one; 1 = one
-                                departure time after the other                */
+                                departure time after the other; default 1
+                                when m > 64 n, else 8 up to 2^21 vertices,
+                                else 4                                        */
     uint32_t batch_layout;   /* 0: one wavefront per frontier vertex, one lane per
                                 query, arrivals stored vertex-major (edges read
                                 once per 64 queries); 1: one thread per query
