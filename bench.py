@@ -293,7 +293,8 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
     return res
 
 
-def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=2000):
+def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=2000,
+                rounds_per_check=0, fifo=True):
     """Open-loop Poisson arrivals: continuous-batching server versus a FIFO
     server answering one query at a time, on the same trace."""
     from workloads import poisson_arrivals
@@ -304,7 +305,7 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
     res = []
     for rate in rates:
         arr = poisson_arrivals(rate, count, 105 + rate)
-        srv = K.kairos_server_create(G, max_slots=64, queue_capacity=1 << 20)
+        srv = K.kairos_server_create(G, max_slots=64, queue_capacity=1 << 20, rounds_per_check=rounds_per_check)
         lat = {}
         done = 0
         start = time.perf_counter()
@@ -327,19 +328,19 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
         fifo_lat = []
         clock = 0.0
         fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
-        n_fifo = min(count, 400)
+        n_fifo = count if fifo else 0
         for j in range(n_fifo):
             clock = max(clock, arr[j])
             t = time.perf_counter()
             fns[kinds[j]](G, int(srcs[j]), int(ta[j]), int(tw[j]), outs[j])
             clock += time.perf_counter() - t
             fifo_lat.append(clock - arr[j])
-        fl = np.array(fifo_lat)
+        fl = np.array(fifo_lat) if fifo_lat else np.zeros(1)
         res.append({"rate": rate, "served_qps": count / wall, "p50_ms": float(np.percentile(lv, 50) * 1e3),
                     "p99_ms": float(np.percentile(lv, 99) * 1e3),
                     "fifo_qps": n_fifo / clock if clock > 0 else None,
-                    "fifo_p50_ms": float(np.percentile(fl, 50) * 1e3),
-                    "fifo_p99_ms": float(np.percentile(fl, 99) * 1e3), "fifo_queries": n_fifo})
+                    "fifo_p50_ms": float(np.percentile(fl, 50) * 1e3) if n_fifo else None,
+                    "fifo_p99_ms": float(np.percentile(fl, 99) * 1e3) if n_fifo else None, "fifo_queries": n_fifo})
         log(f"serve rate={rate}: {res[-1]}")
     return res
 

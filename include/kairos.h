@@ -293,8 +293,10 @@ int kairos_profile_read(kairos_graph *g, kairos_profile *out);
 
 /* -------------------------------------------------------------- serving --
  * Continuous batching: queries are admitted into slots as they arrive while
- * others are on the device; each scheduler iteration runs one frontier round
- * for every active slot in one launch, then retires finished slots.  A slot
+ * others are on the device; each scheduler iteration runs a few frontier
+ * rounds, each for every active slot in one launch, then retires finished
+ * slots.  Latest-departure / fastest slots move to their next departure time
+ * on the device between rounds.  A slot
  * is admitted only when one is free and the device reports at least the
  * slot's state size plus mem_reserve_bytes free.  The graph stays resident.
  */
@@ -305,6 +307,10 @@ typedef struct kairos_server_opts {
     uint32_t queue_capacity;    /* waiting queries before submit returns BUSY  */
     uint64_t mem_reserve_bytes; /* device memory left free by admission        */
     void *hip_stream;           /* stream for server work, NULL = own stream   */
+    uint32_t rounds_per_check;  /* push rounds between two host checks for
+                                   finished queries (1..64; 0 = 4); more
+                                   rounds spend less time in host round trips,
+                                   fewer let finished queries leave sooner   */
 } kairos_server_opts;
 
 typedef struct kairos_completion {

@@ -58,7 +58,7 @@ class kairos_index_view(ctypes.Structure):
 
 class kairos_server_opts(ctypes.Structure):
     _fields_ = [("max_slots", _u32), ("queue_capacity", _u32), ("mem_reserve_bytes", _u64),
-                ("hip_stream", _p)]
+                ("hip_stream", _p), ("rounds_per_check", _u32)]
 
 
 class kairos_completion(ctypes.Structure):
@@ -343,8 +343,8 @@ class Server:
 
 
 def kairos_server_create(g: Graph, max_slots=32, queue_capacity=1 << 16, mem_reserve_bytes=0,
-                         stream=None) -> Server:
-    o = kairos_server_opts(max_slots, queue_capacity, mem_reserve_bytes, stream)
+                         stream=None, rounds_per_check=0) -> Server:
+    o = kairos_server_opts(max_slots, queue_capacity, mem_reserve_bytes, stream, rounds_per_check)
     h = _p()
     _check(_L.kairos_server_create(g.handle, ctypes.byref(o), ctypes.byref(h)), "kairos_server_create")
     return Server(h.value, g)

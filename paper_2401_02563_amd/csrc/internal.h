@@ -196,17 +196,24 @@ struct MultiState {
     uint4 *chunks = nullptr, *qp = nullptr;
     uint64_t chunk_cap = 0;
     unsigned long long *stats = nullptr;
+    // sweep slots: row q of `steps` (step_cap words) holds the slot's
+    // departure times ascending; step_cnt[q] of them, step_pos[q] started
+    uint32_t *steps = nullptr, *step_cnt = nullptr, *step_pos = nullptr;
+    uint32_t step_cap = 0;
     uint32_t round = 0, stamp_next = 2;
     hipStream_t stream = nullptr;
 };
-// One slot start or sweep step: qp[q] = {src, ta, tw, sdep}; the source
-// starts at sdep (ta when sdep == INF, a plain earliest-arrival query).
+// One slot start: qp[q] = {src, ta, tw, sdep}; the source starts at sdep
+// (ta when sdep == INF, a plain earliest-arrival query).  A sweep slot
+// (sweep = 1) only takes its parameters: its steps start the source.
 struct Inject {
-    uint32_t q, src, ta, tw, sdep, pad0, pad1, pad2;
+    uint32_t q, src, ta, tw, sdep, sweep, pad1, pad2;
 };
 int multi_push_round(kairos_graph *g, MultiState *ms);
 int multi_inject(kairos_graph *g, MultiState *ms, const Inject *host_pinned, uint32_t count);
 int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count);
+int multi_sweep_steps(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count);
+int multi_advance(kairos_graph *g, MultiState *ms);
 int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32_t src, uint32_t tw,
                    uint32_t *out);
 

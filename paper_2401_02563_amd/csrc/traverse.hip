@@ -1887,6 +1887,7 @@ __global__ void inject_kernel(TravArgs A, const Inject *__restrict__ list, uint3
         const Inject in = list[i];
         ((uint4 *)A.qp)[in.q] = make_uint4(in.src, in.ta, in.tw, in.sdep);
         A.fpar[in.q] = filter_params(in.ta, in.tw, A.max_a, A.fbits);
+        if (in.sweep) continue;  // a sweep slot's source starts with its first step
         const size_t ss = (size_t)in.q * A.n + in.src;
         // stamp 0: older than every round's stamp, so the source's first
         // improvement (a sweep step) still enqueues it
@@ -1896,12 +1897,90 @@ __global__ void inject_kernel(TravArgs A, const Inject *__restrict__ list, uint3
     }
 }
 
+// Departure times of the sweep slots in `list`, on the device: the distinct
+// departure times t >= t_alpha of the source's out-edges that arrive by
+// t_omega, ascending, into the slot's row of `steps` (at most the largest
+// out-degree).  Edges of equal departure time sit in ascending arrival
+// order, so a time qualifies iff the first edge of its group arrives by
+// t_omega.  One block of SB threads per slot; the block compacts in order.
+constexpr int SB = 256;
+
+__global__ __launch_bounds__(SB) void sweep_steps_kernel(TravArgs A, const uint32_t *__restrict__ list,
+                                                          uint32_t *steps, uint32_t cap, uint32_t *step_cnt,
+                                                          uint32_t *step_pos)
+{
+    __shared__ uint32_t s_w[SB / 64];
+    __shared__ uint32_t s_base;
+    const uint32_t q = list[blockIdx.x];
+    const uint4 p = A.qp[q];
+    const uint32_t b = A.off[p.x], e = A.off[p.x + 1];
+    const uint32_t lo = lower_bound_u32(A.tt, b, e, p.y);
+    const uint32_t hi = lower_bound_u32(A.tt, lo, e, p.z);  // departing at t_omega or later arrives after it
+    uint32_t *row = steps + (size_t)q * cap;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_base = 0;
+    __syncthreads();
+    for (uint32_t j0 = lo; j0 < hi; j0 += SB) {
+        const uint32_t j = j0 + threadIdx.x;
+        bool f = false;
+        uint32_t t = 0;
+        if (j < hi) {
+            t = A.tt[j];
+            f = (j == b || A.tt[j - 1] != t) && A.da[j].y <= p.z;
+        }
+        const unsigned long long bal = __ballot(f);
+        if (lane == 0) s_w[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t off = s_base, tot = 0;
+        for (int k = 0; k < SB / 64; ++k) {
+            if (k < w) off += s_w[k];
+            tot += s_w[k];
+        }
+        if (f) row[off + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) s_base += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        step_cnt[q] = s_base;
+        step_pos[q] = 0u;
+    }
+}
+
+// Between rounds: a sweep slot that enqueued nothing for the coming round
+// (its flag is older than the round) starts its next departure time, latest
+// first, warm-started from the arrivals and claims it holds.  One thread
+// per slot; `A.next` is the coming round's queue.
+__global__ void advance_steps_kernel(TravArgs A, const uint32_t *__restrict__ steps, uint32_t cap,
+                                     const uint32_t *__restrict__ step_cnt, uint32_t *step_pos, uint32_t nslots)
+{
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nslots; q += gridDim.x * blockDim.x) {
+        const uint32_t c = step_cnt[q], k = step_pos[q];
+        if (k >= c || A.qflag[q] == A.round) continue;
+        const uint32_t sd = steps[(size_t)q * cap + (c - 1u - k)];
+        const uint32_t src = A.qp[q].x;
+        ((uint4 *)A.qp)[q].w = sd;
+        const size_t ss = (size_t)q * A.n + src;
+        A.av[ss] = av_word(min(arrival_of(A.av, ss), sd), 0u);
+        const uint32_t pos = atomicAdd(&A.cnt[CNT_FRONT + A.round % 3u], 1u);
+        A.next[pos] = (uint32_t)ss;
+        A.qflag[q] = A.round;
+        step_pos[q] = k + 1u;
+    }
+}
+
 // Fresh state for the listed slots: arrival, claims and fastest = INF,
-// latest departure + 1 = 0, no arrival bound.  Block (x, y): slot list[y],
-// stride over n.
-__global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list, uint8_t *filt)
+// latest departure + 1 = 0, no arrival bound, no sweep steps, no activity
+// flag.  Block (x, y): slot list[y], stride over n.
+__global__ void init_slots_kernel(TravArgs A, const uint32_t *__restrict__ list, uint8_t *filt, uint32_t *step_cnt,
+                                  uint32_t *step_pos)
 {
     const size_t base = (size_t)list[blockIdx.y] * A.n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        step_cnt[list[blockIdx.y]] = 0u;
+        step_pos[list[blockIdx.y]] = 0u;
+        A.qflag[list[blockIdx.y]] = INF;  // never a round number
+    }
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.n; v += gridDim.x * blockDim.x) {
         A.av[base + v] = av_word(INF, 0u);
         A.done[base + v] = INF;
@@ -1991,7 +2070,27 @@ int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinne
     if (!count) return KAIROS_OK;
     TravArgs A = multi_args(g, ms);
     hipLaunchKernelGGL(init_slots_kernel, dim3(grid_cap(g->n, 256 * 4, 256), count), dim3(256), 0,
-                       ms->stream, A, host_pinned, ms->filt);
+                       ms->stream, A, host_pinned, ms->filt, ms->step_cnt, ms->step_pos);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_sweep_steps(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count)
+{
+    if (!count) return KAIROS_OK;
+    TravArgs A = multi_args(g, ms);
+    hipLaunchKernelGGL(sweep_steps_kernel, dim3(count), dim3(SB), 0, ms->stream, A, host_pinned, ms->steps,
+                       ms->step_cap, ms->step_cnt, ms->step_pos);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_advance(kairos_graph *g, MultiState *ms)
+{
+    TravArgs A = multi_args(g, ms);
+    A.next = ms->queue[0];
+    hipLaunchKernelGGL(advance_steps_kernel, dim3(grid_cap(ms->qcap, 256, 64)), dim3(256), 0, ms->stream, A,
+                       ms->steps, ms->step_cap, ms->step_cnt, ms->step_pos, ms->qcap);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;
 }

@@ -55,25 +55,28 @@ def expected(se, kind, s, a, w):
     return (ea, ld, fa)[kind]
 
 
-@pytest.mark.parametrize("name,shift,t_lo,t_hi,codes", [("uniform-10k", 0, 0, 99_999, None),
-                                                         ("rmat20-32m", 6, 0, (1 << 30) - 1, None),
-                                                         ("rmat20-32m", 6, 0, (1 << 30) - 1, 2)])
-def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi, codes):
+@pytest.mark.parametrize("name,shift,t_lo,t_hi,codes,rpc", [("uniform-10k", 0, 0, 99_999, None, 0),
+                                                             ("uniform-10k", 0, 0, 99_999, None, 1),
+                                                             ("uniform-10k", 0, 0, 99_999, None, 5),
+                                                             ("rmat20-32m", 6, 0, (1 << 30) - 1, None, 0),
+                                                             ("rmat20-32m", 6, 0, (1 << 30) - 1, 2, 3)])
+def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi, codes, rpc):
     g, G, se = graph(name, shift)
+    print("case: mixed stream", name, shift, codes, rpc, flush=True)
     old = K.kairos_get_tuning(G)
     if codes is not None:
         K.kairos_set_tuning(G, arrival_filter=codes)
     try:
-        _mixed_stream(g, G, se, t_lo, t_hi)
+        _mixed_stream(g, G, se, t_lo, t_hi, rpc)
     finally:
         K.kairos_set_tuning(G, **old)
 
 
-def _mixed_stream(g, G, se, t_lo, t_hi):
+def _mixed_stream(g, G, se, t_lo, t_hi, rpc):
     count = 120
     src, ta, tw, kinds = mixed_queries(g, count, 7, t_lo, t_hi)
     outs = torch.full((count, g.n), 7, dtype=torch.int32, device="cuda")
-    srv = K.kairos_server_create(G, max_slots=8, queue_capacity=4096)
+    srv = K.kairos_server_create(G, max_slots=8, queue_capacity=4096, rounds_per_check=rpc)
     tickets = {}
 
     def producer():
@@ -146,3 +149,30 @@ def test_slot_reuse_has_no_stale_state():
     K.kairos_server_free(srv)
     for i in tickets.values():
         assert np.array_equal(K.as_u32(outs[i]), expected(se, int(kinds[i]), src[i], ta[i], tw[i])), i
+
+
+@pytest.mark.parametrize("rpc", [1, 4])
+def test_sweeps_with_no_and_many_departures(rpc):
+    """Latest departure and fastest through the server for sources whose
+    departure list is empty (no out-edges, or a window no edge fits) and for
+    the source with the most out-edges (the longest step list), mixed with
+    earliest-arrival queries; each equals the oracle."""
+    g, G, se = graph("uniform-10k", 0)
+    print("case: sweep departures", rpc, flush=True)
+    outdeg = np.bincount(g.src, minlength=g.n)
+    hub = int(np.argmax(outdeg))
+    cases = [(1, hub, 0, 99_999), (2, hub, 0, 99_999), (1, hub, 40_000, 99_999), (2, hub, 99_990, 99_999),
+             (1, hub, 50_000, 50_001), (0, hub, 0, 99_999)]
+    lonely = np.flatnonzero(outdeg == 0)
+    if lonely.size:
+        cases += [(1, int(lonely[0]), 0, 99_999), (2, int(lonely[0]), 0, 99_999)]
+    srv = K.kairos_server_create(G, max_slots=3, queue_capacity=64, rounds_per_check=rpc)
+    outs = torch.full((len(cases), g.n), 7, dtype=torch.int32, device="cuda")
+    tickets = {K.kairos_server_submit(srv, k, s_, a, w, outs[i]): i for i, (k, s_, a, w) in enumerate(cases)}
+    done = drain(srv, len(cases))
+    K.kairos_server_free(srv)
+    for tk, c in done.items():
+        i = tickets[tk]
+        k, s_, a, w = cases[i]
+        assert c["status"] == 0
+        assert np.array_equal(K.as_u32(outs[i]), expected(se, k, s_, a, w)), cases[i]
