@@ -293,56 +293,84 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
     return res
 
 
-def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=2000,
-                rounds_per_check=0, fifo=True):
+def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=20000,
+                warmup=1000, rounds_per_check=0, fifo=True, pool=4096):
     """Open-loop Poisson arrivals: continuous-batching server versus a FIFO
-    server answering one query at a time, on the same trace."""
+    server answering one query at a time, on the same trace of `count`
+    queries per rate.  The server first answers `warmup` other queries
+    (closed loop, growing its slot pool).  Latency runs from the query's
+    arrival time to its completion; queries wait on the client side while
+    all `pool` output buffers are in flight."""
     from workloads import poisson_arrivals
     from workloads.configs import make_kinds
-    srcs, ta, tw = make_queries_log(name, g, count)
-    kinds = make_kinds("serve-rmat20", count)
-    outs = torch.empty((count, g.n), dtype=torch.int32, device="cuda")
+    total = count + warmup
+    srcs, ta, tw = make_queries_log(name, g, total)
+    kinds = make_kinds("serve-rmat20", total)
+    pool = min(pool, total)
+    outs = torch.empty((pool, g.n), dtype=torch.int32, device="cuda")
+    fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
+    for k in range(3):  # first call of each kind allocates its state
+        fns[k](G, int(srcs[0]), int(ta[0]), int(tw[0]), outs[0])
+    torch.cuda.synchronize()
     res = []
     for rate in rates:
-        arr = poisson_arrivals(rate, count, 105 + rate)
         srv = K.kairos_server_create(G, max_slots=64, queue_capacity=1 << 20, rounds_per_check=rounds_per_check)
-        lat = {}
+        for j in range(warmup):
+            K.kairos_server_submit(srv, int(kinds[j]), int(srcs[j]), int(ta[j]), int(tw[j]), outs[j % pool])
+            if j % pool == pool - 1:
+                _drain(K, srv, pool)
+        _drain(K, srv, warmup % pool)
+        arr = poisson_arrivals(rate, count, 105 + rate)
+        free = list(range(pool))
+        inflight = {}
+        lat = np.empty(count)
         done = 0
-        start = time.perf_counter()
         i = 0
-        t_sub = {}
+        start = time.monotonic_ns()
+        last = start
         while done < count:
-            now = time.perf_counter() - start
-            while i < count and arr[i] <= now:
-                tk = K.kairos_server_submit(srv, int(kinds[i]), int(srcs[i]), int(ta[i]), int(tw[i]), outs[i])
-                t_sub[tk] = arr[i]
+            now = (time.monotonic_ns() - start) * 1e-9
+            while i < count and arr[i] <= now and free:
+                b = free.pop()
+                q = warmup + i
+                tk = K.kairos_server_submit(srv, int(kinds[q]), int(srcs[q]), int(ta[q]), int(tw[q]), outs[b])
+                inflight[tk] = (b, arr[i])
                 i += 1
             for c in K.kairos_server_poll(srv, 4096):
-                lat[c["ticket"]] = (c["t_done_ns"] - c["t_submit_ns"]) * 1e-9
+                b, a = inflight.pop(c["ticket"])
+                free.append(b)
+                lat[done] = (c["t_done_ns"] - start) * 1e-9 - a
+                last = max(last, c["t_done_ns"])
                 done += 1
             time.sleep(0.0001)
-        wall = time.perf_counter() - start
+        wall = (last - start) * 1e-9
         K.kairos_server_free(srv)
-        lv = np.array(list(lat.values()))
         # FIFO one-at-a-time on the same trace (virtual clock)
         fifo_lat = []
         clock = 0.0
-        fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
         n_fifo = count if fifo else 0
         for j in range(n_fifo):
+            q = warmup + j
             clock = max(clock, arr[j])
             t = time.perf_counter()
-            fns[kinds[j]](G, int(srcs[j]), int(ta[j]), int(tw[j]), outs[j])
+            fns[kinds[q]](G, int(srcs[q]), int(ta[q]), int(tw[q]), outs[0])
             clock += time.perf_counter() - t
             fifo_lat.append(clock - arr[j])
         fl = np.array(fifo_lat) if fifo_lat else np.zeros(1)
-        res.append({"rate": rate, "served_qps": count / wall, "p50_ms": float(np.percentile(lv, 50) * 1e3),
-                    "p99_ms": float(np.percentile(lv, 99) * 1e3),
-                    "fifo_qps": n_fifo / clock if clock > 0 else None,
+        res.append({"rate": rate, "queries": count, "warmup": warmup, "served_qps": count / wall,
+                    "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                    "fifo_qps": float(n_fifo / clock) if clock > 0 else None,
                     "fifo_p50_ms": float(np.percentile(fl, 50) * 1e3) if n_fifo else None,
-                    "fifo_p99_ms": float(np.percentile(fl, 99) * 1e3) if n_fifo else None, "fifo_queries": n_fifo})
+                    "fifo_p99_ms": float(np.percentile(fl, 99) * 1e3) if n_fifo else None})
         log(f"serve rate={rate}: {res[-1]}")
     return res
+
+
+def _drain(K, srv, want):
+    got = 0
+    while got < want:
+        got += len(K.kairos_server_poll(srv, 4096))
+        time.sleep(0.0001)
 
 
 def make_queries_log(name, g, count):
