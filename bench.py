@@ -294,7 +294,7 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
 
 
 def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 50000), count=20000,
-                warmup=1000, rounds_per_check=0, fifo=True, pool=4096):
+                warmup=1000, rounds_per_check=0, fifo=True, pool=4096, max_slots=256):
     """Open-loop Poisson arrivals: continuous-batching server versus a FIFO
     server answering one query at a time, on the same trace of `count`
     queries per rate.  The server first answers `warmup` other queries
@@ -314,7 +314,8 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
     torch.cuda.synchronize()
     res = []
     for rate in rates:
-        srv = K.kairos_server_create(G, max_slots=64, queue_capacity=1 << 20, rounds_per_check=rounds_per_check)
+        srv = K.kairos_server_create(G, max_slots=max_slots, queue_capacity=1 << 20,
+                                     rounds_per_check=rounds_per_check)
         for j in range(warmup):
             K.kairos_server_submit(srv, int(kinds[j]), int(srcs[j]), int(ta[j]), int(tw[j]), outs[j % pool])
             if j % pool == pool - 1:

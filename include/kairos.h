@@ -295,8 +295,9 @@ int kairos_profile_read(kairos_graph *g, kairos_profile *out);
  * Continuous batching: queries are admitted into slots as they arrive while
  * others are on the device; each scheduler iteration runs a few frontier
  * rounds, each for every active slot in one launch, then retires finished
- * slots.  Latest-departure / fastest slots move to their next departure time
- * on the device between rounds.  A slot
+ * slots.  A latest-departure / fastest query moves to its next departure
+ * time on the device between rounds, or, while slots are plentiful, runs
+ * groups of departure times (tuning sweep_group) on consecutive slots.  A slot
  * is admitted only when one is free and the device reports at least the
  * slot's state size plus mem_reserve_bytes free.  The graph stays resident.
  */

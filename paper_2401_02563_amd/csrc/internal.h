@@ -214,6 +214,14 @@ int multi_inject(kairos_graph *g, MultiState *ms, const Inject *host_pinned, uin
 int multi_init_slots(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count);
 int multi_sweep_steps(kairos_graph *g, MultiState *ms, const uint32_t *host_pinned, uint32_t count);
 int multi_advance(kairos_graph *g, MultiState *ms);
+// A grouped sweep's next `width` departure times on slots lead .. lead +
+// width - 1, from step pos0 of the lead's list.
+struct GroupStart {
+    uint32_t lead, width, pos0, src, tw, pad0, pad1, pad2;
+};
+int multi_group_start(kairos_graph *g, MultiState *ms, const GroupStart *host_pinned, uint32_t count);
+int multi_group_reduce(kairos_graph *g, MultiState *ms, uint32_t lead, uint32_t width);
+int multi_group_warm(kairos_graph *g, MultiState *ms, uint32_t lead, uint32_t width, uint32_t from);
 int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32_t src, uint32_t tw,
                    uint32_t *out);
 

@@ -1969,6 +1969,59 @@ __global__ void advance_steps_kernel(TravArgs A, const uint32_t *__restrict__ st
     }
 }
 
+// Grouped sweep in the server: the query's departure times (its lead slot's
+// row, latest first) are taken `width` at a time by the consecutive slots
+// lead .. lead + width - 1.  Member j of a group starting at step pos0 runs
+// the earliest-arrival query leaving the source at its step s (t_alpha = s,
+// no sweep accumulators, no arrival codes), warm-started from what the slot
+// holds; a member without a step gets t_alpha = INF and no frontier.  The
+// lead's own device stepping is switched off.  One thread per member.
+__global__ void group_start_kernel(TravArgs A, const GroupStart *__restrict__ list, uint32_t count,
+                                   const uint32_t *__restrict__ steps, uint32_t cap, const uint32_t *__restrict__ step_cnt,
+                                   uint32_t *step_pos)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count * 64u; i += gridDim.x * blockDim.x) {
+        const GroupStart e = list[i >> 6];
+        const uint32_t j = i & 63u;
+        if (j >= e.width) continue;
+        const uint32_t m = e.lead + j, k = e.pos0 + j, c = step_cnt[e.lead];
+        if (j == 0) step_pos[e.lead] = INF;
+        if (k >= c) {
+            ((uint4 *)A.qp)[m] = make_uint4(e.src, INF, e.tw, INF);
+            continue;
+        }
+        const uint32_t sd = steps[(size_t)e.lead * cap + (c - 1u - k)];
+        ((uint4 *)A.qp)[m] = make_uint4(e.src, sd, e.tw, INF);
+        A.fpar[m] = filter_params(sd, e.tw, A.max_a, 0u);
+        const size_t ss = (size_t)m * A.n + e.src;
+        A.av[ss] = av_word(min(arrival_of(A.av, ss), sd), 0u);
+        const uint32_t pos = atomicAdd(&A.cnt[CNT_FRONT + A.round % 3u], 1u);
+        A.next[pos] = (uint32_t)ss;
+    }
+}
+
+// After a group: member j holds the earliest arrivals for the source leaving
+// at its t_alpha, so the lead's F[v] = min(F[v], EA_j[v] - t_alpha_j) and,
+// where v is reached, L1[v] = max(L1[v], t_alpha_j + 1).
+__global__ void group_reduce_kernel(TravArgs A, uint32_t lead, uint32_t width)
+{
+    const size_t base = (size_t)lead * A.n;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.n; v += gridDim.x * blockDim.x) {
+        uint32_t f = A.fa[base + v], l = A.l1[base + v];
+        for (uint32_t j = 0; j < width; ++j) {
+            const uint32_t d = A.qp[lead + j].y;
+            if (d == INF) continue;
+            const uint32_t a = arrival_of(A.av, base + (size_t)j * A.n + v);
+            if (a != INF) {
+                f = min(f, a - d);
+                l = max(l, d + 1u);
+            }
+        }
+        A.fa[base + v] = f;
+        A.l1[base + v] = l;
+    }
+}
+
 // Fresh state for the listed slots: arrival, claims and fastest = INF,
 // latest departure + 1 = 0, no arrival bound, no sweep steps, no activity
 // flag.  Block (x, y): slot list[y], stride over n.
@@ -2081,6 +2134,35 @@ int multi_sweep_steps(kairos_graph *g, MultiState *ms, const uint32_t *host_pinn
     TravArgs A = multi_args(g, ms);
     hipLaunchKernelGGL(sweep_steps_kernel, dim3(count), dim3(SB), 0, ms->stream, A, host_pinned, ms->steps,
                        ms->step_cap, ms->step_cnt, ms->step_pos);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_group_start(kairos_graph *g, MultiState *ms, const GroupStart *host_pinned, uint32_t count)
+{
+    if (!count) return KAIROS_OK;
+    TravArgs A = multi_args(g, ms);
+    A.next = ms->queue[0];
+    hipLaunchKernelGGL(group_start_kernel, dim3(grid_cap((uint64_t)count * 64, 256, 64)), dim3(256), 0, ms->stream,
+                       A, host_pinned, count, ms->steps, ms->step_cap, ms->step_cnt, ms->step_pos);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_group_reduce(kairos_graph *g, MultiState *ms, uint32_t lead, uint32_t width)
+{
+    TravArgs A = multi_args(g, ms);
+    hipLaunchKernelGGL(group_reduce_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, ms->stream, A, lead,
+                       width);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+int multi_group_warm(kairos_graph *g, MultiState *ms, uint32_t lead, uint32_t width, uint32_t from)
+{
+    const size_t base = (size_t)lead * g->n;
+    hipLaunchKernelGGL(warm_slots_kernel, dim3(grid_cap(g->n, 256, 4096)), dim3(256), 0, ms->stream, ms->av + base,
+                       ms->done + base, g->n, width, from);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;
 }

@@ -55,17 +55,20 @@ def expected(se, kind, s, a, w):
     return (ea, ld, fa)[kind]
 
 
-@pytest.mark.parametrize("name,shift,t_lo,t_hi,codes,rpc", [("uniform-10k", 0, 0, 99_999, None, 0),
-                                                             ("uniform-10k", 0, 0, 99_999, None, 1),
-                                                             ("uniform-10k", 0, 0, 99_999, None, 5),
-                                                             ("rmat20-32m", 6, 0, (1 << 30) - 1, None, 0),
-                                                             ("rmat20-32m", 6, 0, (1 << 30) - 1, 2, 3)])
-def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi, codes, rpc):
+@pytest.mark.parametrize("name,shift,t_lo,t_hi,codes,rpc,group", [
+    ("uniform-10k", 0, 0, 99_999, None, 0, None),
+    ("uniform-10k", 0, 0, 99_999, None, 1, 1),
+    ("uniform-10k", 0, 0, 99_999, None, 5, 3),
+    ("rmat20-32m", 6, 0, (1 << 30) - 1, None, 0, None),
+    ("rmat20-32m", 6, 0, (1 << 30) - 1, 2, 3, 1)])
+def test_mixed_stream_equals_alone_and_oracle(name, shift, t_lo, t_hi, codes, rpc, group):
     g, G, se = graph(name, shift)
-    print("case: mixed stream", name, shift, codes, rpc, flush=True)
+    print("case: mixed stream", name, shift, codes, rpc, group, flush=True)
     old = K.kairos_get_tuning(G)
     if codes is not None:
         K.kairos_set_tuning(G, arrival_filter=codes)
+    if group is not None:
+        K.kairos_set_tuning(G, sweep_group=group)
     try:
         _mixed_stream(g, G, se, t_lo, t_hi, rpc)
     finally:
@@ -151,14 +154,26 @@ def test_slot_reuse_has_no_stale_state():
         assert np.array_equal(K.as_u32(outs[i]), expected(se, int(kinds[i]), src[i], ta[i], tw[i])), i
 
 
-@pytest.mark.parametrize("rpc", [1, 4])
-def test_sweeps_with_no_and_many_departures(rpc):
+@pytest.mark.parametrize("rpc,group,slots", [(1, 0, 3), (4, 0, 3), (2, 1, 3), (3, 2, 8), (4, 8, 16)])
+def test_sweeps_with_no_and_many_departures(rpc, group, slots):
     """Latest departure and fastest through the server for sources whose
     departure list is empty (no out-edges, or a window no edge fits) and for
     the source with the most out-edges (the longest step list), mixed with
-    earliest-arrival queries; each equals the oracle."""
+    earliest-arrival queries; each equals the oracle.  Sweeps step on one
+    slot (group 1) or run groups of departure times on consecutive slots,
+    also with fewer free slots than the group width."""
     g, G, se = graph("uniform-10k", 0)
-    print("case: sweep departures", rpc, flush=True)
+    print("case: sweep departures", rpc, group, slots, flush=True)
+    old = K.kairos_get_tuning(G)
+    if group:
+        K.kairos_set_tuning(G, sweep_group=group)
+    try:
+        _sweep_departures(g, G, se, rpc, slots)
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+def _sweep_departures(g, G, se, rpc, slots):
     outdeg = np.bincount(g.src, minlength=g.n)
     hub = int(np.argmax(outdeg))
     cases = [(1, hub, 0, 99_999), (2, hub, 0, 99_999), (1, hub, 40_000, 99_999), (2, hub, 99_990, 99_999),
@@ -166,7 +181,7 @@ def test_sweeps_with_no_and_many_departures(rpc):
     lonely = np.flatnonzero(outdeg == 0)
     if lonely.size:
         cases += [(1, int(lonely[0]), 0, 99_999), (2, int(lonely[0]), 0, 99_999)]
-    srv = K.kairos_server_create(G, max_slots=3, queue_capacity=64, rounds_per_check=rpc)
+    srv = K.kairos_server_create(G, max_slots=slots, queue_capacity=64, rounds_per_check=rpc)
     outs = torch.full((len(cases), g.n), 7, dtype=torch.int32, device="cuda")
     tickets = {K.kairos_server_submit(srv, k, s_, a, w, outs[i]): i for i, (k, s_, a, w) in enumerate(cases)}
     done = drain(srv, len(cases))
