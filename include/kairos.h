@@ -85,9 +85,11 @@ void kairos_graph_free(kairos_graph *g);
 int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t *device_bytes);
 
 /* Device pointers of the index, for inspection (read only, owned by g).
- * The index numbers vertices internally in order of decreasing in-degree
- * (ties by caller id), so that the arrival words of the most-targeted
- * vertices share cache lines; perm[v] is the internal id of caller vertex v.
+ * The index numbers vertices internally: the n_live vertices with out-edges
+ * first, then the others, each part in order of decreasing in-degree (ties
+ * by caller id), so that the arrival words of the most-targeted vertices
+ * share cache lines and a vertex with nothing to expand is known by its id;
+ * perm[v] is the internal id of caller vertex v.
  * All calls take and return caller ids.  In internal ids:
  *   off_out[n+1]  first out-edge of each tail;  out-edge e has
  *   t_out[e], and dst_a_out[2e], dst_a_out[2e+1] = head, arrival;
@@ -97,6 +99,7 @@ typedef struct kairos_index_view {
     const uint32_t *off_out, *t_out, *dst_a_out;
     const uint32_t *off_in, *a_in, *src_t_in;
     const uint32_t *perm;
+    uint32_t n_live;
 } kairos_index_view;
 int kairos_graph_index(const kairos_graph *g, kairos_index_view *view);
 

@@ -53,7 +53,8 @@ class kairos_profile(ctypes.Structure):
 
 
 class kairos_index_view(ctypes.Structure):
-    _fields_ = [(k, _p) for k in ("off_out", "t_out", "dst_a_out", "off_in", "a_in", "src_t_in", "perm")]
+    _fields_ = [(k, _p) for k in ("off_out", "t_out", "dst_a_out", "off_in", "a_in", "src_t_in", "perm")] + [
+        ("n_live", _u32)]
 
 
 class kairos_server_opts(ctypes.Structure):
@@ -210,7 +211,7 @@ def kairos_graph_index(g: Graph) -> dict:
     return dict(off_out=_copy_from_device(v.off_out, n + 1), t_out=_copy_from_device(v.t_out, m),
                 dst_a_out=_copy_from_device(v.dst_a_out, 2 * m), off_in=_copy_from_device(v.off_in, n + 1),
                 a_in=_copy_from_device(v.a_in, m), src_t_in=_copy_from_device(v.src_t_in, 2 * m),
-                perm=_copy_from_device(v.perm, n))
+                perm=_copy_from_device(v.perm, n), n_live=int(v.n_live))
 
 
 def _single(name, g, src, ta, tw, out):

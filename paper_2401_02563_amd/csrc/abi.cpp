@@ -180,6 +180,7 @@ int kairos_graph_index(const kairos_graph *g, kairos_index_view *view)
     view->a_in = g->a_in;
     view->src_t_in = (const uint32_t *)g->st_in;
     view->perm = g->perm;
+    view->n_live = g->n_live;
     return KAIROS_OK;
 }
 

@@ -60,6 +60,7 @@ struct BArgs {
     uint32_t chunk;
     uint32_t max_t;                  // largest departure time in the graph
     uint32_t dedupe;                 // one atomic per run of lanes into the same slot
+    uint32_t n_live;                 // vertices from this id on have no out-edges: never enqueued
 };
 
 enum : int { BCNT_RANGE = 10 };  // [10..12] rotating range-table sizes
@@ -136,7 +137,8 @@ __device__ __forceinline__ void relax_span(const BArgs &A, uint32_t g, uint32_t 
             }
             // lanes 0..BU-1 publish the improved heads in parallel
             bool first = false;
-            if (mymask) {
+            // a head without out-edges never joins the frontier
+            if (mymask && myv < A.n_live) {
                 const unsigned long long old = atomicOr(&A.mask_next[gbase + myv], mymask);
                 first = old == 0ull;
             }
@@ -294,13 +296,14 @@ __device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, uns
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] < old[k];
         n_relax += H.ok[k] ? 1ull : 0ull;
-        if (H.ok[k]) om[k] = atomicOr(&A.mask_next[(size_t)H.row[k] + H.v[k]], 1ull << H.bit[k]);
+        // a head without out-edges never joins the frontier
+        if (H.ok[k] && H.v[k] < A.n_live) om[k] = atomicOr(&A.mask_next[(size_t)H.row[k] + H.v[k]], 1ull << H.bit[k]);
     }
     unsigned long long bal[HU];
     uint32_t head[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
-        bal[k] = __ballot(H.ok[k] && om[k] == 0ull);
+        bal[k] = __ballot(H.ok[k] && H.v[k] < A.n_live && om[k] == 0ull);
         head[k] = H.row[k] + H.v[k];
     }
     stage_append(S, bal, head);
@@ -834,6 +837,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 16);
     A.max_t = g->max_t;
     A.dedupe = g->tuning.run_dedupe;
+    A.n_live = g->n_live;
     A.round = 0;
     A.mask_cur = b->mask[0];
     A.mask_next = b->mask[1];

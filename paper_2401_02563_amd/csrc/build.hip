@@ -302,19 +302,46 @@ __global__ void repeat_heads_kernel(const uint2 *__restrict__ da, uint64_t m, un
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
-// Vertex relabelling: new ids in order of decreasing in-degree (ties by id),
-// so the arrival words of the most-targeted heads share cache lines.
-__global__ void indegree_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t *deg)
+// Vertex relabelling: vertices with out-edges first, then those without;
+// within each part in order of decreasing in-degree (ties by id), so the
+// arrival words of the most-targeted heads share cache lines, and whether a
+// head has anything to expand is one comparison of its id.
+__global__ void indegree_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t *deg, uint32_t *has_out)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&deg[e[i].y], 1u);
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 r = e[i];
+        atomicAdd(&deg[r.y], 1u);
+        has_out[r.x] = 1u;  // racing stores of the same value
+    }
 }
 
-__global__ void vertex_keys_kernel(const uint32_t *__restrict__ deg, uint32_t n, uint4 *out)
+// sort key: bit 31 set for a vertex without out-edges, below it the
+// in-degree complemented (clamped to 31 bits), so ascending keys give the
+// order above
+__global__ void vertex_keys_kernel(const uint32_t *__restrict__ deg, const uint32_t *__restrict__ has_out, uint32_t n,
+                                   uint4 *out)
 {
-    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x)
-        out[v] = make_uint4(~deg[v], (uint32_t)v, 0u, 0u);  // ascending ~deg = descending in-degree
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = (has_out[v] ? 0u : 0x80000000u) | (0x7FFFFFFFu - min(deg[v], 0x7FFFFFFFu));
+        out[v] = make_uint4(key, (uint32_t)v, 0u, 0u);
+    }
+}
+
+// Number of vertices with out-edges: after relabelling they are the ids
+// below the first v with off_out[v] == m (one thread, binary search).
+__global__ void live_count_kernel(const uint32_t *__restrict__ off_out, uint32_t n, uint32_t m, uint32_t *out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (off_out[mid] < m)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    *out = lo;
 }
 
 __global__ void perm_kernel(const uint4 *__restrict__ sorted, uint32_t n, uint32_t *perm, uint32_t *inv)
@@ -475,17 +502,20 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         add_field(in_p, F_A, bits_for(max_a), 0);
         add_field(in_p, F_DST, nb, 0);
         {
-            // relabel: in-degrees, stable sort of vertices by descending
-            // in-degree, then remap both endpoints of every record
+            // relabel: in-degrees and out-edge marks, stable sort of the
+            // vertices (out-edges first, then descending in-degree), then
+            // remap both endpoints of every record
             uint64_t vs = 0;
             const uint64_t vtiles = ((uint64_t)n + STILE - 1) / STILE;
             const uint32_t vblocks = (uint32_t)std::min<uint64_t>(vtiles, 1024);
             uint32_t *deg = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)n, &vs);
+            uint32_t *has_out = (uint32_t *)dev_alloc(sizeof(uint32_t) * (size_t)n, &vs);
             uint4 *va = (uint4 *)dev_alloc(sizeof(uint4) * (size_t)n, &vs);
             uint4 *vb = (uint4 *)dev_alloc(sizeof(uint4) * (size_t)n, &vs);
             uint32_t *vhist = (uint32_t *)dev_alloc(sizeof(uint32_t) * 256 * (size_t)vblocks, &vs);
-            if (!deg || !va || !vb || !vhist) {
+            if (!deg || !has_out || !va || !vb || !vhist) {
                 dev_free(deg);
+                dev_free(has_out);
                 dev_free(va);
                 dev_free(vb);
                 dev_free(vhist);
@@ -493,9 +523,11 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
                 break;
             }
             prof_begin(g, st, &ev);
-            const bool okm = hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st) == hipSuccess;
-            hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, a, m, deg);
-            hipLaunchKernelGGL(vertex_keys_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, deg, n, va);
+            const bool okm = hipMemsetAsync(deg, 0, sizeof(uint32_t) * (size_t)n, st) == hipSuccess &&
+                             hipMemsetAsync(has_out, 0, sizeof(uint32_t) * (size_t)n, st) == hipSuccess;
+            hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(m, 256, 16384)), dim3(256), 0, st, a, m, deg, has_out);
+            hipLaunchKernelGGL(vertex_keys_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, deg, has_out, n,
+                               va);
             prof_end(g, st, KAIROS_K_SORT, ev);
             std::vector<Pass> vp;
             add_field(vp, F_SRC, 32, 0);
@@ -508,6 +540,7 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
             }
             hipStreamSynchronize(st);
             dev_free(deg);
+            dev_free(has_out);
             dev_free(va);
             dev_free(vb);
             dev_free(vhist);
@@ -525,18 +558,22 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
     } while (0);
     if (rc == KAIROS_OK) {
         // the 64 bytes past the histograms: max out-degree at byte 32, the
-        // repeat count (8-byte aligned) at byte 40
+        // repeat count (8-byte aligned) at byte 40, vertices with out-edges
+        // at byte 48
         uint32_t *d_max = hist + 256 * (size_t)nblocks + 8;
         unsigned long long *d_rep = (unsigned long long *)(hist + 256 * (size_t)nblocks + 10);
+        uint32_t *d_live = hist + 256 * (size_t)nblocks + 12;
         hipMemsetAsync(d_max, 0, 4, st);
         hipMemsetAsync(d_rep, 0, 8, st);
         hipLaunchKernelGGL(max_degree_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st,
                            g->off_out, n, d_max);
         hipLaunchKernelGGL(repeat_heads_kernel, dim3(grid_for(m, 256 * 8, 8192)), dim3(256), 0, st, g->da_out, m,
                            d_rep);
+        hipLaunchKernelGGL(live_count_kernel, dim3(1), dim3(64), 0, st, g->off_out, n, (uint32_t)m, d_live);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(h_stats, d_max, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(h_stats + 2, d_rep, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(h_stats + 4, d_live, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             rc = KAIROS_ERR_DEVICE;
         } else {
@@ -544,6 +581,7 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
             uint64_t rep;
             std::memcpy(&rep, h_stats + 2, 8);
             g->repeat_heads = rep;
+            g->n_live = h_stats[4];
         }
     }
     if (rc == KAIROS_OK) {

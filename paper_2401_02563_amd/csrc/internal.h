@@ -125,6 +125,7 @@ struct kairos_graph {
     uint32_t *inv = nullptr;      // n
     std::vector<uint32_t> h_perm; // host copy of perm
     uint32_t max_out_degree = 0;
+    uint32_t n_live = 0;          // ids below have out-edges, ids from here none
     uint32_t max_t = 0;           // largest departure time (0 for an empty graph)
     uint32_t max_a = 0;           // largest arrival time
     uint64_t repeat_heads = 0;    // out-edges whose head repeats the previous out-edge's

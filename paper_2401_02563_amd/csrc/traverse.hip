@@ -91,6 +91,7 @@ struct TravArgs {
     uint32_t *hop;
     uint32_t strict;         // succession of queries started by this launch (1: "Strictly succeeds")
     uint32_t dedupe;         // one atomic per run of lanes into the same slot
+    uint32_t n_live;         // vertices from this id on have no out-edges: never enqueued
 };
 
 // Per-query parameter word fpar.y: code shift (bits 0-7), code width (bits
@@ -259,7 +260,9 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
     uint32_t vol = 0;
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
-        const bool push = G.ok[k] && st[k] != A.stamp_val;
+        // a head without out-edges has nothing to expand: its arrival is
+        // final for this round's purpose, so it stays out of the frontier
+        const bool push = G.ok[k] && st[k] != A.stamp_val && G.v[k] < A.n_live;
         bal[k] = __ballot(push);
         item[k] = (uint32_t)sv[k];
         if (push) {
@@ -1131,6 +1134,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
     A.off_in = g->off_in;
     A.a_in = g->a_in;
     A.st_in = g->st_in;
+    A.n_live = g->n_live;
     A.qp = s->qp;
     A.n = g->n;
     A.av = s->av;
@@ -2054,6 +2058,7 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.off_in = g->off_in;
     A.a_in = g->a_in;
     A.st_in = g->st_in;
+    A.n_live = g->n_live;
     A.qp = ms->qp;
     A.n = g->n;
     A.av = ms->av;

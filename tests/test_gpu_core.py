@@ -64,13 +64,17 @@ def print_case(*a):
 def test_index_matches_lexsort(which):
     g, G, _ = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
     print_case("index", which, g.n, g.m)
-    ix = {k: K.as_u32(v) for k, v in K.kairos_graph_index(G).items()}
-    # internal ids: decreasing in-degree, ties by caller id
+    view = K.kairos_graph_index(G)
+    ix = {k: K.as_u32(v) for k, v in view.items() if k != "n_live"}
+    # internal ids: vertices with out-edges first, then the others; within
+    # each part decreasing in-degree (clamped to 31 bits), ties by caller id
     perm = ix["perm"]
     assert np.array_equal(np.sort(perm), np.arange(g.n, dtype=np.uint32))
-    indeg = np.bincount(g.dst, minlength=g.n)
-    order = np.lexsort((np.arange(g.n), -indeg))
+    indeg = np.minimum(np.bincount(g.dst, minlength=g.n), (1 << 31) - 1)
+    sink = np.bincount(g.src, minlength=g.n) == 0
+    order = np.lexsort((np.arange(g.n), -indeg, sink))
     assert np.array_equal(perm[order], np.arange(g.n, dtype=np.uint32))
+    assert view["n_live"] == int((~sink).sum())
     want = O.temporal_csr(g.n, perm[g.src], perm[g.dst], g.t, g.lam)
     assert np.array_equal(ix["off_out"], want["off_out"].astype(np.uint32))
     assert np.array_equal(ix["off_in"], want["off_in"].astype(np.uint32))
