@@ -83,8 +83,12 @@ def main():
     one = torch.empty(g.n, dtype=torch.int32, device="cuda")
 
     if args.tune:
-        best = K.kairos_autotune(G, srcs[: min(q, 16)], ta[: min(q, 16)], tw[: min(q, 16)])
-        log(f"autotuned: {best}")
+        # the sample is the timed work's own shape: the whole batch, or one
+        # query for one-at-a-time calls (a one-query sample tunes that path)
+        k = q if args.mode == "batch" else 1
+        t0 = time.perf_counter()
+        best = K.kairos_autotune(G, srcs[:k], ta[:k], tw[:k])
+        log(f"autotuned on {k} queries in {time.perf_counter() - t0:.1f} s: {best}")
 
     def step():
         if args.mode == "batch":
@@ -158,8 +162,11 @@ def main():
         "traversed_edges_per_step": etrav_total,
         "rounds_per_step": prof["rounds"] / args.steps,
         "roofline": roofline, "cpu_baseline": cpu,
-        "tuning": {k: tuning[k] for k in ("batch_layout", "batch_persistent", "single_persistent", "rounds_per_sync",
-                                          "tail_limit", "split", "chunk", "arrival_filter", "run_dedupe")},
+        "tuning": {"source": "autotuner" if args.tune else "defaults",
+                   **{k: tuning[k] for k in ("batch_layout", "batch_persistent", "single_persistent",
+                                             "rounds_per_sync", "tail_limit", "split", "chunk", "pull_alpha",
+                                             "pull_beta", "dense_frontier", "arrival_filter", "run_dedupe",
+                                             "sweep_group")}},
         **extra,
     }
     print(json.dumps(line), flush=True)
