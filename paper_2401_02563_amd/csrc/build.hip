@@ -240,6 +240,9 @@ __global__ __launch_bounds__(SB) void scatter_kernel(const uint4 *__restrict__ i
 
 // CSR arrays from records sorted by (key, ...).  which = 0: key = tail,
 // writes t_out and {head, a}; which = 1: key = head, writes a_in and {tail, t}.
+constexpr uint64_t kShortGap = 64;
+constexpr uint32_t OFF_UNSET = 0xFFFFFFFFu;
+
 __global__ void finalize_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t n, int which,
                                 uint32_t *__restrict__ off, uint32_t *__restrict__ tk,
                                 uint2 *__restrict__ pair)
@@ -255,10 +258,36 @@ __global__ void finalize_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_
             tk[i] = r.w;
             pair[i] = make_uint2(r.x, r.z);
         }
-        // offsets of the keys in (previous key, key] start here; the keys
-        // after the last one are filled by tail_offsets_kernel
+        // offsets of the keys in (previous key, key] start here.  A short
+        // run of keys without records is filled here; a long one (vertices
+        // without edges in this direction, which the relabelling can put
+        // in one block) is left to gap_offsets_kernel, the keys after the
+        // last one to tail_offsets_kernel
         const uint64_t first = i == 0 ? 0 : (uint64_t)(which == 0 ? e[i - 1].x : e[i - 1].y) + 1;
-        for (uint64_t v = first; v <= key; ++v) off[v] = (uint32_t)i;
+        if (key - first < kShortGap)
+            for (uint64_t v = first; v <= key; ++v) off[v] = (uint32_t)i;
+        else if (first <= key)
+            off[key] = (uint32_t)i;
+    }
+}
+
+// Offsets still unset (OFF_UNSET) after finalize_kernel: the first record
+// whose key is at least v, by binary search over the sorted records.
+__global__ void gap_offsets_kernel(const uint4 *__restrict__ e, uint64_t m, uint32_t n, int which,
+                                   uint32_t *__restrict__ off)
+{
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        if (off[v] != OFF_UNSET) continue;
+        uint64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const uint64_t mid = lo + ((hi - lo) >> 1);
+            if ((which == 0 ? e[mid].x : e[mid].y) < v)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        off[v] = (uint32_t)lo;
     }
 }
 
@@ -548,13 +577,21 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
         }
         if ((rc = run_passes(g, a, b, m, out_p, hist, st)) != KAIROS_OK) break;
         const int fg = grid_for(m, 256, 16384);
+        const int vg = grid_for((uint64_t)n + 1, 256, 4096);
+        if (hipMemsetAsync(g->off_out, 0xFF, sizeof(uint32_t) * ((size_t)n + 1), st) != hipSuccess ||
+            hipMemsetAsync(g->off_in, 0xFF, sizeof(uint32_t) * ((size_t)n + 1), st) != hipSuccess) {
+            rc = KAIROS_ERR_DEVICE;
+            break;
+        }
         hipLaunchKernelGGL(finalize_kernel, dim3(fg), dim3(256), 0, st, a, m, n, 0, g->off_out,
                            g->t_out, g->da_out);
-        hipLaunchKernelGGL(tail_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256), 0, st, a, m, n, 0, g->off_out);
+        hipLaunchKernelGGL(tail_offsets_kernel, dim3(vg), dim3(256), 0, st, a, m, n, 0, g->off_out);
+        hipLaunchKernelGGL(gap_offsets_kernel, dim3(vg), dim3(256), 0, st, a, m, n, 0, g->off_out);
         if ((rc = run_passes(g, a, b, m, in_p, hist, st)) != KAIROS_OK) break;
         hipLaunchKernelGGL(finalize_kernel, dim3(fg), dim3(256), 0, st, a, m, n, 1, g->off_in,
                            g->a_in, g->st_in);
-        hipLaunchKernelGGL(tail_offsets_kernel, dim3(grid_for((uint64_t)n + 1, 256, 4096)), dim3(256), 0, st, a, m, n, 1, g->off_in);
+        hipLaunchKernelGGL(tail_offsets_kernel, dim3(vg), dim3(256), 0, st, a, m, n, 1, g->off_in);
+        hipLaunchKernelGGL(gap_offsets_kernel, dim3(vg), dim3(256), 0, st, a, m, n, 1, g->off_in);
     } while (0);
     if (rc == KAIROS_OK) {
         // the 64 bytes past the histograms: max out-degree at byte 32, the

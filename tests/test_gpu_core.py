@@ -50,6 +50,21 @@ def rmat_wide():
     return built("rmat_wide", lambda: make_graph("rmat22-256m", scale_shift=8))
 
 
+def gappy():
+    """Long blocks of vertices without in-edges and without out-edges in the
+    middle of the internal id order: 3,000 vertices reach only the first 100,
+    1,000 more are isolated, 2,000 are targets only."""
+    def make():
+        rng = np.random.default_rng(17)
+        m = 40_000
+        src = rng.integers(0, 3_000, m).astype(np.uint32)
+        dst = np.where(rng.random(m) < 0.5, rng.integers(0, 100, m), rng.integers(4_000, 6_000, m)).astype(np.uint32)
+        t = rng.integers(0, 50_000, m).astype(np.uint32)
+        lam = rng.integers(1, 20, m).astype(np.uint32)
+        return Graph(6_000, src, dst, t, lam, dict(kind="gappy"))
+    return built("gappy", make)
+
+
 def ea_gpu(G, s, a, w):
     out = torch.empty(G.n, dtype=torch.int32, device="cuda")
     K.kairos_earliest_arrival(G, s, a, w, out)
@@ -60,9 +75,10 @@ def print_case(*a):
     print("case:", *a, flush=True)
 
 
-@pytest.mark.parametrize("which", ["uniform", "rmat16", "bursty16", "rmat_wide"])
+@pytest.mark.parametrize("which", ["uniform", "rmat16", "bursty16", "rmat_wide", "gappy"])
 def test_index_matches_lexsort(which):
-    g, G, _ = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
+    g, G, _ = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide,
+               "gappy": gappy}[which]()
     print_case("index", which, g.n, g.m)
     view = K.kairos_graph_index(G)
     ix = {k: K.as_u32(v) for k, v in view.items() if k != "n_live"}
@@ -448,5 +464,37 @@ def test_dense_frontier_walk(dense):
         pea, pld, pf = O.profile(se, srcs[1], ta[1], tw[1])
         K.kairos_latest_departure(G, int(srcs[1]), int(ta[1]), int(tw[1]), out)
         assert np.array_equal(K.as_u32(out), pld)
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("layout,persistent", [(1, 0), (2, 0), (2, 1), (0, 0)])
+def test_gappy_single_and_batch(layout, persistent):
+    """Vertices without out-edges are never enqueued and vertices without
+    in-edges sit in one block of ids: every query kind and batch layout still
+    matches the oracle, including sources without out-edges."""
+    g, G, se = gappy()
+    old = K.kairos_get_tuning(G)
+    K.kairos_set_tuning(G, batch_layout=layout, batch_persistent=persistent)
+    try:
+        rng = np.random.default_rng(5)
+        srcs = np.concatenate([rng.integers(0, 3_000, 12), [3_500, 4_100, 5_999, 50]]).astype(np.uint32)
+        ta = rng.integers(0, 20_000, len(srcs)).astype(np.uint32)
+        tw = (ta + rng.integers(1_000, 60_000, len(srcs))).astype(np.uint32)
+        print_case("gappy", layout, persistent)
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        rows = K.as_u32(out).reshape(len(srcs), g.n)
+        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for q in range(len(srcs)):
+            s, a, w = int(srcs[q]), int(ta[q]), int(tw[q])
+            pea, pld, pf = O.profile(se, s, a, w)
+            assert np.array_equal(rows[q], pea), q
+            assert np.array_equal(ea_gpu(G, s, a, w), pea), q
+            if q % 4 == 0:
+                K.kairos_latest_departure(G, s, a, w, one)
+                assert np.array_equal(K.as_u32(one), pld), q
+                K.kairos_fastest(G, s, a, w, one)
+                assert np.array_equal(K.as_u32(one), pf), q
     finally:
         K.kairos_set_tuning(G, **old)
