@@ -266,7 +266,7 @@ std::pair<uint32_t, uint32_t> free_run(const kairos_server *s, uint32_t want)
     return {best_start, best_len};
 }
 
-int iterate(kairos_server *s, uint32_t &front)
+int iterate(kairos_server *s)
 {
     kairos_graph *g = s->g;
     hipStream_t st = s->ms.stream;
@@ -385,7 +385,6 @@ int iterate(kairos_server *s, uint32_t &front)
         KAIROS_HIP(hipMemcpyAsync(s->h_pin + pl.step_cnt, s->ms.step_cnt, (size_t)s->cap * 4, hipMemcpyDeviceToHost,
                                   st));
     KAIROS_HIP(hipStreamSynchronize(st));
-    front = s->h_pin[CNT_FRONT + s->ms.round % 3u];
     const uint32_t *flags = s->h_pin + pl.flags + CNT_WORDS;
     const uint32_t *step_cnt = s->h_pin + pl.step_cnt;
     // finishing: a slot with no frontier work (and no step left); a group
@@ -440,13 +439,11 @@ int iterate(kairos_server *s, uint32_t &front)
 
 void scheduler(kairos_server *s)
 {
-    uint32_t front = 0;
     for (;;) {
-        int rc = iterate(s, front);
+        int rc = iterate(s);
         if (rc == 1) break;
         if (rc != 0) {
             fail_all(s);
-            front = 0;
             std::unique_lock<std::mutex> lk(s->mu);
             while (!s->stop) {
                 while (!s->waiting.empty()) {
