@@ -254,6 +254,9 @@ def traffic_for(kname, workload, mode):
 def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
     res = {}
     q = len(srcs)
+    # one untimed call of each form first: it allocates that form's state
+    K.kairos_earliest_arrival(G, int(srcs[0]), int(ta[0]), int(tw[0]), one)
+    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(q):
@@ -261,11 +264,13 @@ def time_extras(K, torch, G, g, srcs, ta, tw, out, one, etrav):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     res["single_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt, "ms_per_query": dt / q * 1e3}
+    reps = 3
     t = time.perf_counter()
-    K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+    for _ in range(reps):
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    res["batch_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt}
+    dt = (time.perf_counter() - t) / reps
+    res["batch_ea"] = {"queries_per_s": q / dt, "edges_per_s": sum(etrav) / dt, "ms_per_batch": dt * 1e3}
     k = min(4, q)
     for kind, fn in (("latest_departure", K.kairos_latest_departure), ("fastest", K.kairos_fastest)):
         fn(G, int(srcs[0]), int(ta[0]), int(tw[0]), one)  # first call allocates the sweep's scratch
