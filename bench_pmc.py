@@ -3,7 +3,8 @@
     python bench_pmc.py run [bench args...]             # on the GPU host: three runs
     python bench_pmc.py summarize OUTDIR WORKLOAD MODE  # writes profiles/*.txt|json
 
-`run` executes bench.py three times under rocprofv3: once with a kernel
+`run` writes under $KAIROS_PROFILE_DIR (default profile_runs/) and
+executes bench.py three times under rocprofv3: once with a kernel
 trace and statistics, once collecting FETCH_SIZE and once WRITE_SIZE (each
 counter in its own pass).  bench.py also copies a 256 MiB buffer with a
 plain copy kernel in that process, which calibrates the counters: the copy
@@ -32,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["paper_2401_02563_amd/csrc/traverse.hip", "paper_2401_02563_amd/csrc/batch.hip",
                   "paper_2401_02563_amd/csrc/build.hip", "paper_2401_02563_amd/csrc/stage.h"]
 COPY_BYTES = 256 << 20
+# raw rocprofv3 output goes under this directory of the repository
+OUT_ROOT = os.environ.get("KAIROS_PROFILE_DIR", "profile_runs")
 
 
 def kernel_source_hash() -> str:
@@ -52,7 +55,7 @@ def short_name(n: str) -> str:
 def run(argv):
     mode = argv[argv.index("--mode") + 1] if "--mode" in argv else "batch"
     workload = argv[argv.index("--workload") + 1] if "--workload" in argv else "rmat20-32m"
-    out = os.path.join(ROOT, "gpurun_out", f"pmc_{workload}_{mode}")
+    out = os.path.join(ROOT, OUT_ROOT, f"pmc_{workload}_{mode}")
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
     with open(os.path.join(out, "args.json"), "w") as f:
@@ -133,13 +136,14 @@ def summarize(outdir, workload="rmat20-32m", mode="batch"):
     b = " ".join(["--no-cpu", *argv])
     lines = [f"# rocprofv3 summary: bench.py workload {workload}, mode {mode}",
              "",
-             "commands (from the repository root, on the GPU host):",
+             "commands (from the repository root, on the GPU host; raw output under",
+             f"$KAIROS_PROFILE_DIR, here {os.path.dirname(os.path.relpath(os.path.abspath(outdir), ROOT))}):",
              f"  python bench_pmc.py run {' '.join(argv)}",
              "  which makes three rocprofv3 passes, each its own process:",
              f"    rocprofv3 --kernel-trace --stats -- python bench.py {b}",
              f"    rocprofv3 --pmc FETCH_SIZE       -- python bench.py {b}",
              f"    rocprofv3 --pmc WRITE_SIZE       -- python bench.py {b}",
-             f"  python bench_pmc.py summarize gpurun_out/pmc_{workload}_{mode} {workload} {mode}",
+             f"  python bench_pmc.py summarize {os.path.relpath(os.path.abspath(outdir), ROOT)} {workload} {mode}",
              "",
              f"kernel sources sha256[:16]: {doc['kernel_sources_sha']}",
              f"calibration (counter / true bytes of a {COPY_BYTES >> 20} MiB copy): "
