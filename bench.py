@@ -223,8 +223,15 @@ def roofline_from_profile(prof, mode, pairs, workload, tuning):
     per_launch = r["bytes"] / r["launches"]
     achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     kname = names[kern]
+    traffic = traffic_for(kname, workload, mode)
+    # counted bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch) over this
+    # run's launch duration: what the kernel moves beyond L2, beside the
+    # algorithmic figure above
+    counted = traffic / (avg_ms * 1e-3) / 1e9 if traffic and avg_ms > 0 else None
     return {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(kname, workload, mode),
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_GBps": round(counted, 1) if counted else None,
+            "traffic_frac": round(counted / HBM_PEAK_GBS, 4) if counted else None,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": r["launches"],
             "alg_bytes_per_launch": int(per_launch),
             "per_kernel": {names[c]: {"ms": round(v["ms"], 3), "launches": v["launches"],
