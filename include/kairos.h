@@ -237,8 +237,8 @@ typedef struct kairos_tuning {
                                 time range cut into 2^bits equal parts); an
                                 edge arriving at or after its head's bound is
                                 dropped before the arrival word is read.
-                                0: off.  Each query keeps the width it started
-                                with                                            */
+                                0: off (the default).  Each query keeps the
+                                width it started with                           */
     uint32_t single_persistent; /* 1: single queries run their rounds with more
                                 than tail_limit frontier entries in one
                                 cooperative launch (grid barriers, no host

@@ -92,6 +92,7 @@ struct TravArgs {
     uint32_t strict;         // succession of queries started by this launch (1: "Strictly succeeds")
     uint32_t dedupe;         // one atomic per run of lanes into the same slot
     uint32_t n_live;         // vertices from this id on have no out-edges: never enqueued
+    uint32_t max_deg;        // largest out-degree
 };
 
 // Per-query parameter word fpar.y: code shift (bits 0-7), code width (bits
@@ -653,9 +654,10 @@ __global__ __launch_bounds__(TT) void tail_kernel(TravArgs A, uint32_t which0, u
         }
         const uint32_t F = s_F;
         if (F == 0 || F > limit || rounds >= max_rounds) break;
-        {
+        if ((uint64_t)F * A.max_deg > vol_limit) {
             // out-degree volume of the frontier bounds this round's edge work;
-            // beyond vol_limit the multi-block kernels are faster
+            // beyond vol_limit the multi-block kernels are faster (no need to
+            // count when F entries of the largest out-degree stay within it)
             uint32_t vol = 0;
             const uint32_t *cq = which ? q1 : q0;
             for (uint32_t i = tid; i < F; i += TT) {
@@ -1135,6 +1137,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
     A.a_in = g->a_in;
     A.st_in = g->st_in;
     A.n_live = g->n_live;
+    A.max_deg = g->max_out_degree;
     A.qp = s->qp;
     A.n = g->n;
     A.av = s->av;
@@ -1868,12 +1871,12 @@ kairos_tuning default_tuning(const kairos_graph *g)
     t.batch_layout = g && g->m >= (1u << 22) ? 2u : 1u;
     t.tail_limit = 4096;
     t.dense_frontier = 0;
-    // arrival codes add a dependent read in front of the arrival read; they
-    // only break even while the arrival words themselves nearly fit in L2
-    // (2^20 vertices: 0.866 against 0.870 ms per query); at 2^22 and 2^24
-    // vertices every width measured slower than none (2, 4, 8 bits:
-    // 5.88, 5.78, 5.75 ms against 5.13 ms per query at 2^24)
-    t.arrival_filter = g && g->n <= (1u << 21) ? 8u : 0u;
+    // arrival codes add a dependent read in front of the arrival read: at
+    // 2^22 and 2^24 vertices every width measured slower than none (2, 4, 8
+    // bits: 5.88, 5.78, 5.75 ms against 5.13 ms per query at 2^24); at 2^20
+    // vertices 8-bit codes tie on earliest arrival and lose 7% on latest
+    // departure (2.75 against 2.56 ms), at 10^4 vertices 5% on both
+    t.arrival_filter = 0;
     // runs of equal heads (bursty pairs): 2.1x on single queries and 2.5x
     // on batches of the 10^9-edge bursty graph; on R-MAT graphs, which have
     // almost none, the extra ballot costs up to 1.4%
@@ -2059,6 +2062,7 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.a_in = g->a_in;
     A.st_in = g->st_in;
     A.n_live = g->n_live;
+    A.max_deg = g->max_out_degree;
     A.qp = ms->qp;
     A.n = g->n;
     A.av = ms->av;
