@@ -59,7 +59,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (queries shard across GPUs by replicating the index, see the design notes)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_2401_02563_amd as K
