@@ -20,8 +20,8 @@ Contents (each function names the passage of the paper it follows):
 * ``paths.min_hops``         -- temporal BFS: fewest edges within the window.
 * ``paths.brute_force_walks``-- enumeration pinning the two above.
 
-Reading of the paper used throughout (its text leaves these open or
-garbled; each is listed with its reason in the design notes):
+Reading of the paper used throughout, where its text leaves a point open
+or garbled:
   * a = t + lambda with lambda >= 1;
   * consecutive edges follow the non-strict "Succeeds" predicate of §2.2
     (next departure >= previous arrival), as the Update test of Alg. 2 does;
