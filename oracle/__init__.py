@@ -12,9 +12,16 @@ Contents (each function names the passage of the paper it follows):
 * ``earliest_arrival``       -- one-pass EA scan (C).
 * ``profile``                -- EA / LD / F by Pareto profiles (C).
 * ``traversed_edges``        -- temporal edges traversed by a query (C).
-* ``ea_certificate``         -- O(m) check that an array is exactly EA.
+* ``shortest_duration``      -- least total duration by Pareto profiles of
+                                (arrival, duration) (C).
+* ``ea_certificate``         -- O(m) check that an array is exactly EA
+                                (numpy; ``ea_certificate_scan``: the same
+                                three conditions as one C loop, for 10^9
+                                edges).
 * ``brute_force``            -- enumeration of all time-respecting walks
-                                (pure Python, tiny inputs only).
+                                (pure Python, tiny inputs only);
+                                ``walk_facts`` adds, per walk, the edges it
+                                uses and its total duration.
 * ``temporal_csr``           -- expected out/in temporal CSR (numpy lexsort).
 * ``paths.ea_predecessors``  -- last edge of an earliest-arrival path (numpy).
 * ``paths.min_hops``         -- temporal BFS: fewest edges within the window.
@@ -65,6 +72,10 @@ def _lib():
         lib.oracle_traversed_edges.argtypes = [u64, p, p, p, u32, u32, p]
         lib.oracle_profile.restype = ctypes.c_int
         lib.oracle_profile.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p, p, p]
+        lib.oracle_shortest_duration.restype = ctypes.c_int
+        lib.oracle_shortest_duration.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p]
+        lib.oracle_ea_certificate.restype = ctypes.c_int
+        lib.oracle_ea_certificate.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p, p]
         _LIB = lib
     return _LIB
 
@@ -88,15 +99,83 @@ class SortedEdges:
         return int(self.src.shape[0])
 
 
-def sort_by_departure(n, src, dst, t, lam) -> SortedEdges:
+def _threads() -> int:
+    return max(1, os.cpu_count() or 1)
+
+
+def _chunks(m: int, parts: int):
+    step = -(-m // parts) if m else 1
+    return [(lo, min(m, lo + step)) for lo in range(0, m, step)]
+
+
+def departure_order(t, threads: int | None = None) -> np.ndarray:
+    """The stable order of ``t`` (np.argsort(t, kind="stable")), as int64.
+
+    A plain library sort of the packed keys (t << 32 | position), which are
+    distinct, so sorting them is sorting by t with ties by position.  For
+    large inputs the keys are sorted in P slices on P threads, split at
+    common key bounds taken from the sorted slices, and each of the P key
+    ranges sorted again on its own thread: range j holds exactly the keys
+    between bound j-1 and bound j, so the ranges placed one after another
+    are the whole sorted sequence."""
+    t = np.asarray(t, np.uint32)
+    m = int(t.size)
+    P = threads or _threads()
+    if m < (1 << 22) or P == 1:
+        return np.argsort(t, kind="stable").astype(np.int64)
+    from concurrent.futures import ThreadPoolExecutor
+    keys = np.empty(m, np.uint64)
+    parts = _chunks(m, P)
+
+    def pack(c):
+        lo, hi = c
+        np.left_shift(t[lo:hi].astype(np.uint64), np.uint64(32), out=keys[lo:hi])
+        keys[lo:hi] |= np.arange(lo, hi, dtype=np.uint64)
+        keys[lo:hi].sort()
+
+    with ThreadPoolExecutor(P) as ex:
+        list(ex.map(pack, parts))
+        # bounds: every (m/P)-th key of the union, estimated from the slices
+        sample = np.sort(np.concatenate([keys[lo:hi][:: max(1, (hi - lo) // 256)] for lo, hi in parts]))
+        bounds = sample[np.linspace(0, sample.size, P + 1).astype(np.int64)[1:-1]]
+        cuts = [np.searchsorted(keys[lo:hi], bounds) + lo for lo, hi in parts]
+        # range j: keys >= bounds[j-1] and < bounds[j] from every slice
+        sizes = [sum(int((np.r_[c, hi][j]) - (np.r_[lo, c][j])) for c, (lo, hi) in zip(cuts, parts))
+                 for j in range(P)]
+        starts = np.concatenate([[0], np.cumsum(sizes)])
+        order = np.empty(m, np.int64)
+
+        def merge(j):
+            pieces = [keys[(np.r_[lo, c][j]):(np.r_[c, hi][j])] for c, (lo, hi) in zip(cuts, parts)]
+            r = np.concatenate(pieces) if pieces else np.empty(0, np.uint64)
+            r.sort()
+            order[starts[j]:starts[j + 1]] = (r & np.uint64(0xFFFFFFFF)).astype(np.int64)
+
+        list(ex.map(merge, range(P)))
+    return order
+
+
+def _gather(x, order, threads):
+    out = np.empty(order.size, x.dtype)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: np.take(x, order[c[0]:c[1]], out=out[c[0]:c[1]]), _chunks(order.size, threads)))
+    return out
+
+
+def sort_by_departure(n, src, dst, t, lam, threads: int | None = None) -> SortedEdges:
     """Sort edges by departure time (§2.1 data model; a = t + lambda)."""
     t = np.asarray(t, np.uint32)
     a64 = t.astype(np.uint64) + np.asarray(lam, np.uint64)
     if a64.size and int(a64.max()) > 0xFFFFFFFE:
         raise ValueError("t + lambda exceeds the largest finite time")
-    order = np.argsort(t, kind="stable")
-    return SortedEdges(n, np.asarray(src, np.uint32)[order], np.asarray(dst, np.uint32)[order],
-                       t[order], a64[order].astype(np.uint32))
+    a = a64.astype(np.uint32)
+    del a64
+    P = threads or _threads()
+    order = departure_order(t, P)
+    return SortedEdges(n, _gather(np.asarray(src, np.uint32), order, P),
+                       _gather(np.asarray(dst, np.uint32), order, P), _gather(t, order, P),
+                       _gather(a, order, P))
 
 
 def earliest_arrival(se: SortedEdges, source: int, t_alpha: int, t_omega: int,
@@ -127,6 +206,30 @@ def profile(se: SortedEdges, source: int, t_alpha: int, t_omega: int):
     if rc != 0:
         raise MemoryError("oracle_profile")
     return ea, ld, fa
+
+
+def shortest_duration(se: SortedEdges, source: int, t_alpha: int, t_omega: int) -> np.ndarray:
+    """SD[v]: least total duration (sum of lambda) of a time-respecting path
+    from ``source`` to v within [t_alpha, t_omega] (Table 4's shortest
+    duration), by per-vertex Pareto profiles of (arrival, duration)."""
+    sd = np.empty(se.n, np.uint32)
+    rc = _lib().oracle_shortest_duration(se.m, _ptr(se.src), _ptr(se.dst), _ptr(se.t), _ptr(se.a), se.n,
+                                         int(source), int(t_alpha), int(t_omega), _ptr(sd))
+    if rc != 0:
+        raise MemoryError("oracle_shortest_duration")
+    return sd
+
+
+def ea_certificate_scan(n, src, dst, t, a, source, t_alpha, t_omega, A) -> bool:
+    """``ea_certificate``'s three conditions checked by one C loop over the
+    edges (any order; ``a`` = t + lambda as uint32)."""
+    arrs = [np.ascontiguousarray(x, np.uint32) for x in (src, dst, t, a)]
+    A = np.ascontiguousarray(A, np.uint32)
+    if A.shape != (n,):
+        return False
+    scratch = np.empty(n, np.uint8)
+    return bool(_lib().oracle_ea_certificate(arrs[0].size, *[_ptr(x) for x in arrs], int(n), int(source),
+                                             int(t_alpha), int(t_omega), _ptr(A), _ptr(scratch)))
 
 
 def ea_certificate(n, src, dst, t, lam, source, t_alpha, t_omega, A) -> bool:
@@ -195,6 +298,34 @@ def brute_force(n, edges, source, t_alpha, t_omega):
     ld[source] = t_omega
     fa[source] = 0
     return ea, ld, fa
+
+
+def walk_facts(n, edges, source, t_alpha, t_omega):
+    """Enumerate every time-respecting walk from ``source`` (tiny inputs).
+
+    ``edges`` is a list of (u, v, t, lam).  Returns (used, sd): the set of
+    indices of the edges that lie on at least one walk, and per vertex the
+    least total duration (sum of lambda) of a walk reaching it (0 for the
+    source, INF if none)."""
+    sd = [INF] * n
+    used = set()
+    out = [[] for _ in range(n)]
+    for i, (u, v, t, lam) in enumerate(edges):
+        if t >= t_alpha and t + lam <= t_omega:
+            out[u].append((i, v, t, t + lam, lam))
+
+    def walk(u, now, total):
+        for (i, v, t, a, lam) in out[u]:
+            if t < now:
+                continue
+            used.add(i)
+            if total + lam < sd[v]:
+                sd[v] = total + lam
+            walk(v, a, total + lam)
+
+    walk(source, t_alpha, 0)
+    sd[source] = 0
+    return used, sd
 
 
 def temporal_csr(n, src, dst, t, lam):

@@ -18,8 +18,10 @@
  *   F[v]  = min (arrival at v - departure from src)        (F[src]  = 0)
  *   unreachable vertices get 0xFFFFFFFF in all three.
  *
- * All functions take the edge list already sorted by departure time t
- * (ascending; ties in any order) as four parallel uint32 arrays.
+ * The scans (earliest arrival, profiles, shortest duration) take the edge
+ * list already sorted by departure time t (ascending; ties in any order) as
+ * four parallel uint32 arrays; the traversed-edge count and the
+ * earliest-arrival certificate take the edges in any order.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -219,6 +221,163 @@ int oracle_profile(uint64_t m, const uint32_t *src, const uint32_t *dst, const u
             fa[v] = f_v;
         free(P[v].arr);
         free(P[v].dep);
+    }
+    free(P);
+    return rc;
+}
+
+/*
+ * Earliest-arrival certificate: returns 1 iff A is exactly the
+ * earliest-arrival array of the query, 0 otherwise.  Edges in any order.
+ *   (i)   A[source] == t_alpha, and every finite A[v] lies in the window;
+ *   (ii)  every finite A[v], v != source, equals the arrival of a usable
+ *         edge (u, v, t, a) whose tail has arrived by its departure,
+ *         A[u] <= t (a witness);
+ *   (iii) no usable edge with A[u] <= t arrives before A[v].
+ * By (ii) A strictly decreases back along witnesses to the source (lambda
+ * >= 1), so each finite A[v] is the arrival of a real path: A >= EA.  By
+ * (iii), induction along any time-respecting path gives A <= EA.  Usable:
+ * t >= t_alpha and a <= t_omega.  `witnessed` is caller scratch of n bytes.
+ */
+int oracle_ea_certificate(uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *t,
+                          const uint32_t *a, uint32_t n, uint32_t source, uint32_t t_alpha,
+                          uint32_t t_omega, const uint32_t *A, uint8_t *witnessed)
+{
+    if (source >= n || A[source] != t_alpha)
+        return 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        witnessed[v] = 0;
+        if (A[v] != ORACLE_INF && (A[v] < t_alpha || A[v] > t_omega))
+            return 0;
+    }
+    for (uint64_t e = 0; e < m; ++e) {
+        uint32_t u = src[e], v = dst[e];
+        if (t[e] < t_alpha || a[e] > t_omega || A[u] == ORACLE_INF || A[u] > t[e])
+            continue;
+        if (a[e] < A[v])
+            return 0; /* (iii) */
+        if (a[e] == A[v])
+            witnessed[v] = 1;
+    }
+    for (uint32_t v = 0; v < n; ++v)
+        if (v != source && A[v] != ORACLE_INF && !witnessed[v])
+            return 0; /* (ii) */
+    return 1;
+}
+
+/* ---- Shortest duration ------------------------------------------------------
+ * SD[v] = least total duration (sum of lambda over its edges) of a
+ * time-respecting path from the source to v within the window; SD[src] = 0
+ * (the "S. Duration" row of Table 4).  Waiting at a vertex costs nothing, so
+ * a later arrival with a smaller total can still matter: each vertex keeps
+ * the non-dominated pairs (arrival, duration) of the paths found so far.  A
+ * pair (a1, d1) dominates (a2, d2) when a1 <= a2 and d1 <= d2.  Kept sorted
+ * by arrival ascending, which makes duration strictly descending.  Scanning
+ * edges in departure order, an edge (u, v, t, a) extends the pair of u with
+ * the least duration among those that have arrived by t -- the last pair
+ * with arrival <= t -- or starts at the source (duration 0 at any time from
+ * t_alpha on).  Pairs of u that have arrived by t all come from edges that
+ * departed before t (lambda >= 1), which the scan has already examined.
+ */
+typedef struct {
+    uint32_t *arr;
+    uint32_t *dur;
+    uint32_t len, cap;
+} dprofile_t;
+
+/* index of the last pair with arr <= t, or -1 */
+static int64_t dprofile_last_by(const dprofile_t *p, uint32_t t)
+{
+    uint32_t lo = 0, hi = p->len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) / 2;
+        if (p->arr[mid] <= t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (int64_t)lo - 1;
+}
+
+static int dprofile_insert(dprofile_t *p, uint32_t a, uint32_t d)
+{
+    int64_t k = dprofile_last_by(p, a); /* pairs [0, k] have arr <= a */
+    if (k >= 0 && p->dur[k] <= d)
+        return 0; /* dominated by a pair arriving no later and no longer */
+    /* the new pair dominates the pairs with arr >= a and dur >= d: a pair
+     * with arr == a at k (its dur is > d here), and the pairs after k whose
+     * durations (descending) are still >= d */
+    uint32_t first = (uint32_t)(k + 1);
+    if (k >= 0 && p->arr[k] == a)
+        first = (uint32_t)k;
+    uint32_t last = (uint32_t)(k + 1);
+    while (last < p->len && p->dur[last] >= d)
+        ++last;
+    uint32_t removed = last - first;
+    if (removed == 0) {
+        if (p->len == p->cap) {
+            uint32_t nc = p->cap ? 2 * p->cap : 4;
+            uint32_t *na = realloc(p->arr, (size_t)nc * sizeof(uint32_t));
+            if (!na)
+                return -1;
+            p->arr = na;
+            uint32_t *nd = realloc(p->dur, (size_t)nc * sizeof(uint32_t));
+            if (!nd)
+                return -1;
+            p->dur = nd;
+            p->cap = nc;
+        }
+        memmove(p->arr + first + 1, p->arr + first, (size_t)(p->len - first) * sizeof(uint32_t));
+        memmove(p->dur + first + 1, p->dur + first, (size_t)(p->len - first) * sizeof(uint32_t));
+        p->len += 1;
+    } else if (removed > 1) {
+        memmove(p->arr + first + 1, p->arr + last, (size_t)(p->len - last) * sizeof(uint32_t));
+        memmove(p->dur + first + 1, p->dur + last, (size_t)(p->len - last) * sizeof(uint32_t));
+        p->len -= removed - 1;
+    }
+    p->arr[first] = a;
+    p->dur[first] = d;
+    return 1;
+}
+
+/* Returns 0 on success, -1 on allocation failure.  sd: n entries. */
+int oracle_shortest_duration(uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *t,
+                             const uint32_t *a, uint32_t n, uint32_t source, uint32_t t_alpha,
+                             uint32_t t_omega, uint32_t *sd)
+{
+    dprofile_t *P = calloc(n, sizeof(dprofile_t));
+    if (!P)
+        return -1;
+    int rc = 0;
+    uint64_t e = first_at_or_after(t, m, t_alpha);
+    for (; e < m && t[e] < t_omega; ++e) {
+        uint32_t u = src[e], v = dst[e];
+        if (a[e] > t_omega || v == source)
+            continue;
+        uint32_t lam = a[e] - t[e];
+        uint32_t d;
+        if (u == source) {
+            d = lam;
+        } else {
+            int64_t k = dprofile_last_by(&P[u], t[e]);
+            if (k < 0)
+                continue;
+            d = P[u].dur[k] + lam;
+        }
+        if (dprofile_insert(&P[v], a[e], d) < 0) {
+            rc = -1;
+            break;
+        }
+    }
+    for (uint32_t v = 0; v < n; ++v) {
+        uint32_t s_v = ORACLE_INF;
+        if (v == source)
+            s_v = 0;
+        else if (P[v].len)
+            s_v = P[v].dur[P[v].len - 1]; /* durations descend with arrival */
+        sd[v] = s_v;
+        free(P[v].arr);
+        free(P[v].dur);
     }
     free(P);
     return rc;
