@@ -3,15 +3,19 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--mode batch|single] [--no-cpu] [--serve]
 
-A step answers every query of the workload once: the earliest-arrival
-queries of the R-MAT scale-20 graph (2^25 edges, 64 sources, t_alpha in the
-first half of the span, t_omega = max) by default.  The graph and the
-queries are synthetic and resident in HBM before timing starts.
+A step answers every query of the workload once.  By default that is the
+largest workload: the bursty communication-style multigraph (R-MAT scale-22
+pair structure, about 1.007e9 edges, bursty Pareto departure times, lambda
+in [1, 100]) with its 32 earliest-arrival queries (t_alpha in the first half
+of the span, t_omega = max), one query per call.  The graph and the queries
+are synthetic and resident in HBM before timing starts.
 
 value = sum over queries of the temporal edges each traverses (edges whose
 tail is reached, departing no earlier than the tail's earliest arrival and
-t_alpha, arriving by t_omega; counted on the GPU from the result) times
-steps, divided by the wall time of the timed steps.
+t_alpha, arriving by t_omega) times steps, divided by the wall time of the
+timed steps.  The count per query comes from the CPU oracle's own result
+(untimed) and must equal the GPU's count of the same query; with --no-cpu
+(profiling runs) the GPU's count is used.
 
 Printed as one JSON line.  The timed steps run without per-launch events;
 the same steps then run again with every launch bracketed by HIP events on
@@ -46,10 +50,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20-32m")
-    ap.add_argument("--mode", choices=["batch", "single"], default="batch")
+    ap.add_argument("--workload", default="bursty22-1b")
+    ap.add_argument("--mode", choices=["batch", "single"], default=None,
+                    help="default: the workload's own form (one query per call, or the batch)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true", help="also run the serving sweep")
     ap.add_argument("--extras", action="store_true", help="also time LD/F and one-at-a-time EA")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
@@ -67,6 +72,8 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = CONFIGS[args.workload]
+    if args.mode is None:
+        args.mode = cfg.get("bench_mode", "batch")
     t0 = time.time()
     g = make_graph(args.workload)
     srcs, ta, tw = make_queries(args.workload, g)
@@ -97,12 +104,13 @@ def main():
             for i in range(q):
                 K.kairos_earliest_arrival(G, int(srcs[i]), int(ta[i]), int(tw[i]), out[i * g.n:(i + 1) * g.n])
 
-    # traversed edges per query, from the GPU result (not timed)
+    # traversed edges per query, from the GPU result (not timed); the
+    # oracle's own count replaces it below when the CPU leg runs
     step()
     torch.cuda.synchronize()
     etrav = [K.kairos_traversed_edges(G, int(ta[i]), int(tw[i]), out[i * g.n:(i + 1) * g.n]) for i in range(q)]
     etrav_total = int(sum(etrav))
-    log(f"traversed edges per step: {etrav_total}")
+    log(f"traversed edges per step (GPU count): {etrav_total}")
 
     for _ in range(args.warmup):
         step()
@@ -130,8 +138,6 @@ def main():
     K.kairos_profile_enable(G, False)
 
     tuning = K.kairos_get_tuning(G)
-    roofline = roofline_from_profile(prof, args.mode, etrav_total * args.steps, args.workload, tuning)
-    roofline["profiled_ms_per_step"] = round(prof_elapsed / args.steps * 1e3, 3)
     if os.environ.get("KAIROS_CALIBRATION_COPY"):
         # a plain 256 MiB copy: the counter-calibration kernel of bench_pmc.py
         src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
@@ -147,8 +153,24 @@ def main():
         extra["serving"] = serve_sweep(K, torch, G, g, args.workload)
 
     cpu = None
+    numerator = {"source": "gpu count (kairos_traversed_edges)", "queries": q}
     if not args.no_cpu:
-        cpu = cpu_baseline(g, srcs, ta, tw, etrav, args.cpu_seconds)
+        del out, one
+        G.free()  # the oracle's sorted copy needs host memory, not the GPU; free device state first
+        G = None
+        cpu, oracle_etrav = cpu_baseline(g, srcs, ta, tw, args.cpu_seconds)
+        bad = [i for i in range(q) if oracle_etrav[i] != etrav[i]]
+        if bad:
+            print(json.dumps({"error": "traversed-edge count differs between the GPU and the oracle",
+                              "queries": bad[:8]}), flush=True)
+            sys.exit(1)
+        etrav_total = int(sum(oracle_etrav))
+        value = etrav_total * args.steps / elapsed
+        numerator = {"source": "oracle (C scan result, untimed), equal to the gpu count on every query",
+                     "queries": q}
+    roofline = roofline_from_profile(prof, args.mode, etrav_total * args.steps, args.workload, tuning)
+    roofline["profiled_ms_per_step"] = round(prof_elapsed / args.steps * 1e3, 3)
+    roofline["path"] = path_bytes(prof, etrav_total * args.steps, g.n * q * args.steps, elapsed)
 
     line = {
         "metric": "temporal edges traversed/s", "value": value, "unit": "edges/s",
@@ -159,7 +181,7 @@ def main():
                    "mode": args.mode, "window": cfg["window"]},
         "queries_per_s": q * args.steps / elapsed,
         "build_ms": round(build_s * 1e3, 2), "build_edges_per_s": g.m / build_s,
-        "traversed_edges_per_step": etrav_total,
+        "traversed_edges_per_step": etrav_total, "numerator": numerator,
         "rounds_per_step": prof["rounds"] / args.steps,
         "roofline": roofline, "cpu_baseline": cpu,
         "tuning": {"source": "autotuner" if args.tune else "defaults",
@@ -170,21 +192,37 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
-    G.free()
+    if G is not None:
+        G.free()
 
 
 # Algorithmic bytes per unit of work (what the method must move, not what the
-# caches do):
-#   per-(query, vertex) kernels -- single queries (push, chunk, tail,
-#   persist), the query-major batch, the lane-dense batch (hpush, hchunk,
-#   hpersist): 8 B per scanned out-edge record (head, arrival) + 4 B for the
-#   head's arrival + 16 B per frontier entry (two offsets, the tail's arrival,
-#   its claim word) + 8 B per improving relaxation (the new arrival and the
-#   enqueued entry);
-#   vertex-major batch (bpush, bchunk): 8 B per edge record, read once for
-#   the 64 queries of a group + 4 B per (edge, query) check of the head's
-#   arrival row + 12 B per (frontier vertex, query) claim + 4 B per improving
-#   relaxation.
+# caches do), for the per-(query, vertex) kernels -- single queries (push,
+# chunk, tail, persist), the query-major batch and the lane-dense batch
+# (hpush, hchunk, hpersist):
+#   8 B per traversed edge (the record's head and arrival),
+#   16 B per frontier entry expanded (two offsets, the tail's arrival, its
+#        claim word),
+#   4 B per successful relaxation (the new arrival),
+#   8 B per (query, vertex) for the whole query (arrival init + result),
+#        charged to the path figure, not to a traversal kernel.
+# A kernel's traversed edges are the step's traversed edges (counted from
+# the result) in proportion to the edges that kernel scanned.  The
+# vertex-major batch (bpush, bchunk) reads each edge record once for the 64
+# queries of a group: 8 B per edge record + 4 B per (edge, query) check of
+# the head's arrival row + 12 B per (vertex, query) claim + 4 B per
+# successful relaxation.
+B_EDGE, B_ITEM, B_RELAX, B_VERTEX = 8, 16, 4, 8
+
+
+def path_bytes(prof, traversed, vertex_queries, seconds):
+    """Whole-step algorithmic bytes (all kernels) over the timed step time."""
+    b = B_EDGE * traversed + B_ITEM * (prof["items"] + prof.get("tail_items", 0)) \
+        + B_RELAX * prof["relaxations"] + B_VERTEX * vertex_queries
+    gbs = b / seconds / 1e9 if seconds > 0 else 0.0
+    return {"bytes": int(b), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def kernel_names(mode, tuning):
     """Kernel names of the push, chunk and tail classes for this run."""
     if mode == "single":
@@ -215,7 +253,7 @@ def roofline_from_profile(prof, mode, pairs, workload, tuning):
         if vertex_major:
             b = 8 * edges[c] + 4 * pairs * share + 12 * items[c] + 4 * prof["relaxations"] * share
         else:
-            b = 12 * edges[c] + 16 * items[c] + 8 * prof["relaxations"] * share
+            b = B_EDGE * pairs * share + B_ITEM * items[c] + B_RELAX * prof["relaxations"] * share
         res[c] = {"bytes": b, "launches": max(1, prof[f"launches_{c}"]), "ms": prof[f"ms_{c}"]}
     kern = max(res, key=lambda c: res[c]["ms"])
     r = res[kern]
@@ -320,10 +358,10 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
     (closed loop, growing its slot pool).  Latency runs from the query's
     arrival time to its completion; queries wait on the client side while
     all `pool` output buffers are in flight."""
-    from workloads import poisson_arrivals
+    from workloads import make_queries, poisson_arrivals
     from workloads.configs import make_kinds
     total = count + warmup
-    srcs, ta, tw = make_queries_log(name, g, total)
+    srcs, ta, tw = make_queries("serve-rmat20", g, total)
     kinds = make_kinds("serve-rmat20", total)
     pool = min(pool, total)
     outs = torch.empty((pool, g.n), dtype=torch.int32, device="cuda")
@@ -393,41 +431,73 @@ def _drain(K, srv, want):
         time.sleep(0.0001)
 
 
-def make_queries_log(name, g, count):
-    from workloads.gen import log_uniform_windows, sample_sources
-    from workloads import CONFIGS
-    c = CONFIGS["serve-rmat20"]
-    ss = np.random.SeedSequence(c["qseed"]).spawn(2)
-    src = sample_sources(g, count, int(ss[0].generate_state(1)[0]))
-    ta, tw = log_uniform_windows(count, c["t_lo"], c["t_hi"], int(ss[1].generate_state(1)[0]))
-    return src, ta, tw
+def host_threads():
+    """Threads the CPU leg may use: this process's CPU affinity, capped by
+    OMP_NUM_THREADS when the host sets it (the host's share of cores)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
 
 
-def cpu_baseline(g, srcs, ta, tw, etrav, seconds):
+def host_description():
+    model, mem = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem = round(int(line.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "mem_gib": mem}
+
+
+def cpu_baseline(g, srcs, ta, tw, seconds):
     """The CPU oracle (one-pass scan over edges sorted by departure time),
-    one query per host thread, on as many of the workload's queries as fit
-    in about `seconds` of wall time."""
+    one query per host thread.  Timed on as many of the workload's queries
+    as fit in about `seconds` of wall time (all of them when they fit);
+    then, untimed, the oracle answers every query and counts the edges each
+    traverses from its own result: the benchmark's numerator."""
     import oracle
     from concurrent.futures import ThreadPoolExecutor
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = host_threads()
+    q = len(srcs)
     t = time.perf_counter()
-    se = oracle.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    se = oracle.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam, threads=cores)
     sort_s = time.perf_counter() - t
-    # probe one query to size the sample
+    # probe one query to size the timed sample
     t = time.perf_counter()
     oracle.earliest_arrival(se, srcs[0], ta[0], tw[0])
     per = max(time.perf_counter() - t, 1e-4)
-    k = int(min(len(srcs), max(cores, seconds * cores / per)))
-    k = max(1, min(k, len(srcs)))
+    k = int(min(q, max(cores, seconds * cores / per)))
+    k = max(1, min(k, q))
+    results = {}
+
+    def run(i):
+        results[i] = oracle.earliest_arrival(se, srcs[i], ta[i], tw[i])
+
     t = time.perf_counter()
     with ThreadPoolExecutor(cores) as ex:
-        list(ex.map(lambda i: oracle.earliest_arrival(se, srcs[i], ta[i], tw[i]), range(k)))
+        list(ex.map(run, range(k)))
     dt = time.perf_counter() - t
+
+    def count(i):
+        arr = results.pop(i) if i in results else oracle.earliest_arrival(se, srcs[i], ta[i], tw[i])
+        return oracle.traversed_edges(se, ta[i], tw[i], arr)
+
+    with ThreadPoolExecutor(cores) as ex:
+        etrav = list(ex.map(count, range(q)))
     edges = float(sum(etrav[:k]))
-    return {"value": edges / dt, "unit": "edges/s", "cores": cores, "kind": "oracle",
-            "queries_per_s": k / dt,
-            "sample": f"first {k} of {len(srcs)} queries of the workload, one per thread; "
-                      f"edges pre-sorted by departure once ({sort_s:.1f} s, not counted)"}
+    cpu = {"value": edges / dt, "unit": "edges/s", "cores": cores, "kind": "oracle",
+           "queries_per_s": k / dt, "host": host_description(),
+           "sample": f"first {k} of {q} queries of the workload, one per thread on {cores} threads; "
+                     f"edges pre-sorted by departure once ({sort_s:.1f} s, not counted)"}
+    return cpu, etrav
 
 
 if __name__ == "__main__":

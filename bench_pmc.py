@@ -53,8 +53,10 @@ def short_name(n: str) -> str:
 
 
 def run(argv):
-    mode = argv[argv.index("--mode") + 1] if "--mode" in argv else "batch"
-    workload = argv[argv.index("--workload") + 1] if "--workload" in argv else "rmat20-32m"
+    sys.path.insert(0, ROOT)
+    from workloads import CONFIGS
+    workload = argv[argv.index("--workload") + 1] if "--workload" in argv else "bursty22-1b"
+    mode = argv[argv.index("--mode") + 1] if "--mode" in argv else CONFIGS[workload].get("bench_mode", "batch")
     out = os.path.join(ROOT, OUT_ROOT, f"pmc_{workload}_{mode}")
     os.makedirs(out, exist_ok=True)
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
@@ -63,6 +65,7 @@ def run(argv):
     bench = [sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu", *argv]
     passes = [("trace", ["--kernel-trace", "--stats"]), ("fetch", ["--pmc", "FETCH_SIZE"]),
               ("write", ["--pmc", "WRITE_SIZE"])]
+    exits = {}
     for tag, opts in passes:
         cmd = ["timeout", "-s", "KILL", "240", "rocprofv3", *opts, "-d", os.path.join(out, tag), "-o", "run",
                "--", *bench]
@@ -70,13 +73,18 @@ def run(argv):
         with open(os.path.join(out, f"{tag}.log"), "w") as log:
             rc = subprocess.call(cmd, stdout=log, stderr=subprocess.STDOUT, env=env)
         print(f"pass {tag} rc={rc}", flush=True)
+        exits[tag] = rc
+        with open(os.path.join(out, "exits.json"), "w") as f:
+            json.dump(exits, f)  # the summary states every pass's exit status
         if rc in (-11, 139) and _bench_line_printed(os.path.join(out, f"{tag}.log")):
             # rocprofv3 can fault in its own exit handler after a cooperative
-            # launch; the program had finished and the results are complete
-            print(f"pass {tag}: profiler ended with a fault after the program finished; results kept", flush=True)
+            # launch once the program has printed its last line; the results
+            # are complete, and the summary records the fault
+            print(f"pass {tag}: profiler faulted after the program finished (status {rc}); "
+                  "results kept and the fault recorded in the summary", flush=True)
             continue
         if rc != 0:
-            sys.exit(rc)
+            sys.exit(rc if rc > 0 else 1)
 
 
 def _bench_line_printed(log_path):
@@ -91,7 +99,7 @@ def _db(path):
     return sqlite3.connect(dbs[0])
 
 
-def summarize(outdir, workload="rmat20-32m", mode="batch"):
+def summarize(outdir, workload="bursty22-1b", mode="single"):
     trace = _db(os.path.join(outdir, "trace"))
     stats = collections.defaultdict(lambda: [0, 0.0])
     for name, dur in trace.execute("select name, duration from kernels"):
@@ -125,8 +133,10 @@ def summarize(outdir, workload="rmat20-32m", mode="batch"):
             "fetch_bytes_per_launch": (f[1] / f[0] * 1024.0 / cal["FETCH_SIZE"]) if f else None,
             "write_bytes_per_launch": (w[1] / w[0] * 1024.0 / cal["WRITE_SIZE"]) if w else None,
         }
+    exits_path = os.path.join(outdir, "exits.json")
+    exits = json.load(open(exits_path)) if os.path.exists(exits_path) else {}
     doc = {"workload": workload, "mode": mode, "kernel_sources_sha": kernel_source_hash(), "calibration": cal,
-           "copy_bytes": COPY_BYTES, "kernels": rows}
+           "copy_bytes": COPY_BYTES, "profiler_exit_status": exits, "kernels": rows}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"traffic_{workload}_{mode}.json"), "w") as f:
         json.dump(doc, f, indent=1)
@@ -146,6 +156,9 @@ def summarize(outdir, workload="rmat20-32m", mode="batch"):
              f"  python bench_pmc.py summarize {os.path.relpath(os.path.abspath(outdir), ROOT)} {workload} {mode}",
              "",
              f"kernel sources sha256[:16]: {doc['kernel_sources_sha']}",
+             "profiler exit status per pass: " + (", ".join(f"{k}={v}" for k, v in exits.items()) or "not recorded")
+             + ("  (nonzero: rocprofv3 faulted in its own exit handler after the program printed its result line;"
+                " the result files were complete)" if any(v != 0 for v in exits.values()) else ""),
              f"calibration (counter / true bytes of a {COPY_BYTES >> 20} MiB copy): "
              + ", ".join(f"{k}={v:.3f}" for k, v in cal.items()),
              "",

@@ -144,8 +144,9 @@ int kairos_temporal_bfs(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_
 
 /* One single-source query of a given kind under a chosen succession
  * predicate (§2.2: TemporalEdgeMap takes the predicate as a parameter).
- *   kind   KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST
- *          or KAIROS_TEMPORAL_BFS; out as for the matching call above.
+ *   kind   KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST,
+ *          KAIROS_TEMPORAL_BFS, KAIROS_LATEST_DEPARTURE_TO or
+ *          KAIROS_SHORTEST_DURATION; out as for the matching call.
  *   flags  0: consecutive edges "Succeeds" (next departure >= previous
  *          arrival), as every other call here; KAIROS_STRICT: "Strictly
  *          succeeds" (next departure > previous arrival).  Under both, the
@@ -159,7 +160,8 @@ enum {
     KAIROS_LATEST_DEPARTURE = 1,
     KAIROS_FASTEST = 2,
     KAIROS_TEMPORAL_BFS = 3,
-    KAIROS_LATEST_DEPARTURE_TO = 4  /* src names the target; see below */
+    KAIROS_LATEST_DEPARTURE_TO = 4, /* src names the target; see below */
+    KAIROS_SHORTEST_DURATION = 5
 };
 #define KAIROS_STRICT 1u
 int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha,
@@ -179,6 +181,20 @@ int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32
  *   NOMEM, DEVICE. */
 int kairos_latest_departure_to(kairos_graph *g, uint32_t target, uint32_t t_alpha, uint32_t t_omega,
                                uint32_t *out);
+
+/* Shortest duration (Table 4's "S. Duration" row, on which §6.1 builds
+ * temporal betweenness): out[v] = the least total duration, the sum of
+ * lambda over its edges, of a time-respecting path from src to v within
+ * [t_alpha, t_omega]; 0 for src, INF if v is unreachable.  Waiting at a
+ * vertex costs nothing, so this differs from fastest (arrival minus
+ * departure).  The first call builds, once per graph, a map from each
+ * out-edge to the position of the same edge in the in-index (4 bytes per
+ * edge, counted by kairos_graph_stats); each query also takes 4 bytes per
+ * edge of scratch state, pooled per graph.  KAIROS_STRICT in kairos_query
+ * applies "Strictly succeeds" between consecutive edges.
+ *   out: device, n uint32.  Errors: INVALID, RANGE, NOMEM, DEVICE. */
+int kairos_shortest_duration(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                             uint32_t *out);
 
 /* q earliest-arrival queries answered together.
  *   src, t_alpha, t_omega  host, q entries each.
@@ -342,9 +358,15 @@ int kairos_server_poll(kairos_server *s, kairos_completion *done, uint32_t cap, 
 /* Waits for all submitted queries, stops the scheduler, frees the server. */
 void kairos_server_free(kairos_server *s);
 
+/* Counters of a server.  admitted_waits_mem counts the times the pool could
+ * not grow for lack of device memory; pool_slots is the current pool size
+ * and slot_bytes the device memory one slot takes (growing the pool from k
+ * to k' slots needs k' * slot_bytes free, since the new pool is allocated
+ * before the old one is released). */
 typedef struct kairos_server_stats {
     uint64_t submitted, completed, iterations, admitted_waits_mem;
-    uint32_t active_slots, waiting, max_slots_seen;
+    uint32_t active_slots, waiting, max_slots_seen, pool_slots;
+    uint64_t slot_bytes;
 } kairos_server_stats;
 int kairos_server_stats_read(kairos_server *s, kairos_server_stats *out);
 

@@ -73,7 +73,7 @@ def _lib():
         lib.oracle_profile.restype = ctypes.c_int
         lib.oracle_profile.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p, p, p]
         lib.oracle_shortest_duration.restype = ctypes.c_int
-        lib.oracle_shortest_duration.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p]
+        lib.oracle_shortest_duration.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, ctypes.c_int, p]
         lib.oracle_ea_certificate.restype = ctypes.c_int
         lib.oracle_ea_certificate.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p, p]
         _LIB = lib
@@ -208,13 +208,15 @@ def profile(se: SortedEdges, source: int, t_alpha: int, t_omega: int):
     return ea, ld, fa
 
 
-def shortest_duration(se: SortedEdges, source: int, t_alpha: int, t_omega: int) -> np.ndarray:
+def shortest_duration(se: SortedEdges, source: int, t_alpha: int, t_omega: int,
+                      strict: bool = False) -> np.ndarray:
     """SD[v]: least total duration (sum of lambda) of a time-respecting path
     from ``source`` to v within [t_alpha, t_omega] (Table 4's shortest
-    duration), by per-vertex Pareto profiles of (arrival, duration)."""
+    duration), by per-vertex Pareto profiles of (arrival, duration).
+    ``strict``: consecutive edges follow "Strictly succeeds" (§2.2)."""
     sd = np.empty(se.n, np.uint32)
     rc = _lib().oracle_shortest_duration(se.m, _ptr(se.src), _ptr(se.dst), _ptr(se.t), _ptr(se.a), se.n,
-                                         int(source), int(t_alpha), int(t_omega), _ptr(sd))
+                                         int(source), int(t_alpha), int(t_omega), 1 if strict else 0, _ptr(sd))
     if rc != 0:
         raise MemoryError("oracle_shortest_duration")
     return sd
@@ -300,13 +302,14 @@ def brute_force(n, edges, source, t_alpha, t_omega):
     return ea, ld, fa
 
 
-def walk_facts(n, edges, source, t_alpha, t_omega):
+def walk_facts(n, edges, source, t_alpha, t_omega, strict=False):
     """Enumerate every time-respecting walk from ``source`` (tiny inputs).
 
     ``edges`` is a list of (u, v, t, lam).  Returns (used, sd): the set of
     indices of the edges that lie on at least one walk, and per vertex the
     least total duration (sum of lambda) of a walk reaching it (0 for the
-    source, INF if none)."""
+    source, INF if none).  ``strict``: consecutive edges follow "Strictly
+    succeeds" (§2.2); the first edge needs only t >= t_alpha."""
     sd = [INF] * n
     used = set()
     out = [[] for _ in range(n)]
@@ -314,16 +317,16 @@ def walk_facts(n, edges, source, t_alpha, t_omega):
         if t >= t_alpha and t + lam <= t_omega:
             out[u].append((i, v, t, t + lam, lam))
 
-    def walk(u, now, total):
+    def walk(u, now, total, first):
         for (i, v, t, a, lam) in out[u]:
-            if t < now:
+            if t < now or (strict and not first and t == now):
                 continue
             used.add(i)
             if total + lam < sd[v]:
                 sd[v] = total + lam
-            walk(v, a, total + lam)
+            walk(v, a, total + lam, False)
 
-    walk(source, t_alpha, 0)
+    walk(source, t_alpha, 0, True)
     sd[source] = 0
     return used, sd
 

@@ -340,10 +340,12 @@ static int dprofile_insert(dprofile_t *p, uint32_t a, uint32_t d)
     return 1;
 }
 
-/* Returns 0 on success, -1 on allocation failure.  sd: n entries. */
+/* Returns 0 on success, -1 on allocation failure.  sd: n entries.
+ * strict != 0: consecutive edges follow "Strictly succeeds" (§2.2), so an
+ * edge departing at t extends only paths that arrived by t - 1. */
 int oracle_shortest_duration(uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *t,
                              const uint32_t *a, uint32_t n, uint32_t source, uint32_t t_alpha,
-                             uint32_t t_omega, uint32_t *sd)
+                             uint32_t t_omega, int strict, uint32_t *sd)
 {
     dprofile_t *P = calloc(n, sizeof(dprofile_t));
     if (!P)
@@ -359,7 +361,9 @@ int oracle_shortest_duration(uint64_t m, const uint32_t *src, const uint32_t *ds
         if (u == source) {
             d = lam;
         } else {
-            int64_t k = dprofile_last_by(&P[u], t[e]);
+            if (strict && t[e] == 0)
+                continue;
+            int64_t k = dprofile_last_by(&P[u], strict ? t[e] - 1 : t[e]);
             if (k < 0)
                 continue;
             d = P[u].dur[k] + lam;

@@ -17,7 +17,7 @@ import torch
 __all__ = [
     "KairosError", "Graph", "INF", "TMAX", "lib_path",
     "kairos_graph_build", "kairos_graph_free", "kairos_graph_stats", "kairos_graph_index",
-    "kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest",
+    "kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_shortest_duration",
     "kairos_earliest_arrival_batch", "kairos_traversed_edges",
     "kairos_get_tuning", "kairos_set_tuning", "kairos_autotune",
     "kairos_profile_enable", "kairos_profile_read",
@@ -70,7 +70,7 @@ class kairos_completion(ctypes.Structure):
 class kairos_server_stats(ctypes.Structure):
     _fields_ = [("submitted", _u64), ("completed", _u64), ("iterations", _u64),
                 ("admitted_waits_mem", _u64), ("active_slots", _u32), ("waiting", _u32),
-                ("max_slots_seen", _u32)]
+                ("max_slots_seen", _u32), ("pool_slots", _u32), ("slot_bytes", _u64)]
 
 
 def _sig(name, res, *args):
@@ -85,12 +85,13 @@ _sig("kairos_graph_free", None, _p)
 _sig("kairos_graph_stats", _i32, _p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
 _sig("kairos_graph_index", _i32, _p, ctypes.POINTER(kairos_index_view))
 for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs",
-           "kairos_latest_departure_to"):
+           "kairos_latest_departure_to", "kairos_shortest_duration"):
     _sig(_n, _i32, _p, _u32, _u32, _u32, _p)
 _sig("kairos_earliest_arrival_path", _i32, _p, _u32, _u32, _u32, _p, _p, _p)
 _sig("kairos_query", _i32, _p, _i32, _u32, _u32, _u32, _u32, _p)
 KAIROS_EARLIEST_ARRIVAL, KAIROS_LATEST_DEPARTURE, KAIROS_FASTEST, KAIROS_TEMPORAL_BFS = 0, 1, 2, 3
 KAIROS_LATEST_DEPARTURE_TO = 4
+KAIROS_SHORTEST_DURATION = 5
 KAIROS_STRICT = 1
 _sig("kairos_earliest_arrival_batch", _i32, _p, _u32, _p, _p, _p, _p)
 _sig("kairos_traversed_edges", _i32, _p, _u32, _u32, _p, ctypes.POINTER(_u64))
@@ -239,6 +240,10 @@ def kairos_latest_departure_to(g: Graph, target: int, t_alpha: int, t_omega: int
 
 def kairos_temporal_bfs(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
     return _single("kairos_temporal_bfs", g, src, t_alpha, t_omega, out)
+
+
+def kairos_shortest_duration(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
+    return _single("kairos_shortest_duration", g, src, t_alpha, t_omega, out)
 
 
 def kairos_query(g: Graph, kind: int, src: int, t_alpha: int, t_omega: int, out: torch.Tensor,

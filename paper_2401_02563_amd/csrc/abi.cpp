@@ -58,6 +58,7 @@ static void graph_release(kairos_graph *g)
 {
     if (!g) return;
     graph_release(g->rev);
+    release_duration_state(g);
     for (Slot *s : g->free_slots) slot_destroy(s);
     for (Slot *s : g->batch_slots) slot_destroy(s);
     for (VBatch *b : g->vbatches) vbatch_destroy(b);
@@ -136,7 +137,7 @@ int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t
     if (!g) return KAIROS_ERR_INVALID;
     if (n) *n = g->n;
     if (m) *m = g->m;
-    if (device_bytes) *device_bytes = g->index_bytes + (g->rev ? g->rev->index_bytes : 0);
+    if (device_bytes) *device_bytes = g->index_bytes + (g->rev ? g->rev->index_bytes : 0) + g->o2i_bytes;
     return KAIROS_OK;
 }
 
@@ -271,6 +272,20 @@ int kairos_latest_departure_to(kairos_graph *g, uint32_t target, uint32_t t_alph
     return latest_departure_to(g, target, t_alpha, t_omega, out, false);
 }
 
+static int shortest_duration(kairos_graph *g, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out, bool strict)
+{
+    if (!g || !out) return KAIROS_ERR_INVALID;
+    (void)hipGetLastError();
+    int rc = check_query(g, src, ta, tw);
+    if (rc) return rc;
+    return run_shortest_duration(g, src, ta, tw, out, strict);
+}
+
+int kairos_shortest_duration(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega, uint32_t *out)
+{
+    return shortest_duration(g, src, t_alpha, t_omega, out, false);
+}
+
 int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
                  uint32_t *out)
 {
@@ -278,6 +293,8 @@ int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32
     static const int internal[] = {0, 1, 2, 4};  // EA, LD, F, temporal BFS
     if (kind == KAIROS_LATEST_DEPARTURE_TO)
         return latest_departure_to(g, src, t_alpha, t_omega, out, (flags & KAIROS_STRICT) != 0);
+    if (kind == KAIROS_SHORTEST_DURATION)
+        return shortest_duration(g, src, t_alpha, t_omega, out, (flags & KAIROS_STRICT) != 0);
     if (kind < KAIROS_EARLIEST_ARRIVAL || kind > KAIROS_TEMPORAL_BFS) return KAIROS_ERR_INVALID;
     return single_query(g, internal[kind], src, t_alpha, t_omega, out, nullptr, nullptr,
                         (flags & KAIROS_STRICT) != 0);

@@ -668,6 +668,7 @@ struct VBatch {
     unsigned long long *stats = nullptr;
     uint32_t *bar = nullptr;  // grid barrier words of the persistent launch
     uint32_t *h_pin = nullptr;
+    uint4 *h_q = nullptr;  // groups * 64: pinned staging of query parameters
     hipStream_t stream = nullptr;
     bool own_stream = false;
 };
@@ -689,6 +690,7 @@ void vbatch_destroy(VBatch *b)
     dev_free(b->stats);
     dev_free(b->bar);
     if (b->h_pin) hipHostFree(b->h_pin);
+    if (b->h_q) hipHostFree(b->h_q);
     if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
     delete b;
 }
@@ -726,6 +728,11 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
               b->chunks && b->ranges && b->stats && b->bar;
     if (ok && hipHostMalloc((void **)&b->h_pin, 256, hipHostMallocDefault) != hipSuccess) {
         b->h_pin = nullptr;
+        ok = false;
+    }
+    if (ok && hipHostMalloc((void **)&b->h_q, (size_t)groups * 64 * sizeof(uint4), hipHostMallocDefault) !=
+                  hipSuccess) {
+        b->h_q = nullptr;
         ok = false;
     }
     if (ok) {
@@ -812,12 +819,12 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     // masks are left all-zero by every completed run (each processed entry
     // clears its word); a failed run destroys this state instead
 
-    std::vector<uint4> hq(q);
-    for (uint32_t i = 0; i < q; ++i) hq[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], 0);
-    uint4 *staging = nullptr;
-    if (hipHostMalloc((void **)&staging, std::max<size_t>(q, 1) * sizeof(uint4), hipHostMallocDefault) != hipSuccess)
-        return KAIROS_ERR_NOMEM;
-    std::memcpy(staging, hq.data(), q * sizeof(uint4));
+    // query parameters go through the batch state's pinned staging array
+    // (groups * 64 entries, allocated with the state; the init kernel reads
+    // it before the synchronisation below)
+    if (q > (size_t)b->groups * 64) return KAIROS_ERR_INVALID;
+    uint4 *staging = b->h_q;
+    for (uint32_t i = 0; i < q; ++i) staging[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], 0);
 
     BArgs A{};
     A.off = g->off_out;
@@ -845,11 +852,7 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
     prof_begin(g, st, &ev);
     hipLaunchKernelGGL(binit_kernel, dim3(gridc(q, 256, 64)), dim3(256), 0, st, A, staging, q);
     prof_end(g, st, KAIROS_K_INIT, ev);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
-        hipHostFree(staging);
-        return KAIROS_ERR_DEVICE;
-    }
-    hipHostFree(staging);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return KAIROS_ERR_DEVICE;
     KAIROS_HIP(hipMemcpyAsync(b->h_pin, b->cnt, 64, hipMemcpyDeviceToHost, st));
     KAIROS_HIP(hipStreamSynchronize(st));
     uint32_t F = b->h_pin[CNT_FRONT];

@@ -1,0 +1,570 @@
+// Shortest duration (Table 4's "S. Duration" row): the least total duration
+// (sum of lambda) of a time-respecting path from the source to each vertex
+// within the query interval.
+//
+// Unlike an arrival time, the duration of the best path into a vertex is not
+// one label: a path that arrives later with a smaller total can be the one
+// worth extending, so the state of a vertex v is a step function
+// D_v(t) = least duration of a path reaching v by time t.  It is kept per
+// in-edge: the index sorts v's in-edges by arrival, and after a prefix
+// minimum pm[k] over that order equals D_v(a_k).  An out-edge f = (v, w, t,
+// lambda) has the candidate D_v(t) + lambda, read at the last in-edge of v
+// arriving by t (before t under "Strictly succeeds"), and lowers pm at f's
+// own position in w's in-list (o2i[f]).
+//
+// Label-correcting rounds.  A relaxation that lowers pm at position k of w's
+// in-list widens w's dirty range [lo, hi] for the next round and enqueues w
+// once.  Expanding v redoes the prefix minimum from lo; past hi the stored
+// values are the previous prefix minima, so the scan stops at the first
+// position past hi whose value does not change, `stop`.  D_v changed exactly
+// on departures in [a_lo, a_stop), so only v's out-edges departing in that
+// interval are relaxed again.  Every value is the duration of a real path
+// and values only decrease, so a stale read costs work, never a wrong
+// result.  The source's D is 0 from t_alpha on: its usable out-edges are
+// relaxed once at the start with their own lambda, and it is never expanded.
+// When no vertex is left to expand, the result for v is the minimum of pm
+// over v's in-list.
+
+#include "internal.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace kairos {
+
+struct SDState {
+    uint32_t *pm = nullptr;                         // m: per in-edge duration label
+    uint32_t *dlo[2] = {nullptr, nullptr};          // n each: dirty range start (INF: clean)
+    uint32_t *dhi[2] = {nullptr, nullptr};          // n each: dirty range end (inclusive)
+    uint32_t *queue[2] = {nullptr, nullptr};        // n each: frontier vertices
+    uint4 *rng = nullptr;                           // n: {v, first out-edge, count, lo}
+    uint32_t *rstop = nullptr;                      // n: first in-position past the change
+    uint32_t *base = nullptr;                       // n + 1: out-edge counts, then their exclusive scan
+    uint32_t *bsum = nullptr;                       // block sums of the scan
+    uint32_t *cnt = nullptr;                        // SD_CNT_WORDS counters
+    uint32_t *h_pin = nullptr;                      // pinned read-back of cnt
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+namespace {
+
+constexpr int SDT = 256;                  // threads per block
+constexpr int SCAN_PER = 4;               // scan entries per thread
+constexpr int SCAN_BLK = SDT * SCAN_PER;  // scan entries per block
+constexpr int TOPT = 1024;                // threads of the top-level scan
+// counters: frontier sizes of the two parities, relax total
+enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_CNT_WORDS = 4 };
+
+struct SDArgs {
+    const uint32_t *off_out, *t_out;
+    const uint2 *da_out;
+    const uint32_t *off_in, *a_in;
+    const uint32_t *o2i;
+    uint32_t *pm;
+    uint32_t n, n_live, max_t, src, ta, tw, strict;
+};
+
+__device__ __forceinline__ uint32_t lower_bound_t(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi,
+                                                  uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// First position in [lo, hi) whose value exceeds key.
+__device__ __forceinline__ uint32_t upper_bound_t(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi,
+                                                  uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t below_mask()
+{
+    const uint32_t lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(SDT) void sd_fill_kernel(uint32_t *p, uint64_t count, uint32_t value)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * SDT + threadIdx.x; i < count; i += (uint64_t)gridDim.x * SDT)
+        p[i] = value;
+}
+
+// o2i[f] = position in the in-index of the first in-edge equal to out-edge
+// f in (tail, head, t, a).  Edges equal in all four are interchangeable for
+// every label here, so they may share one position.  One wavefront per tail.
+__global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ off_out,
+                                                  const uint32_t *__restrict__ t_out,
+                                                  const uint2 *__restrict__ da_out,
+                                                  const uint32_t *__restrict__ off_in,
+                                                  const uint32_t *__restrict__ a_in,
+                                                  const uint2 *__restrict__ st_in, uint32_t n_live,
+                                                  uint32_t *__restrict__ o2i)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (SDT / 64);
+    for (uint32_t u = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); u < n_live; u += waves) {
+        const uint32_t e = off_out[u + 1];
+        for (uint32_t f = off_out[u] + lane; f < e; f += 64) {
+            const uint2 va = da_out[f];
+            const uint32_t t = t_out[f];
+            uint32_t lo = off_in[va.x], hi = off_in[va.x + 1];
+            // in-list order: (a, t, tail)
+            while (lo < hi) {
+                const uint32_t mid = lo + ((hi - lo) >> 1);
+                const uint32_t am = a_in[mid];
+                const uint2 st = st_in[mid];
+                const bool less = am < va.y || (am == va.y && (st.y < t || (st.y == t && st.x < u)));
+                if (less)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            o2i[f] = lo;
+        }
+    }
+}
+
+// Lowers pm[pos] to `cand`; on success widens the head's dirty range and
+// reports whether this is the range's first entry of the round (then the
+// caller enqueues the head).
+__device__ __forceinline__ bool sd_lower(uint32_t *pm, uint32_t pos, uint32_t cand, uint32_t *dlo, uint32_t *dhi,
+                                         uint32_t w)
+{
+    if (cand >= pm[pos]) return false;
+    if (cand >= atomicMin(&pm[pos], cand)) return false;
+    atomicMax(&dhi[w], pos);
+    return atomicMin(&dlo[w], pos) == INF;
+}
+
+// Appends w for every lane with `push` set, one atomicAdd per wavefront.
+// Every lane of the wavefront calls it.
+__device__ __forceinline__ void wave_append(bool push, uint32_t w, uint32_t *next, uint32_t *cnt)
+{
+    const unsigned long long b = __ballot(push);
+    if (!b) return;
+    uint32_t base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(cnt, (uint32_t)__popcll(b));
+    base = __shfl(base, 0);
+    if (push) next[base + __popcll(b & below_mask())] = w;
+}
+
+// The source's usable out-edges (t >= t_alpha, a <= t_omega), each a path
+// of one edge with duration lambda.
+__global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, uint32_t *dhi, uint32_t *next,
+                                                      uint32_t *cnt)
+{
+    const uint32_t b = A.off_out[A.src], e = A.off_out[A.src + 1];
+    const uint32_t lo = lower_bound_t(A.t_out, b, e, A.ta);
+    const uint32_t hi = A.tw > A.max_t ? e : lower_bound_t(A.t_out, lo, e, A.tw);
+    for (uint32_t f0 = lo + blockIdx.x * SDT; f0 < hi; f0 += gridDim.x * SDT) {
+        const uint32_t f = f0 + threadIdx.x;
+        bool push = false;
+        uint32_t w = 0;
+        if (f < hi) {
+            const uint2 va = A.da_out[f];
+            w = va.x;
+            if (va.y <= A.tw && w != A.src)
+                push = sd_lower(A.pm, A.o2i[f], va.y - A.t_out[f], dlo, dhi, w) && w < A.n_live;
+        }
+        wave_append(push, w, next, cnt);
+    }
+}
+
+// One wavefront per frontier vertex v: prefix minimum of pm over v's
+// in-list from its dirty start until it stops changing past the dirty end,
+// then the range of v's out-edges whose candidate can have changed.
+__global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur, uint32_t F,
+                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng, uint32_t *rstop,
+                                                        uint32_t *lens, uint32_t *cnt_next)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (SDT / 64);
+    for (uint32_t i = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); i < F; i += waves) {
+        const uint32_t v = cur[i];
+        // lane 0 reads the dirty range and cleans it for the round after
+        // next (the relaxations of this round write the other parity)
+        uint32_t p = 0, hi = 0;
+        if (lane == 0) {
+            p = dlo[v];
+            hi = dhi[v];
+            dlo[v] = INF;
+            dhi[v] = 0u;
+        }
+        p = __shfl(p, 0);
+        hi = __shfl(hi, 0);
+        const uint32_t end = A.off_in[v + 1];
+        uint32_t carry = p > A.off_in[v] ? A.pm[p - 1] : INF;
+        uint32_t stop = end;
+        for (uint32_t k0 = p; k0 < end; k0 += 64) {
+            const uint32_t k = k0 + lane;
+            const uint32_t old = k < end ? A.pm[k] : INF;
+            uint32_t x = old;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= (uint32_t)o) x = min(x, y);
+            }
+            x = min(x, carry);
+            // past the dirty end an unchanged value means every later one
+            // is unchanged too
+            const unsigned long long same = __ballot(k < end && k > hi && x == old);
+            const uint32_t first = same ? (uint32_t)__ffsll((long long)same) - 1u : 64u;
+            if (k < end && lane < first && x != old) A.pm[k] = x;
+            if (same) {
+                stop = k0 + first;
+                break;
+            }
+            carry = __shfl(x, 63);
+        }
+        // out-edges departing in [a_p, a_stop) ([a_p + 1, a_stop + 1) under
+        // strict succession), and before t_omega
+        const uint32_t ob = A.off_out[v], oe = A.off_out[v + 1];
+        const uint32_t klo = A.a_in[p] + A.strict;
+        const uint32_t lo = lower_bound_t(A.t_out, ob, oe, klo);
+        uint32_t hi_out;
+        if (stop < end) {
+            const uint32_t khi = min(A.a_in[stop] + A.strict, A.tw);
+            hi_out = lower_bound_t(A.t_out, lo, oe, khi);
+        } else {
+            hi_out = A.tw > A.max_t ? oe : lower_bound_t(A.t_out, lo, oe, A.tw);
+        }
+        if (lane == 0) {
+            const uint32_t len = hi_out > lo ? hi_out - lo : 0u;
+            rng[i] = make_uint4(v, lo, len, p);
+            rstop[i] = stop;
+            lens[i] = len;
+        }
+    }
+}
+
+// Exclusive scan of `count` words, SCAN_BLK per block; block totals to bsum.
+__global__ __launch_bounds__(SDT) void sd_scan_block_kernel(uint32_t *data, uint32_t count, uint32_t *bsum)
+{
+    __shared__ uint32_t s_w[SDT / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t b0 = blockIdx.x * SCAN_BLK + tid * SCAN_PER;
+    uint32_t v[SCAN_PER];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        v[j] = b0 + j < count ? data[b0 + j] : 0u;
+        s += v[j];
+    }
+    uint32_t x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (uint32_t k = 0; k < SDT / 64; ++k) {
+        if (k < w) off += s_w[k];
+        tot += s_w[k];
+    }
+    uint32_t run = off + x - s;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        if (b0 + j < count) data[b0 + j] = run;
+        run += v[j];
+    }
+    if (tid == 0) bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the nb block totals in one block; the grand total to
+// *total.
+__global__ __launch_bounds__(TOPT) void sd_scan_top_kernel(uint32_t *bsum, uint32_t nb, uint32_t *total)
+{
+    __shared__ uint32_t part[TOPT];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (nb + TOPT - 1) / TOPT;
+    const uint32_t beg = min(nb, tid * per), end = min(nb, beg + per);
+    uint32_t s = 0;
+    for (uint32_t i = beg; i < end; ++i) s += bsum[i];
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t o = 1; o < TOPT; o <<= 1) {
+        const uint32_t y = tid >= o ? part[tid - o] : 0u;
+        __syncthreads();
+        part[tid] += y;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - s;
+    for (uint32_t i = beg; i < end; ++i) {
+        const uint32_t y = bsum[i];
+        bsum[i] = run;
+        run += y;
+    }
+    if (tid == TOPT - 1) *total = part[TOPT - 1];
+}
+
+__global__ __launch_bounds__(SDT) void sd_scan_add_kernel(uint32_t *data, uint32_t count, const uint32_t *bsum)
+{
+    const uint32_t add = bsum[blockIdx.x];
+    const uint32_t b0 = blockIdx.x * SCAN_BLK;
+    for (uint32_t j = threadIdx.x; j < SCAN_BLK; j += SDT)
+        if (b0 + j < count) data[b0 + j] += add;
+}
+
+// One thread per out-edge of the ranges: candidate D_v(t) + lambda into the
+// head's in-list position.
+__global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, const uint32_t *__restrict__ base,
+                                                       const uint4 *__restrict__ rng,
+                                                       const uint32_t *__restrict__ rstop,
+                                                       const uint32_t *__restrict__ total_p, uint32_t *dlo,
+                                                       uint32_t *dhi, uint32_t *next, uint32_t *cnt)
+{
+    const uint32_t total = *total_p;
+    for (uint32_t j0 = blockIdx.x * SDT; j0 < total; j0 += gridDim.x * SDT) {
+        const uint32_t j = j0 + threadIdx.x;
+        bool push = false;
+        uint32_t w = 0;
+        if (j < total) {
+            const uint32_t i = upper_bound_t(base, 0, F, j) - 1u;  // the range holding edge j
+            const uint4 r = rng[i];
+            const uint32_t f = r.y + (j - base[i]);
+            const uint2 va = A.da_out[f];
+            const uint32_t t = A.t_out[f];
+            w = va.x;
+            if (va.y <= A.tw && w != A.src) {
+                // last in-edge of v arriving by t (before t when strict);
+                // t lies in [a_lo, a_stop) by construction of the range
+                const uint32_t key = t - A.strict;
+                const uint32_t k = upper_bound_t(A.a_in, r.w, rstop[i], key) - 1u;
+                const uint32_t d = A.pm[k];
+                if (d != INF) push = sd_lower(A.pm, A.o2i[f], d + (va.y - t), dlo, dhi, w) && w < A.n_live;
+            }
+        }
+        wave_append(push, w, next, cnt);
+    }
+}
+
+// out[c] for caller vertex c: 0 at the source, else the least label over
+// its in-list (INF when none).  One wavefront per vertex.
+__global__ __launch_bounds__(SDT) void sd_output_kernel(const uint32_t *__restrict__ off_in,
+                                                        const uint32_t *__restrict__ pm,
+                                                        const uint32_t *__restrict__ perm, uint32_t n, uint32_t src,
+                                                        uint32_t *__restrict__ out)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (SDT / 64);
+    for (uint32_t c = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); c < n; c += waves) {
+        const uint32_t v = perm[c];
+        uint32_t x = INF;
+        if (v != src)
+            for (uint32_t k = off_in[v] + lane; k < off_in[v + 1]; k += 64) x = min(x, pm[k]);
+        else
+            x = 0u;
+        for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o));
+        if (lane == 0) out[c] = x;
+    }
+}
+
+uint32_t grid_for(uint64_t items, uint32_t per_block, uint32_t cap)
+{
+    const uint64_t b = (items + per_block - 1) / per_block;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(b, cap));
+}
+
+void sd_state_free(SDState *s)
+{
+    if (!s) return;
+    if (s->stream) hipStreamSynchronize(s->stream);
+    dev_free(s->pm);
+    for (int k = 0; k < 2; ++k) {
+        dev_free(s->dlo[k]);
+        dev_free(s->dhi[k]);
+        dev_free(s->queue[k]);
+    }
+    dev_free(s->rng);
+    dev_free(s->rstop);
+    dev_free(s->base);
+    dev_free(s->bsum);
+    dev_free(s->cnt);
+    if (s->h_pin) hipHostFree(s->h_pin);
+    if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int sd_state_alloc(kairos_graph *g, SDState **out)
+{
+    SDState *s = new SDState();
+    const size_t n = g->n, m = std::max<uint64_t>(g->m, 1);
+    bool ok = (s->pm = (uint32_t *)dev_alloc(m * 4, nullptr)) != nullptr;
+    for (int k = 0; k < 2; ++k) {
+        ok = ok && (s->dlo[k] = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
+        ok = ok && (s->dhi[k] = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
+        ok = ok && (s->queue[k] = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
+    }
+    ok = ok && (s->rng = (uint4 *)dev_alloc(n * sizeof(uint4), nullptr)) != nullptr;
+    ok = ok && (s->rstop = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
+    ok = ok && (s->base = (uint32_t *)dev_alloc((n + 1) * 4, nullptr)) != nullptr;
+    ok = ok && (s->bsum = (uint32_t *)dev_alloc((n / SCAN_BLK + 2) * 4, nullptr)) != nullptr;
+    ok = ok && (s->cnt = (uint32_t *)dev_alloc(SD_CNT_WORDS * 4, nullptr)) != nullptr;
+    if (ok && hipHostMalloc((void **)&s->h_pin, SD_CNT_WORDS * 4, hipHostMallocDefault) != hipSuccess) {
+        s->h_pin = nullptr;
+        ok = false;
+    }
+    if (ok) {
+        if (g->stream) {
+            s->stream = g->stream;
+        } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
+            s->own_stream = true;
+        } else {
+            ok = false;
+        }
+    }
+    if (!ok) {
+        sd_state_free(s);
+        return KAIROS_ERR_NOMEM;
+    }
+    *out = s;
+    return KAIROS_OK;
+}
+
+// The out-edge -> in-edge position map, built once per graph.
+int ensure_o2i(kairos_graph *g, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g->sd_mu);
+    if (g->o2i) return KAIROS_OK;
+    uint32_t *o2i = (uint32_t *)dev_alloc(std::max<uint64_t>(g->m, 1) * 4, nullptr);
+    if (!o2i) return KAIROS_ERR_NOMEM;
+    if (g->m > 0) {
+        hipLaunchKernelGGL(o2i_kernel, dim3(grid_for(g->n_live, SDT / 64, (uint32_t)g->num_cus * 16)), dim3(SDT), 0,
+                           st, g->off_out, g->t_out, g->da_out, g->off_in, g->a_in, g->st_in, g->n_live, o2i);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            dev_free(o2i);
+            return KAIROS_ERR_DEVICE;
+        }
+    }
+    g->o2i = o2i;
+    g->o2i_bytes = std::max<uint64_t>(g->m, 1) * 4;
+    return KAIROS_OK;
+}
+
+int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out, bool strict)
+{
+    hipStream_t st = s->stream;
+    const uint32_t n = g->n;
+    const uint32_t src_i = g->h_perm[src];
+    const uint32_t cap = (uint32_t)g->num_cus * 16;
+    SDArgs A{};
+    A.off_out = g->off_out;
+    A.t_out = g->t_out;
+    A.da_out = g->da_out;
+    A.off_in = g->off_in;
+    A.a_in = g->a_in;
+    A.o2i = g->o2i;
+    A.pm = s->pm;
+    A.n = n;
+    A.n_live = g->n_live;
+    A.max_t = g->max_t;
+    A.src = src_i;
+    A.ta = ta;
+    A.tw = tw;
+    A.strict = strict ? 1u : 0u;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    const uint64_t m = std::max<uint64_t>(g->m, 1);
+    hipLaunchKernelGGL(sd_fill_kernel, dim3(grid_for(m, SDT, cap * 4)), dim3(SDT), 0, st, s->pm, m, INF);
+    for (int k = 0; k < 2; ++k) {
+        hipLaunchKernelGGL(sd_fill_kernel, dim3(grid_for(n, SDT, cap)), dim3(SDT), 0, st, s->dlo[k], (uint64_t)n, INF);
+        hipLaunchKernelGGL(sd_fill_kernel, dim3(grid_for(n, SDT, cap)), dim3(SDT), 0, st, s->dhi[k], (uint64_t)n, 0u);
+    }
+    hipLaunchKernelGGL(sd_fill_kernel, dim3(1), dim3(SDT), 0, st, s->cnt, (uint64_t)SD_CNT_WORDS, 0u);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    if (g->m > 0 && src_i < g->n_live) {
+        const uint32_t deg = g->max_out_degree;
+        prof_begin(g, st, &ev);
+        hipLaunchKernelGGL(sd_seed_kernel, dim3(grid_for(deg, SDT, cap)), dim3(SDT), 0, st, A, s->dlo[0], s->dhi[0],
+                           s->queue[0], s->cnt + SD_FRONT);
+        prof_end(g, st, KAIROS_K_PUSH, ev);
+        KAIROS_HIP(hipGetLastError());
+        KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, SD_CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
+        KAIROS_HIP(hipStreamSynchronize(st));
+        uint32_t F = s->h_pin[SD_FRONT];
+        uint32_t r = 0;
+        while (F > 0) {
+            const uint32_t p = r & 1u, q = p ^ 1u;
+            prof_begin(g, st, &ev);
+            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, cap)), dim3(SDT), 0, st, A, s->queue[p],
+                               F, s->dlo[p], s->dhi[p], s->rng, s->rstop, s->base, s->cnt + SD_FRONT + q);
+            const uint32_t nb = (F + SCAN_BLK - 1) / SCAN_BLK;
+            hipLaunchKernelGGL(sd_scan_block_kernel, dim3(nb), dim3(SDT), 0, st, s->base, F, s->bsum);
+            hipLaunchKernelGGL(sd_scan_top_kernel, dim3(1), dim3(TOPT), 0, st, s->bsum, nb, s->cnt + SD_TOTAL);
+            if (nb > 1) hipLaunchKernelGGL(sd_scan_add_kernel, dim3(nb), dim3(SDT), 0, st, s->base, F, s->bsum);
+            hipLaunchKernelGGL(sd_relax_kernel, dim3(cap), dim3(SDT), 0, st, A, F, s->base, s->rng, s->rstop,
+                               s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q);
+            prof_end(g, st, KAIROS_K_PUSH, ev);
+            KAIROS_HIP(hipGetLastError());
+            KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, SD_CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
+            KAIROS_HIP(hipStreamSynchronize(st));
+            F = s->h_pin[SD_FRONT + q];
+            ++r;
+            if (F > n) return KAIROS_ERR_DEVICE;  // a vertex is enqueued at most once per round
+        }
+        if (g->prof.on) {
+            std::lock_guard<std::mutex> lk(g->prof.mu);
+            g->prof.rounds += r;
+        }
+    }
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(sd_output_kernel, dim3(grid_for(n, SDT / 64, cap * 4)), dim3(SDT), 0, st, g->off_in, s->pm,
+                       g->perm, n, src_i, out);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    return KAIROS_OK;
+}
+
+}  // namespace
+
+int run_shortest_duration(kairos_graph *g, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out, bool strict)
+{
+    SDState *s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->pool_mu);
+        if (!g->sd_states.empty()) {
+            s = g->sd_states.back();
+            g->sd_states.pop_back();
+        }
+    }
+    int rc = s ? KAIROS_OK : sd_state_alloc(g, &s);
+    if (rc) return rc;
+    rc = ensure_o2i(g, s->stream);
+    if (rc == KAIROS_OK) rc = run_sd(g, s, src, ta, tw, out, strict);
+    if (rc == KAIROS_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    if (rc == KAIROS_OK) {
+        std::lock_guard<std::mutex> lk(g->pool_mu);
+        g->sd_states.push_back(s);
+    } else {
+        sd_state_free(s);
+    }
+    return rc;
+}
+
+void release_duration_state(kairos_graph *g)
+{
+    for (SDState *s : g->sd_states) sd_state_free(s);
+    g->sd_states.clear();
+    dev_free(g->o2i);
+    g->o2i = nullptr;
+    g->o2i_bytes = 0;
+}
+
+}  // namespace kairos

@@ -56,6 +56,7 @@ struct Slot {
     unsigned long long *stats = nullptr; // device work counters, see ST_*
     uint32_t *bar = nullptr;     // grid barrier words of persistent launches
     uint32_t *h_pin = nullptr;   // pinned host mirror for counter read-back
+    uint4 *h_q = nullptr;        // qcap: pinned staging of query parameters (read by the init kernel)
     uint32_t stamp_next = 2;     // next round stamp value (0 = never stamped, 1 = spare)
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -95,6 +96,7 @@ inline void stats_sum_shards(const unsigned long long *raw, unsigned long long *
 }
 
 struct VBatch;
+struct SDState;
 
 struct ProfileAcc {
     bool on = false;
@@ -143,6 +145,12 @@ struct kairos_graph {
     // lambda, lambda)), built on the first single-target query
     kairos_graph *rev = nullptr;
     std::mutex rev_mu;
+    // shortest duration: for each out-edge, the in-index position of the
+    // same edge (built on the first such query), and pooled query state
+    uint32_t *o2i = nullptr;
+    uint64_t o2i_bytes = 0;
+    std::mutex sd_mu;
+    std::vector<kairos::SDState *> sd_states;
 };
 
 namespace kairos {
@@ -176,6 +184,11 @@ int run_latest_departure_to(kairos_graph *rev, Slot *s, uint32_t target, uint32_
 int run_batch(kairos_graph *g, Slot *s, uint32_t q, const uint32_t *src, const uint32_t *ta,
               const uint32_t *tw, uint32_t *out);
 int count_traversed(kairos_graph *g, uint32_t ta, uint32_t tw, const uint32_t *ea, uint64_t *count);
+
+// duration.hip: least total duration of a time-respecting path (Table 4's
+// shortest duration); strict: "Strictly succeeds" between consecutive edges
+int run_shortest_duration(kairos_graph *g, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out, bool strict);
+void release_duration_state(kairos_graph *g);
 
 // batch.hip: vertex-major batches of up to 64 queries per group
 int vbatch_acquire(kairos_graph *g, uint32_t groups, VBatch **out);

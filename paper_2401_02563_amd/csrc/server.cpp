@@ -145,11 +145,13 @@ void free_state(MultiState &m)
 }
 
 // Grow the slot pool to `ncap` slots, keeping the state of existing slots.
-// Called between rounds only.  Returns false if memory is short.
+// Called between rounds only.  Returns false if memory is short.  The new
+// pool is allocated whole while the old one is still live (its state is
+// copied over), so the check charges all ncap slots, the transient peak.
 bool grow(kairos_server *s, uint32_t ncap)
 {
     if (ncap <= s->cap) return true;
-    const uint64_t need = slot_bytes(s) * (ncap - s->cap);
+    const uint64_t need = slot_bytes(s) * ncap;
     if (!free_bytes_ok(s, need)) return false;
     const size_t n = s->g->n;
     const size_t qn = (size_t)ncap * n, on = (size_t)s->cap * n;
@@ -536,6 +538,8 @@ int kairos_server_stats_read(kairos_server *s, kairos_server_stats *out)
     if (!s || !out) return KAIROS_ERR_INVALID;
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
+    out->pool_slots = s->cap;
+    out->slot_bytes = slot_bytes(s);
     return KAIROS_OK;
 }
 

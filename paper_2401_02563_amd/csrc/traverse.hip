@@ -1387,6 +1387,11 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
         s->h_pin = nullptr;
         ok = false;
     }
+    if (ok && qcap > 8 && hipHostMalloc((void **)&s->h_q, (size_t)qcap * sizeof(uint4), hipHostMallocDefault) !=
+                              hipSuccess) {
+        s->h_q = nullptr;
+        ok = false;
+    }
     if (ok) {
         if (g->stream) {
             s->stream = g->stream;
@@ -1493,6 +1498,7 @@ void slot_destroy(Slot *s)
     dev_free(s->l1);
     dev_free(s->steps);
     if (s->h_pin) hipHostFree(s->h_pin);
+    if (s->h_q) hipHostFree(s->h_q);
     if (s->own_stream && s->stream) hipStreamDestroy(s->stream);
     delete s;
 }
@@ -1535,17 +1541,16 @@ static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq
     A.round = 0;
     A.next = s->queue[0];
     A.front_stamp = s->stamp_next - 1u;
-    // parameters travel through the pinned mirror (256 B) or a staging copy
+    // parameters travel through the pinned mirror (up to 8 queries) or the
+    // slot's pinned staging array (qcap entries, allocated with the slot)
+    if (nq > s->qcap) return KAIROS_ERR_INVALID;
     uint4 *dq = nullptr;
-    uint4 *staging = nullptr;
     if (nq * sizeof(uint4) <= 128) {
         std::memcpy(s->h_pin + 32, hqp, nq * sizeof(uint4));
         dq = (uint4 *)(s->h_pin + 32);
     } else {
-        if (hipHostMalloc((void **)&staging, nq * sizeof(uint4), hipHostMallocDefault) != hipSuccess)
-            return KAIROS_ERR_NOMEM;
-        std::memcpy(staging, hqp, nq * sizeof(uint4));
-        dq = staging;
+        std::memcpy(s->h_q, hqp, nq * sizeof(uint4));
+        dq = s->h_q;
     }
     hipEvent_t ev;
     prof_begin(g, st, &ev);
@@ -1553,9 +1558,9 @@ static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq
                        from_w ? 1u : 0u);
     prof_end(g, st, KAIROS_K_INIT, ev);
     hipError_t e1 = hipGetLastError();
-    if (staging) {
-        hipStreamSynchronize(st);
-        hipHostFree(staging);
+    if (nq * sizeof(uint4) > 128 && e1 == hipSuccess) {
+        // the staging array is rewritten by the next start on this slot
+        e1 = hipStreamSynchronize(st);
     }
     if (e1 != hipSuccess) {
         note_hip_error(e1, "init_queries_kernel", __FILE__, __LINE__);

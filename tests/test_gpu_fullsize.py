@@ -1,15 +1,19 @@
-"""Parity at the benchmark's full size and launch configuration.
+"""Parity at the benchmark's full sizes and launch configurations.
 
-The scale-20 R-MAT workload (2^25 edges) is checked in full: every row of
-the 64-query batch the benchmark times, single queries, latest departure /
-fastest samples and traversed-edge counts, all bit-exact against the oracle.
-The scale-24 single queries and the 2^28-edge batch are checked at full size
-by the EA certificate on sampled rows; the oracle's own scans of the larger
-workloads (about 10^9 bursty edges, 2^28 and 2^29 R-MAT edges, with latest
-departure / fastest on the bursty one) run when KAIROS_FULL_SIZE=1, since
-sorting those edge lists takes minutes of host time."""
-import os
+* rmat20-32m (2^25 edges): every row of the 64-query batch, single queries,
+  latest departure / fastest samples, predecessors, hop counts and
+  traversed-edge counts, all bit-exact against the oracle.
+* bursty22-1b (about 10^9 edges; the largest workload, and the one the
+  benchmark times one query per call): earliest arrival of five of its 32
+  queries checked by the exact EA certificate, two of them also against the
+  oracle's one-pass scan with their traversed-edge counts, and latest
+  departure / fastest of one query against the oracle's profile scan.
+* rmat22-256m (256-query batch) and rmat24-512m (single queries): eight rows
+  each by the EA certificate, two of them also against the oracle's scan.
 
+The certificate (source at t_alpha, a witness edge for every reached
+vertex, no usable edge arriving earlier) is exact and needs no sorted copy
+of the edges; it runs as one C loop over the edge list."""
 import numpy as np
 import pytest
 
@@ -23,18 +27,17 @@ import oracle as O  # noqa: E402
 import paper_2401_02563_amd as K  # noqa: E402
 from workloads import make_graph, make_queries  # noqa: E402
 
-FULL = os.environ.get("KAIROS_FULL_SIZE") == "1"
 _C = {}
 
 
 def load(name):
     if name not in _C:
+        _C.clear()  # keep one large workload in memory at a time
         print(f"case: generating {name}", flush=True)
         g = make_graph(name)
         G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
         print(f"case: index built for {name} (m={g.m})", flush=True)
         se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
-        _C.clear()  # keep one large workload in memory at a time
         _C[name] = (g, G, se)
     return _C[name]
 
@@ -91,68 +94,74 @@ def test_rmat20_paths_and_hops():
         assert np.array_equal(K.as_u32(out), wh)
 
 
-@pytest.mark.parametrize("name,kind,rows", [("rmat24-512m", "single", (0, 63)), ("rmat22-256m", "batch", (0, 255))])
-def test_full_size_certificate(name, kind, rows):
-    """The scale-24 single queries and the 256-query batch at full size, in
-    the launch configuration the benchmark times, checked by the EA
-    certificate (exact: source at t_alpha, a witness edge for every reached
-    vertex, no usable edge arriving earlier), which needs no sorted copy of
-    the edges and so runs in seconds of host time."""
+def _spread(k, count):
+    """`count` query indices spread over 0..k-1, first and last included."""
+    return sorted(set(np.linspace(0, k - 1, count).round().astype(int).tolist()))
+
+
+@pytest.mark.parametrize("name,kind,cert_rows,scan_rows,sweep_rows", [
+    ("bursty22-1b", "single", 5, 2, 1),
+    ("rmat24-512m", "single", 8, 2, 0),
+    ("rmat22-256m", "batch", 8, 2, 0)])
+def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
+    """Earliest arrival at full size in the launch configuration the
+    benchmark times (one query per call, or the whole batch in one call):
+    `cert_rows` rows by the exact certificate, the first and the middle of
+    them (`scan_rows`) also element by element against the oracle's scan
+    with their traversed-edge counts; latest departure / fastest of
+    `sweep_rows` queries against the oracle's profile scan."""
     _C.clear()
     print(f"case: generating {name}", flush=True)
     g = make_graph(name)
     G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    torch.cuda.synchronize()
     srcs, ta, tw = make_queries(name, g)
+    rows = _spread(len(srcs), cert_rows)
+    scan = [rows[0], rows[len(rows) // 2]][:scan_rows]
+    got, counts = {}, {}
+    one = torch.empty(g.n, dtype=torch.int32, device="cuda")
     if kind == "batch":
         out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
         print(f"case: {name} batch of {len(srcs)}", flush=True)
         K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
         view = out.view(len(srcs), g.n)
-        got = {q: K.as_u32(view[q]) for q in rows}
+        for q in rows:
+            got[q] = K.as_u32(view[q])
+            if q in scan:
+                counts[q] = K.kairos_traversed_edges(G, int(ta[q]), int(tw[q]), view[q])
         del out, view
     else:
-        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        got = {}
         for q in rows:
+            print(f"case: {name} single query {q}", flush=True)
             K.kairos_earliest_arrival(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
             got[q] = K.as_u32(one)
+            if q in scan:
+                counts[q] = K.kairos_traversed_edges(G, int(ta[q]), int(tw[q]), one)
+    sweeps = {}
+    for q in range(1, 1 + sweep_rows):
+        print(f"case: {name} latest departure / fastest of query {q}", flush=True)
+        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        ld = K.as_u32(one)
+        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        sweeps[q] = (ld, K.as_u32(one))
+    del one
     G.free()
+    torch.cuda.empty_cache()
+    a = (g.t.astype(np.uint64) + g.lam).astype(np.uint32)
     for q in rows:
         print(f"case: {name} certificate of query {q}", flush=True)
-        assert O.ea_certificate(g.n, g.src, g.dst, g.t, g.lam, int(srcs[q]), int(ta[q]), int(tw[q]), got[q]), q
+        assert O.ea_certificate_scan(g.n, g.src, g.dst, g.t, a, int(srcs[q]), int(ta[q]), int(tw[q]), got[q]), q
+    del a
     assert max(int((got[q] != 0xFFFFFFFF).sum()) for q in rows) > 1000  # real traversals, not trivial ones
-
-
-@pytest.mark.skipif(not FULL, reason="set KAIROS_FULL_SIZE=1 (minutes of host time)")
-@pytest.mark.parametrize("name,kind", [("rmat22-256m", "batch"), ("rmat24-512m", "single"),
-                                       ("bursty22-1b", "single")])
-def test_large_sampled(name, kind):
-    g, G, se = load(name)
-    srcs, ta, tw = make_queries(name, g)
-    sample = [0, 1, len(srcs) // 2, len(srcs) - 1]
-    if kind == "batch":
-        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
-        print(f"case: {name} batch of {len(srcs)}", flush=True)
-        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
-        rows = out.view(len(srcs), g.n)
-        got = {q: K.as_u32(rows[q]) for q in sample}
-    else:
-        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        got = {}
-        for q in sample:
-            K.kairos_earliest_arrival(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
-            got[q] = K.as_u32(one)
-    for q in sample:
-        print(f"case: {name} query {q}", flush=True)
-        assert np.array_equal(got[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
-    q = sample[0]
-    assert O.ea_certificate(g.n, g.src, g.dst, g.t, g.lam, int(srcs[q]), int(ta[q]), int(tw[q]), got[q])
-    if name == "bursty22-1b":
-        one = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        q = 1
-        print("case: bursty sweeps", flush=True)
+    print(f"case: {name} sorting edges by departure for the oracle", flush=True)
+    se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    for q in scan:
+        print(f"case: {name} oracle scan of query {q}", flush=True)
+        want = O.earliest_arrival(se, srcs[q], ta[q], tw[q])
+        assert np.array_equal(got[q], want), q
+        assert counts[q] == O.traversed_edges(se, ta[q], tw[q], want), q
+    for q, (ld, fa) in sweeps.items():
+        print(f"case: {name} oracle profile of query {q}", flush=True)
         pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
-        K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
-        assert np.array_equal(K.as_u32(one), pld)
-        K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
-        assert np.array_equal(K.as_u32(one), pf)
+        assert np.array_equal(ld, pld), q
+        assert np.array_equal(fa, pf), q

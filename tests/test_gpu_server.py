@@ -134,6 +134,31 @@ def test_admission_waits_for_memory_and_queue_is_bounded():
     K.kairos_server_free(srv)
 
 
+def test_pool_growth_charges_the_transient_peak():
+    """Growing the slot pool from k to k' slots allocates the new pool while
+    the old one is live, so it needs k' slots' worth of free memory, not
+    k' - k.  With room for six slots the pool grows to four but not to
+    eight; the queries still all finish, four at a time."""
+    g, G, se = graph("uniform-10k", 0)
+    srv = K.kairos_server_create(G, max_slots=8, queue_capacity=64)
+    K.kairos_server_set_free_bytes_override(srv, 0)
+    k = 12
+    src = sample_sources(g, k, 5)
+    outs = torch.empty((k, g.n), dtype=torch.int32, device="cuda")
+    for i in range(k):
+        K.kairos_server_submit(srv, 0, int(src[i]), 0, 99_999, outs[i])
+    time.sleep(0.05)
+    st = K.kairos_server_stats_read(srv)
+    assert st["completed"] == 0 and st["pool_slots"] == 0 and st["slot_bytes"] > 0, st
+    K.kairos_server_set_free_bytes_override(srv, 6 * st["slot_bytes"])
+    drain(srv, k)
+    st = K.kairos_server_stats_read(srv)
+    K.kairos_server_free(srv)
+    assert st["pool_slots"] == 4 and st["admitted_waits_mem"] > 0, st
+    for i in range(k):
+        assert np.array_equal(K.as_u32(outs[i]), O.earliest_arrival(se, src[i], 0, 99_999)), i
+
+
 def test_slot_reuse_has_no_stale_state():
     """One slot, queries alternating between wide and narrow windows: each
     result must match its own oracle, so nothing leaks from the previous
@@ -191,3 +216,48 @@ def _sweep_departures(g, G, se, rpc, slots):
         k, s_, a, w = cases[i]
         assert c["status"] == 0
         assert np.array_equal(K.as_u32(outs[i]), expected(se, k, s_, a, w)), cases[i]
+
+
+def test_served_mix_on_the_full_scale20_graph():
+    """The serving workload at full size: 240 queries of the 60/20/20
+    earliest-arrival / latest-departure / fastest mix with log-uniform
+    windows on the whole rmat20-32m graph, arriving as a Poisson stream at
+    5,000 q/s while earlier ones are on the device.  Every served result
+    equals the same query run alone; every earliest-arrival result and
+    twelve latest-departure / fastest results also equal the oracle."""
+    from workloads import make_queries, poisson_arrivals
+    from workloads.configs import make_kinds
+    g, G, se = graph("rmat20-32m", 0)
+    count = 240
+    src, ta, tw = make_queries("serve-rmat20", g, count)
+    kinds = make_kinds("serve-rmat20", count)
+    assert (kinds == 0).sum() > 100 and (kinds == 1).sum() > 20 and (kinds == 2).sum() > 20
+    arrive = poisson_arrivals(5_000, count, 105)
+    outs = torch.full((count, g.n), 7, dtype=torch.int32, device="cuda")
+    srv = K.kairos_server_create(G, max_slots=64, queue_capacity=4096)
+    tickets = {}
+    print("case: served mix on rmat20-32m", flush=True)
+    t0 = time.monotonic()
+    for i in range(count):
+        while time.monotonic() - t0 < arrive[i]:
+            time.sleep(0.0001)
+        tickets[K.kairos_server_submit(srv, int(kinds[i]), int(src[i]), int(ta[i]), int(tw[i]), outs[i])] = i
+    done = drain(srv, count, timeout=300.0)
+    st = K.kairos_server_stats_read(srv)
+    K.kairos_server_free(srv)
+    assert st["completed"] == count and st["max_slots_seen"] >= 2, st
+    alone = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    fns = (K.kairos_earliest_arrival, K.kairos_latest_departure, K.kairos_fastest)
+    profiled = 0
+    for tk, c in sorted(done.items()):
+        i = tickets[tk]
+        assert c["status"] == 0 and c["kind"] == kinds[i]
+        mixed = K.as_u32(outs[i])
+        fns[kinds[i]](G, int(src[i]), int(ta[i]), int(tw[i]), alone)
+        assert np.array_equal(mixed, K.as_u32(alone)), (i, kinds[i])
+        if kinds[i] == 0:
+            assert np.array_equal(mixed, O.earliest_arrival(se, src[i], ta[i], tw[i])), i
+        elif profiled < 12:
+            profiled += 1
+            assert np.array_equal(mixed, expected(se, int(kinds[i]), src[i], ta[i], tw[i])), (i, kinds[i])
+    assert profiled == 12

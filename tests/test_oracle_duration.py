@@ -53,6 +53,9 @@ def test_walk_enumeration_pins_traversed_edges_and_duration(case):
     ea = O.earliest_arrival(se, s, ta, tw)
     assert O.traversed_edges(se, ta, tw, ea) == len(used)
     assert list(O.shortest_duration(se, s, ta, tw)) == bsd
+    # "Strictly succeeds" (§2.2): enumeration with departures after arrivals
+    _, bsd_strict = O.walk_facts(n, edges, s, ta, tw, strict=True)
+    assert list(O.shortest_duration(se, s, ta, tw, strict=True)) == bsd_strict
     # the C certificate accepts exactly what the numpy one accepts
     a = t + lam
     assert O.ea_certificate_scan(n, src, dst, t, a, s, ta, tw, ea)
@@ -185,7 +188,10 @@ MUTANTS = [  # (original text, planted text, harmless?)
     ("uint32_t lo = r > t_alpha ? r : t_alpha;", "uint32_t lo = r;", True),
     ("if (t[e] >= lo && a[e] <= t_omega)", "if (t[e] >= t_alpha && a[e] <= t_omega)", False),
     ("d = P[u].dur[k] + lam;", "d = P[u].dur[0] + lam;", False),
-    ("int64_t k = dprofile_last_by(&P[u], t[e]);", "int64_t k = dprofile_last_by(&P[u], t[e] - 1);", False),
+    ("dprofile_last_by(&P[u], strict ? t[e] - 1 : t[e]);", "dprofile_last_by(&P[u], t[e] - 1);", False),
+    # strict succession read as the non-strict one: only the strict pin sees it
+    ("dprofile_last_by(&P[u], strict ? t[e] - 1 : t[e]);", "dprofile_last_by(&P[u], t[e]);", False),
+    ("if (strict && t[e] == 0)\n                continue;", "if (0)\n                continue;", False),
     ("            d = lam;\n", "            d = 0;\n", False),
     ("s_v = P[v].dur[P[v].len - 1];", "s_v = P[v].dur[0];", False),
     ("if (k >= 0 && p->dur[k] <= d)", "if (k >= 0 && p->dur[k] < d)", True),
@@ -204,7 +210,10 @@ def test_planted_mutations_are_caught(tmp_path):
     src_c = open(os.path.join(os.path.dirname(O.__file__), "kairos_oracle.c")).read()
     rng = np.random.default_rng(11)
     # the hand-worked case above first, then drawn ones
-    cases = [(5, [(0, 1, 0, 10), (0, 2, 0, 1), (2, 1, 20, 1), (1, 3, 15, 1), (1, 4, 25, 1)], 0, 0, 100)]
+    cases = [(5, [(0, 1, 0, 10), (0, 2, 0, 1), (2, 1, 20, 1), (1, 3, 15, 1), (1, 4, 25, 1)], 0, 0, 100),
+             # departures at time 0 after an arrival listed first: under strict
+             # succession nothing arrives before 0
+             (3, [(0, 1, 0, 1), (1, 2, 0, 1)], 0, 0, 10)]
     for _ in range(600):
         n = int(rng.integers(1, 7))
         m = int(rng.integers(0, 12))
@@ -222,7 +231,7 @@ def test_planted_mutations_are_caught(tmp_path):
         u64, u32, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
         lib.oracle_traversed_edges.restype = u64
         lib.oracle_traversed_edges.argtypes = [u64, p, p, p, u32, u32, p]
-        lib.oracle_shortest_duration.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, p]
+        lib.oracle_shortest_duration.argtypes = [u64, p, p, p, p, u32, u32, u32, u32, ctypes.c_int, p]
         caught = False
         for (n, edges, s, ta, tw) in cases:
             se = O.sort_by_departure(n, *arrays(edges))
@@ -231,8 +240,12 @@ def test_planted_mutations_are_caught(tmp_path):
             cnt = lib.oracle_traversed_edges(se.m, O._ptr(se.src), O._ptr(se.t), O._ptr(se.a), ta, tw, O._ptr(ea))
             sd = np.empty(n, np.uint32)
             lib.oracle_shortest_duration(se.m, O._ptr(se.src), O._ptr(se.dst), O._ptr(se.t), O._ptr(se.a),
-                                         n, s, ta, tw, O._ptr(sd))
-            if cnt != len(used) or list(sd) != bsd:
+                                         n, s, ta, tw, 0, O._ptr(sd))
+            _, bsd_strict = O.walk_facts(n, edges, s, ta, tw, strict=True)
+            sds = np.empty(n, np.uint32)
+            lib.oracle_shortest_duration(se.m, O._ptr(se.src), O._ptr(se.dst), O._ptr(se.t), O._ptr(se.a),
+                                         n, s, ta, tw, 1, O._ptr(sds))
+            if cnt != len(used) or list(sd) != bsd or list(sds) != bsd_strict:
                 caught = True
                 break
         assert caught != harmless, (old, new, caught)

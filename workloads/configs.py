@@ -21,6 +21,9 @@ edges" window sweeps (§6.2, §6.5) with log-uniform window widths.
                   EA/LD/F, log-uniform windows.
   rmat24-512m     R-MAT scale 24, 2^29 edges, otherwise like rmat20-32m.
 
+``bench_mode`` is the form the benchmark times by default: one query per
+call for the single-source workloads, one batched call for the batch.
+
 ``scale_shift`` shrinks an R-MAT recipe by that many powers of two in both
 vertices and edges (same edge factor), for tests that must finish quickly.
 """
@@ -34,18 +37,21 @@ from .gen import (TMAX, Graph, bursty_pair_graph, first_half_windows, log_unifor
 CONFIGS = {
     "uniform-10k": dict(kind="uniform", n=10_000, m=100_000, seed=1, t_lo=0, t_hi=99_999,
                         lam_lo=1, lam_hi=10, queries=16, qseed=101, window="fixed",
-                        t_alpha=0, t_omega=99_999),
+                        t_alpha=0, t_omega=99_999, bench_mode="single"),
     "rmat20-32m": dict(kind="rmat", scale=20, m=1 << 25, seed=2, t_lo=0, t_hi=(1 << 30) - 1,
-                       lam_lo=1, lam_hi=1, queries=64, qseed=102, window="first_half"),
+                       lam_lo=1, lam_hi=1, queries=64, qseed=102, window="first_half",
+                       bench_mode="single"),
     "bursty22-1b": dict(kind="bursty", scale=22, pairs=12 << 22, seed=3, lam_lo=1, lam_hi=100,
-                        queries=32, qseed=103, window="first_half"),
+                        queries=32, qseed=103, window="first_half", bench_mode="single"),
     "rmat22-256m": dict(kind="rmat", scale=22, m=1 << 28, seed=4, t_lo=0, t_hi=TMAX - 10,
-                        lam_lo=1, lam_hi=10, queries=256, qseed=104, window="log_uniform"),
+                        lam_lo=1, lam_hi=10, queries=256, qseed=104, window="log_uniform",
+                        bench_mode="batch"),
     "serve-rmat20": dict(kind="rmat", scale=20, m=1 << 25, seed=2, t_lo=0, t_hi=(1 << 30) - 1,
                          lam_lo=1, lam_hi=1, queries=20_000, qseed=105, window="log_uniform",
                          rates=[1_000, 2_000, 5_000, 10_000, 20_000, 50_000], warmup=1_000),
     "rmat24-512m": dict(kind="rmat", scale=24, m=1 << 29, seed=24, t_lo=0, t_hi=(1 << 30) - 1,
-                        lam_lo=1, lam_hi=1, queries=64, qseed=124, window="first_half"),
+                        lam_lo=1, lam_hi=1, queries=64, qseed=124, window="first_half",
+                        bench_mode="single"),
 }
 
 
