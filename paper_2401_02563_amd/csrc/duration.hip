@@ -113,7 +113,7 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
                                                   const uint32_t *__restrict__ off_in,
                                                   const uint32_t *__restrict__ a_in,
                                                   const uint2 *__restrict__ st_in, uint32_t n_live,
-                                                  uint32_t *__restrict__ o2i)
+                                                  uint32_t *__restrict__ o2i, uint32_t *err)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (SDT / 64);
@@ -134,7 +134,11 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
                 else
                     hi = mid;
             }
-            o2i[f] = lo;
+            // the same edge is in the in-index; anything else is an index
+            // fault, reported instead of used
+            const bool found = lo < off_in[va.x + 1] && a_in[lo] == va.y && st_in[lo].y == t && st_in[lo].x == u;
+            if (!found) atomicOr(err, 1u);
+            o2i[f] = found ? lo : off_in[va.x];
         }
     }
 }
@@ -443,15 +447,26 @@ int ensure_o2i(kairos_graph *g, hipStream_t st)
     std::lock_guard<std::mutex> lk(g->sd_mu);
     if (g->o2i) return KAIROS_OK;
     uint32_t *o2i = (uint32_t *)dev_alloc(std::max<uint64_t>(g->m, 1) * 4, nullptr);
-    if (!o2i) return KAIROS_ERR_NOMEM;
+    uint32_t *err = (uint32_t *)dev_alloc(4, nullptr);
+    if (!o2i || !err) {
+        dev_free(o2i);
+        dev_free(err);
+        return KAIROS_ERR_NOMEM;
+    }
     if (g->m > 0) {
+        uint32_t h_err = 0;
+        hipLaunchKernelGGL(sd_fill_kernel, dim3(1), dim3(SDT), 0, st, err, (uint64_t)1, 0u);
         hipLaunchKernelGGL(o2i_kernel, dim3(grid_for(g->n_live, SDT / 64, (uint32_t)g->num_cus * 16)), dim3(SDT), 0,
-                           st, g->off_out, g->t_out, g->da_out, g->off_in, g->a_in, g->st_in, g->n_live, o2i);
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+                           st, g->off_out, g->t_out, g->da_out, g->off_in, g->a_in, g->st_in, g->n_live, o2i, err);
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st) !=
+                                                    hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess || h_err != 0) {
             dev_free(o2i);
+            dev_free(err);
             return KAIROS_ERR_DEVICE;
         }
     }
+    dev_free(err);
     g->o2i = o2i;
     g->o2i_bytes = std::max<uint64_t>(g->m, 1) * 4;
     return KAIROS_OK;

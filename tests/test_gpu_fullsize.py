@@ -7,7 +7,8 @@
   benchmark times one query per call): earliest arrival of five of its 32
   queries checked by the exact EA certificate, two of them also against the
   oracle's one-pass scan with their traversed-edge counts, and latest
-  departure / fastest of one query against the oracle's profile scan.
+  departure / fastest / shortest duration of one query against the
+  oracle's profile scans.
 * rmat22-256m (256-query batch) and rmat24-512m (single queries): eight rows
   each by the EA certificate, two of them also against the oracle's scan.
 
@@ -108,8 +109,8 @@ def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
     benchmark times (one query per call, or the whole batch in one call):
     `cert_rows` rows by the exact certificate, the first and the middle of
     them (`scan_rows`) also element by element against the oracle's scan
-    with their traversed-edge counts; latest departure / fastest of
-    `sweep_rows` queries against the oracle's profile scan."""
+    with their traversed-edge counts; latest departure / fastest / shortest
+    duration of `sweep_rows` queries against the oracle's profile scans."""
     _C.clear()
     print(f"case: generating {name}", flush=True)
     g = make_graph(name)
@@ -143,7 +144,9 @@ def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
         K.kairos_latest_departure(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
         ld = K.as_u32(one)
         K.kairos_fastest(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
-        sweeps[q] = (ld, K.as_u32(one))
+        fa = K.as_u32(one)
+        K.kairos_shortest_duration(G, int(srcs[q]), int(ta[q]), int(tw[q]), one)
+        sweeps[q] = (ld, fa, K.as_u32(one))
     del one
     G.free()
     torch.cuda.empty_cache()
@@ -160,8 +163,10 @@ def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
         want = O.earliest_arrival(se, srcs[q], ta[q], tw[q])
         assert np.array_equal(got[q], want), q
         assert counts[q] == O.traversed_edges(se, ta[q], tw[q], want), q
-    for q, (ld, fa) in sweeps.items():
+    for q, (ld, fa, sd) in sweeps.items():
         print(f"case: {name} oracle profile of query {q}", flush=True)
         pea, pld, pf = O.profile(se, srcs[q], ta[q], tw[q])
         assert np.array_equal(ld, pld), q
         assert np.array_equal(fa, pf), q
+        print(f"case: {name} oracle shortest duration of query {q}", flush=True)
+        assert np.array_equal(sd, O.shortest_duration(se, srcs[q], ta[q], tw[q])), q
