@@ -217,7 +217,11 @@ int kairos_traversed_edges(kairos_graph *g, uint32_t t_alpha, uint32_t t_omega,
  * parallel grain; §5.1, §6.1) by experiment; kairos_autotune measures them
  * on a sample of the caller's own queries. */
 typedef struct kairos_tuning {
-    uint32_t block;          /* threads per workgroup of the push kernel: 256 or 512 */
+    uint32_t block;          /* threads per workgroup of the push and chunk kernels
+                                of single queries, sweeps and query-major
+                                batches: 256 or 512 (512 launches half as many
+                                blocks); the lane-dense batch, one-workgroup
+                                and persistent kernels keep 256               */
     uint32_t chunk;          /* edges per chunk when a long adjacency is split     */
     uint32_t split;          /* adjacency ranges at least this long are split      */
     uint32_t pull_alpha;     /* pull when frontier out-edges > m / pull_alpha;
@@ -271,9 +275,17 @@ int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);
  * no query, batch or server of g is in flight; results never depend on it. */
 int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in);
 
-/* Grid search over the tuning space on q sample queries (host arrays, as in
- * the batch call); keeps the fastest setting in g and copies it to *best
- * (may be NULL).  Results never change; only time does. */
+/* Coordinate descent over the tuning space on q sample queries (host
+ * arrays, as in the batch call): one query tunes the one-query path, more
+ * tune the batch they form; the sweep group width is then tuned on
+ * latest-departure queries from the first two sample sources.  Keeps the
+ * fastest setting in g and copies it to *best (may be NULL).  Results never
+ * change; only time does.  The sample should be held out from the queries
+ * that will be timed.  When the environment variable KAIROS_TUNING_CACHE
+ * names a file, settings are stored there per device and index shape
+ * (architecture, compute units, n, m, vertices with out-edges, largest
+ * out-degree, repeated heads, largest departure, one query or a batch) and a
+ * stored setting is taken without measuring. */
 int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
                     const uint32_t *t_omega, kairos_tuning *best);
 

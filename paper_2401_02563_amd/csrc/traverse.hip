@@ -305,18 +305,18 @@ using TStage = Stage<SCAP>;
 // part of its adjacency; short claims are relaxed by the block with a
 // prefix-sum load balance, claims of at least `split` edges are cut into
 // chunks for part 2 (one chunk-list reservation per block and pass).
-template <bool SWEEP>
+template <bool SWEEP, int B>
 __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage &S, unsigned long long &n_edges,
                                            unsigned long long &n_relax, unsigned long long &n_items)
 {
-    __shared__ uint32_t s_pref[TB + 1];
-    __shared__ uint32_t s_lo[TB];
-    __shared__ uint32_t s_q[TB];
-    __shared__ uint32_t s_tw[TB];
-    __shared__ uint32_t s_sd[TB];
-    __shared__ uint2 s_fp[TB];
-    __shared__ uint32_t s_wsum[TB / 64];
-    __shared__ uint32_t s_csum[TB / 64];
+    __shared__ uint32_t s_pref[B + 1];
+    __shared__ uint32_t s_lo[B];
+    __shared__ uint32_t s_q[B];
+    __shared__ uint32_t s_tw[B];
+    __shared__ uint32_t s_sd[B];
+    __shared__ uint2 s_fp[B];
+    __shared__ uint32_t s_wsum[B / 64];
+    __shared__ uint32_t s_csum[B / 64];
     __shared__ uint32_t s_cb;
 
     const int tid = threadIdx.x;
@@ -335,7 +335,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     // in id order and expand the members (stamped by the previous round), so
     // offsets, claim words and adjacency ranges are read in address order
     const uint32_t span = A.dense ? A.n : F;
-    for (uint32_t base = blockIdx.x * TB; base < span; base += gridDim.x * TB) {
+    for (uint32_t base = blockIdx.x * B; base < span; base += gridDim.x * B) {
         const uint32_t i = base + tid;
         uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, nch = 0;
         uint2 fpq = make_uint2(0u, 0u);
@@ -365,7 +365,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             if (len >= A.split) nch = (len + A.chunk - 1) / A.chunk;
         }
         // exclusive prefix sums over the block of the short claim lengths
-        // (so the block total stays below TB * split) and of the chunk counts
+        // (so the block total stays below B * split) and of the chunk counts
         const uint32_t sl = nch ? 0u : len;
         uint32_t x = sl, c = nch;
         for (int o = 1; o < 64; o <<= 1) {
@@ -387,7 +387,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
         s_fp[tid] = fpq;
         __syncthreads();
         uint32_t woff = 0, total = 0, coff = 0, ctotal = 0;
-        for (int w2 = 0; w2 < TB / 64; ++w2) {
+        for (int w2 = 0; w2 < B / 64; ++w2) {
             if (w2 < w) {
                 woff += s_wsum[w2];
                 coff += s_csum[w2];
@@ -397,7 +397,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
         }
         s_pref[tid] = woff + x - sl;
         if (tid == 0) {
-            s_pref[TB] = total;
+            s_pref[B] = total;
             if (ctotal) s_cb = atomicAdd(chunk_cnt, ctotal);
         }
         __syncthreads();
@@ -414,14 +414,14 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             ser_len = len - covered;
         }
         if (tid == 0) n_edges += total;
-        for (uint32_t j0 = 0; j0 < total; j0 += TB * UNR) {
+        for (uint32_t j0 = 0; j0 < total; j0 += B * UNR) {
             EdgeGroup G;
 #pragma unroll
             for (int k = 0; k < UNR; ++k) {
-                const uint32_t j = j0 + k * TB + tid;
+                const uint32_t j = j0 + k * B + tid;
                 G.ok[k] = j < total;
                 // owner: the last item whose prefix is <= j
-                int lo_k = 0, hi_k = TB;
+                int lo_k = 0, hi_k = B;
                 while (hi_k - lo_k > 1) {
                     const int mid = (lo_k + hi_k) >> 1;
                     if (s_pref[mid] <= j)
@@ -472,22 +472,22 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     }
 }
 
-template <bool SWEEP>
-__global__ __launch_bounds__(TB) void push_kernel(TravArgs A)
+template <bool SWEEP, int B>
+__global__ __launch_bounds__(B) void push_kernel(TravArgs A)
 {
-    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    __shared__ uint32_t s_stage[B / 64][SCAP];
     TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
-    push_phase<SWEEP>(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
-    stage_flush_block<SCAP, TB / 64>(S);
+    push_phase<SWEEP, B>(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
+    stage_flush_block<SCAP, B / 64>(S);
     unsigned long long v[4] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges};
     const int slot[4] = {ST_RELAX, ST_ATTEMPTS, ST_ITEMS, ST_EDGES};
-    block_stats<TB / 64>(A.stats, v, slot);
+    block_stats<B / 64>(A.stats, v, slot);
 }
 
 // Push round, part 2: every wave takes whole chunks (grid-stride over the
 // chunk list) and relaxes their edges UNR per lane at a time.
-template <bool SWEEP>
+template <bool SWEEP, int B>
 __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsigned long long &n_edges,
                                             unsigned long long &n_relax)
 {
@@ -495,8 +495,8 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
     const uint32_t C = min(A.cnt[CNT_CHUNK + r3], A.chunk_cap);
     uint32_t *vol_cnt = &A.cnt[CNT_PULLVOL + (A.round + 1u) % 3u];
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t waves = gridDim.x * (TB / 64);
-    for (uint32_t c = blockIdx.x * (TB / 64) + (threadIdx.x >> 6); c < C; c += waves) {
+    const uint32_t waves = gridDim.x * (B / 64);
+    for (uint32_t c = blockIdx.x * (B / 64) + (threadIdx.x >> 6); c < C; c += waves) {
         const uint4 ch = A.chunks[c];
         const uint4 p = A.qp[ch.x];
         const uint2 fpq = A.fpar[ch.x];
@@ -524,17 +524,17 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
     }
 }
 
-template <bool SWEEP>
-__global__ __launch_bounds__(TB) void chunk_kernel(TravArgs A)
+template <bool SWEEP, int B>
+__global__ __launch_bounds__(B) void chunk_kernel(TravArgs A)
 {
-    __shared__ uint32_t s_stage[TB / 64][SCAP];
+    __shared__ uint32_t s_stage[B / 64][SCAP];
     TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0;
-    chunk_phase<SWEEP>(A, S, n_edges, n_relax);
-    stage_flush_block<SCAP, TB / 64>(S);
+    chunk_phase<SWEEP, B>(A, S, n_edges, n_relax);
+    stage_flush_block<SCAP, B / 64>(S);
     unsigned long long v[3] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_edges};
     const int slot[3] = {ST_RELAX, ST_ATTEMPTS, ST_CHUNK_EDGES};
-    block_stats<TB / 64>(A.stats, v, slot);
+    block_stats<B / 64>(A.stats, v, slot);
 }
 
 // Rounds of one query set in a single cooperative launch: push phase, grid
@@ -575,10 +575,10 @@ __global__ __launch_bounds__(TB) void persist_kernel(TravArgs A, uint32_t which0
         B.next = odd ? q0 : q1;
         B.dense = (A.nq == 1 && dense_div && (uint64_t)F * dense_div >= A.n) ? 1u : 0u;
         TStage S{s_stage[threadIdx.x >> 6], 0u, B.next, &A.cnt[CNT_FRONT + (r + 1u) % 3u]};
-        push_phase<SWEEP>(B, F, S, n_edges, n_relax, n_items);
+        push_phase<SWEEP, TB>(B, F, S, n_edges, n_relax, n_items);
         stage_flush_block<SCAP, TB / 64>(S);
         grid_barrier(bar, spin_limit);
-        chunk_phase<SWEEP>(B, S, n_cedges, n_relax);
+        chunk_phase<SWEEP, TB>(B, S, n_cedges, n_relax);
         stage_flush_block<SCAP, TB / 64>(S);
         grid_barrier(bar, spin_limit);
         ++r;
@@ -1316,16 +1316,27 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
                 A.dense = (A.nq == 1 && tu.dense_frontier && k == 0 && !levels &&
                            (uint64_t)F * tu.dense_frontier >= g->n) ? 1u : 0u;
                 A.front_stamp = A.stamp_val - 1u;
-                const int pg = A.dense ? grid_cap(g->n, TB, spec_grid)
-                                       : (k == 0 ? grid_cap(F, TB, spec_grid) : spec_grid);
+                // workgroup size from the tuning: 512 threads take half as
+                // many blocks for the same number of threads
+                const bool wide = tu.block == 512;
+                const int bs = wide ? 512 : TB;
+                const int sg = wide ? std::max(1, spec_grid / 2) : spec_grid;
+                const int cg = wide ? std::max(1, chunk_grid / 2) : chunk_grid;
+                const int pg = A.dense ? grid_cap(g->n, bs, sg) : (k == 0 ? grid_cap(F, bs, sg) : sg);
                 if (levels)
                     hipLaunchKernelGGL(snapshot_kernel, dim3(k == 0 ? grid_cap(F, 256, spec_grid) : chunk_grid),
                                        dim3(256), 0, st, A);
                 prof_begin(g, st, &ev);
-                hipLaunchKernelGGL(push_kernel<SWEEP>, dim3(pg), dim3(TB), 0, st, A);
+                if (wide)
+                    hipLaunchKernelGGL((push_kernel<SWEEP, 512>), dim3(pg), dim3(512), 0, st, A);
+                else
+                    hipLaunchKernelGGL((push_kernel<SWEEP, TB>), dim3(pg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_PUSH, ev);
                 prof_begin(g, st, &ev);
-                hipLaunchKernelGGL(chunk_kernel<SWEEP>, dim3(chunk_grid), dim3(TB), 0, st, A);
+                if (wide)
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, 512>), dim3(cg), dim3(512), 0, st, A);
+                else
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, TB>), dim3(cg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_CHUNK, ev);
             }
             KAIROS_HIP(hipGetLastError());
@@ -2110,10 +2121,10 @@ int multi_push_round(kairos_graph *g, MultiState *ms)
     A.stamp_val = ms->stamp_next++;
     hipEvent_t ev;
     prof_begin(g, ms->stream, &ev);
-    hipLaunchKernelGGL(push_kernel<true>, dim3(std::max(1, g->num_cus * 8)), dim3(TB), 0, ms->stream, A);
+    hipLaunchKernelGGL((push_kernel<true, TB>), dim3(std::max(1, g->num_cus * 8)), dim3(TB), 0, ms->stream, A);
     prof_end(g, ms->stream, KAIROS_K_PUSH, ev);
     prof_begin(g, ms->stream, &ev);
-    hipLaunchKernelGGL(chunk_kernel<true>, dim3(std::max(1, g->num_cus * 4)), dim3(TB), 0, ms->stream, A);
+    hipLaunchKernelGGL((chunk_kernel<true, TB>), dim3(std::max(1, g->num_cus * 4)), dim3(TB), 0, ms->stream, A);
     prof_end(g, ms->stream, KAIROS_K_CHUNK, ev);
     KAIROS_HIP(hipGetLastError());
     ms->round += 1;

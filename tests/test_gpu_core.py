@@ -3,6 +3,7 @@ CPU oracle, through the C interface.  Integer results: bit-exact."""
 import json
 import glob
 import os
+import time
 
 import numpy as np
 import pytest
@@ -135,7 +136,10 @@ def test_ea_skewed(which):
                                     dict(arrival_filter=2, tail_limit=0, dense_frontier=4),
                                     dict(single_persistent=0), dict(run_dedupe=1),
                                     dict(single_persistent=1, tail_limit=0),
-                                    dict(single_persistent=1, tail_limit=0, dense_frontier=4)])
+                                    dict(single_persistent=1, tail_limit=0, dense_frontier=4),
+                                    dict(block=512), dict(block=512, tail_limit=0),
+                                    dict(block=512, tail_limit=0, split=64, chunk=64),
+                                    dict(block=512, tail_limit=0, dense_frontier=4, pull_alpha=8, pull_beta=24)])
 def test_ea_independent_of_tuning(tuning):
     """Results are unique, so every launch configuration must agree bit for bit."""
     g, G, se = rmat16()
@@ -427,13 +431,33 @@ def test_chunk_list_overflow_paths():
         del os.environ["KAIROS_TEST_CHUNK_CAP"]
 
 
-def test_autotune_keeps_results():
+def test_autotune_keeps_results(tmp_path):
+    """The tuner keeps results exact, stores its choice under the graph's key
+    in the cache file, and takes it from there the next time without
+    measuring; the tuning sample is held out from the timed queries."""
     g, G, se = rmat16()
     srcs, ta, tw = make_queries("rmat20-32m", g, count=8)
+    hs, ha, hw = make_queries("rmat20-32m", g, count=8, held_out=True)
+    assert not set(zip(srcs.tolist(), ta.tolist())) & set(zip(hs.tolist(), ha.tolist()))
     old = K.kairos_get_tuning(G)
+    cache = tmp_path / "tuning.txt"
+    os.environ["KAIROS_TUNING_CACHE"] = str(cache)
     try:
-        best = K.kairos_autotune(G, srcs, ta, tw)
+        best = K.kairos_autotune(G, hs, ha, hw)
         assert best == K.kairos_get_tuning(G)
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].split()[0].endswith("/batch")
+        assert [int(x) for x in lines[0].split()[1:]] == list(best.values())
+        K.kairos_set_tuning(G, **old)
+        t0 = time.perf_counter()
+        again = K.kairos_autotune(G, hs, ha, hw)
+        assert again == best and time.perf_counter() - t0 < 0.5
+        one = K.kairos_autotune(G, hs[:1], ha[:1], hw[:1])  # another key: one-query form
+        assert len(cache.read_text().splitlines()) == 2
+        K.kairos_set_tuning(G, **one)
+        assert np.array_equal(ea_gpu(G, int(srcs[1]), int(ta[1]), int(tw[1])),
+                              O.earliest_arrival(se, srcs[1], ta[1], tw[1]))
+        K.kairos_set_tuning(G, **best)
         out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
         K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
         rows = K.as_u32(out).reshape(len(srcs), g.n)
@@ -442,6 +466,7 @@ def test_autotune_keeps_results():
         assert np.array_equal(ea_gpu(G, int(srcs[0]), int(ta[0]), int(tw[0])),
                               O.earliest_arrival(se, srcs[0], ta[0], tw[0]))
     finally:
+        del os.environ["KAIROS_TUNING_CACHE"]
         K.kairos_set_tuning(G, **old)
 
 

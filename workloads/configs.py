@@ -78,11 +78,14 @@ def _span(g: Graph, c: dict):
     return int(g.t.min()), int(g.t.max())
 
 
-def make_queries(name: str, g: Graph, count: int | None = None):
-    """Return (sources, t_alpha, t_omega) as uint32 arrays."""
+def make_queries(name: str, g: Graph, count: int | None = None, held_out: bool = False):
+    """Return (sources, t_alpha, t_omega) as uint32 arrays.
+
+    ``held_out``: queries of the same recipe drawn from another seed, for
+    tuning on a sample that is not the one timed."""
     c = CONFIGS[name]
     k = c["queries"] if count is None else count
-    ss = np.random.SeedSequence(c["qseed"]).spawn(2)
+    ss = np.random.SeedSequence([c["qseed"], 1] if held_out else c["qseed"]).spawn(2)
     src = sample_sources(g, k, int(ss[0].generate_state(1)[0]))
     lo, hi = _span(g, c)
     wseed = int(ss[1].generate_state(1)[0])
