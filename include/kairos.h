@@ -51,7 +51,9 @@ typedef enum kairos_status {
                                t_alpha > t_omega, t_omega > TMAX, m >= 2^32 */
     KAIROS_ERR_NOMEM = 3,   /* device or host allocation failed             */
     KAIROS_ERR_DEVICE = 4,  /* a HIP call or kernel failed                  */
-    KAIROS_ERR_BUSY = 5     /* a server queue is full                       */
+    KAIROS_ERR_BUSY = 5,    /* a server queue is full                       */
+    KAIROS_ERR_SCRATCH = 6  /* the graph needs more state than the fixed
+                               scratch of kairos_earliest_arrival_noalloc  */
 } kairos_status;
 
 typedef struct kairos_graph kairos_graph;
@@ -181,6 +183,27 @@ int kairos_query(kairos_graph *g, int kind, uint32_t flags, uint32_t src, uint32
  *   NOMEM, DEVICE. */
 int kairos_latest_departure_to(kairos_graph *g, uint32_t target, uint32_t t_alpha, uint32_t t_omega,
                                uint32_t *out);
+
+/* Earliest arrival that allocates nothing: for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, result and errors as
+ * kairos_earliest_arrival, run with the same kernels; the query's state
+ * lives in one fixed device array of KAIROS_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every device it runs on until the process exits.  The
+ * call makes no hipMalloc / hipFree and no other allocation; it is not
+ * profiled (kairos_profile_enable does not cover it).
+ *   Limit: about 22 bytes per vertex plus a fixed chunk list must fit the
+ *   array (graphs up to roughly 11 million vertices); a larger graph gets
+ *   KAIROS_ERR_SCRATCH and nothing is written.
+ *   Calls on one device share the array: the library serialises them with a
+ *   lock (overlapping calls would race on it), and every word a query reads
+ *   before writing is cleared at the start of each call.
+ *   The graph must live on the current device (else INVALID).  Work runs on
+ *   the graph's stream, or the null stream for a graph built without one;
+ *   the call returns when out is complete. */
+#define KAIROS_NOALLOC_SCRATCH_BYTES (256u << 20)
+int kairos_earliest_arrival_noalloc(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
+                                    uint32_t *out);
 
 /* Shortest duration (Table 4's "S. Duration" row, on which §6.1 builds
  * temporal betweenness): out[v] = the least total duration, the sum of

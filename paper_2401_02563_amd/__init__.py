@@ -17,7 +17,7 @@ import torch
 __all__ = [
     "KairosError", "Graph", "INF", "TMAX", "lib_path",
     "kairos_graph_build", "kairos_graph_free", "kairos_graph_stats", "kairos_graph_index",
-    "kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_shortest_duration",
+    "kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_shortest_duration", "kairos_earliest_arrival_noalloc",
     "kairos_earliest_arrival_batch", "kairos_traversed_edges",
     "kairos_get_tuning", "kairos_set_tuning", "kairos_autotune",
     "kairos_profile_enable", "kairos_profile_read",
@@ -85,7 +85,7 @@ _sig("kairos_graph_free", None, _p)
 _sig("kairos_graph_stats", _i32, _p, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64))
 _sig("kairos_graph_index", _i32, _p, ctypes.POINTER(kairos_index_view))
 for _n in ("kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_temporal_bfs",
-           "kairos_latest_departure_to", "kairos_shortest_duration"):
+           "kairos_latest_departure_to", "kairos_shortest_duration", "kairos_earliest_arrival_noalloc"):
     _sig(_n, _i32, _p, _u32, _u32, _u32, _p)
 _sig("kairos_earliest_arrival_path", _i32, _p, _u32, _u32, _u32, _p, _p, _p)
 _sig("kairos_query", _i32, _p, _i32, _u32, _u32, _u32, _u32, _p)
@@ -244,6 +244,10 @@ def kairos_temporal_bfs(g: Graph, src: int, t_alpha: int, t_omega: int, out: tor
 
 def kairos_shortest_duration(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
     return _single("kairos_shortest_duration", g, src, t_alpha, t_omega, out)
+
+
+def kairos_earliest_arrival_noalloc(g: Graph, src: int, t_alpha: int, t_omega: int, out: torch.Tensor):
+    return _single("kairos_earliest_arrival_noalloc", g, src, t_alpha, t_omega, out)
 
 
 def kairos_query(g: Graph, kind: int, src: int, t_alpha: int, t_omega: int, out: torch.Tensor,

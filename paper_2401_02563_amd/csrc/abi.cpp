@@ -50,6 +50,7 @@ const char *kairos_status_string(int status)
     case KAIROS_ERR_NOMEM: return "out of memory";
     case KAIROS_ERR_DEVICE: return "device error";
     case KAIROS_ERR_BUSY: return "queue full";
+    case KAIROS_ERR_SCRATCH: return "graph too large for the fixed scratch array";
     default: return "unknown status";
     }
 }

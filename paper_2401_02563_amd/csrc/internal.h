@@ -57,6 +57,12 @@ struct Slot {
     uint32_t *bar = nullptr;     // grid barrier words of persistent launches
     uint32_t *h_pin = nullptr;   // pinned host mirror for counter read-back
     uint4 *h_q = nullptr;        // qcap: pinned staging of query parameters (read by the init kernel)
+    // A slot over caller-provided memory (the allocation-free entry point):
+    // h_pin is ordinary host memory, so query parameters are copied to
+    // d_stage (device, qcap entries) instead of being read by the kernel
+    // from the host, and the slot's launches are never profiled.
+    uint4 *d_stage = nullptr;
+    bool fixed = false;
     uint32_t stamp_next = 2;     // next round stamp value (0 = never stamped, 1 = spare)
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -239,7 +245,15 @@ int multi_group_warm(kairos_graph *g, MultiState *ms, uint32_t lead, uint32_t wi
 int multi_finalize(kairos_graph *g, MultiState *ms, uint32_t q, int kind, uint32_t src, uint32_t tw,
                    uint32_t *out);
 
+// A single-query slot laid out in `bytes` of device memory at `base`
+// (256-byte aligned), with host read-back through `host_words` (>= 256
+// words of ordinary host memory).  Returns the bytes it needs, and fills
+// *s only if they fit.
+uint64_t slot_layout(const kairos_graph *g, uint64_t chunk_cap, unsigned char *base, uint64_t bytes,
+                     uint32_t *host_words, Slot *s);
+
 // profiling (traverse.hip)
+void set_unprofiled(bool on);  // this thread's launches skip profiling while on
 void prof_begin(kairos_graph *g, hipStream_t st, hipEvent_t *ev0);
 void prof_end(kairos_graph *g, hipStream_t st, int cls, hipEvent_t ev0);
 void prof_add_stats(kairos_graph *g, const unsigned long long *h);

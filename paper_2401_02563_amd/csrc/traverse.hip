@@ -1147,7 +1147,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
     A.cnt = s->cnt;
     A.chunks = s->chunks;
     A.chunk_cap = (uint32_t)std::min<uint64_t>(s->chunk_cap, 0xFFFFFFF0u);
-    A.stats = g->prof.on ? s->stats : nullptr;
+    A.stats = g->prof.on && !s->fixed ? s->stats : nullptr;
     A.split = std::max<uint32_t>(g->tuning.split, 1);
     A.chunk = std::max<uint32_t>(g->tuning.chunk, 1);
     A.nq = nq;
@@ -1426,9 +1426,50 @@ int slot_alloc(kairos_graph *g, uint32_t qcap, Slot **out)
     return KAIROS_OK;
 }
 
+}  // namespace
+
+uint64_t slot_layout(const kairos_graph *g, uint64_t chunk_cap, unsigned char *base, uint64_t bytes,
+                     uint32_t *host_words, Slot *s)
+{
+    const uint64_t n = g->n;
+    uint64_t off = 0;
+    auto take = [&](uint64_t b) {
+        const uint64_t at = off;
+        off += (b + 255) / 256 * 256;
+        return at;
+    };
+    const uint64_t o_av = take(n * 8), o_done = take(n * 4), o_q0 = take(n * 4), o_q1 = take(n * 4);
+    const uint64_t o_filt = take(filt_stride(g->n)), o_fpar = take(sizeof(uint2)), o_qp = take(sizeof(uint4));
+    const uint64_t o_stage = take(sizeof(uint4)), o_cnt = take(CNT_WORDS * 4), o_bar = take(BAR_WORDS * 4);
+    const uint64_t o_stats = take(ST_TOTAL_WORDS * 8), o_chunks = take(chunk_cap * sizeof(uint4));
+    if (off > bytes || !s) return off;
+    *s = Slot{};
+    s->qcap = 1;
+    s->n = g->n;
+    s->av = (unsigned long long *)(base + o_av);
+    s->done = (uint32_t *)(base + o_done);
+    s->queue[0] = (uint32_t *)(base + o_q0);
+    s->queue[1] = (uint32_t *)(base + o_q1);
+    s->filt = base + o_filt;
+    s->fpar = (uint2 *)(base + o_fpar);
+    s->qp = (uint4 *)(base + o_qp);
+    s->d_stage = (uint4 *)(base + o_stage);
+    s->cnt = (uint32_t *)(base + o_cnt);
+    s->bar = (uint32_t *)(base + o_bar);
+    s->stats = (unsigned long long *)(base + o_stats);
+    s->chunks = (uint4 *)(base + o_chunks);
+    s->chunk_cap = chunk_cap;
+    s->h_pin = host_words;
+    s->fixed = true;
+    s->stream = g->stream;  // the caller's stream, or the null stream
+    return off;
+}
+
+namespace {
+
 int read_stats(kairos_graph *g, Slot *s)
 {
-    if (!g->prof.on) return KAIROS_OK;
+    if (!g->prof.on || s->fixed) return KAIROS_OK;
     std::vector<unsigned long long> raw((size_t)ST_SHARDS * ST_WORDS);
     unsigned long long h[ST_WORDS];
     KAIROS_HIP(hipMemcpyAsync(raw.data(), s->stats, raw.size() * 8, hipMemcpyDeviceToHost, s->stream));
@@ -1442,10 +1483,16 @@ int read_stats(kairos_graph *g, Slot *s)
 }  // namespace
 
 // ------------------------------------------------------------ profiling --
+// Launches of the allocation-free entry point are never profiled (a
+// profiled launch creates events); it clears this flag on its thread.
+thread_local bool tl_unprofiled = false;
+
+void set_unprofiled(bool on) { tl_unprofiled = on; }
+
 void prof_begin(kairos_graph *g, hipStream_t st, hipEvent_t *ev0)
 {
     *ev0 = nullptr;
-    if (!g->prof.on) return;
+    if (!g->prof.on || tl_unprofiled) return;
     std::lock_guard<std::mutex> lk(g->prof.mu);
     hipEvent_t e = nullptr;
     if (!g->prof.free_events.empty()) {
@@ -1556,7 +1603,13 @@ static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq
     // slot's pinned staging array (qcap entries, allocated with the slot)
     if (nq > s->qcap) return KAIROS_ERR_INVALID;
     uint4 *dq = nullptr;
-    if (nq * sizeof(uint4) <= 128) {
+    if (s->fixed) {
+        // ordinary host memory: copy to the device first (the source may
+        // be reused as soon as the copy has finished)
+        KAIROS_HIP(hipMemcpyAsync(s->d_stage, hqp, nq * sizeof(uint4), hipMemcpyHostToDevice, st));
+        KAIROS_HIP(hipStreamSynchronize(st));
+        dq = s->d_stage;
+    } else if (nq * sizeof(uint4) <= 128) {
         std::memcpy(s->h_pin + 32, hqp, nq * sizeof(uint4));
         dq = (uint4 *)(s->h_pin + 32);
     } else {
@@ -1569,7 +1622,7 @@ static int start_queries(kairos_graph *g, Slot *s, const uint4 *hqp, uint32_t nq
                        from_w ? 1u : 0u);
     prof_end(g, st, KAIROS_K_INIT, ev);
     hipError_t e1 = hipGetLastError();
-    if (nq * sizeof(uint4) > 128 && e1 == hipSuccess) {
+    if (!s->fixed && nq * sizeof(uint4) > 128 && e1 == hipSuccess) {
         // the staging array is rewritten by the next start on this slot
         e1 = hipStreamSynchronize(st);
     }
