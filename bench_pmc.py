@@ -46,7 +46,8 @@ def kernel_source_hash() -> str:
 
 
 def short_name(n: str) -> str:
-    m = re.search(r"::(\w+)(<\w+>)?\(", n.replace("(anonymous namespace)", "anon"))
+    # template arguments (possibly several) are dropped: push_kernel<false, 256> -> push_kernel
+    m = re.search(r"::(\w+)(<[^()]*>)?\(", n.replace("(anonymous namespace)", "anon"))
     if m:
         return m.group(1)
     return n.split("(")[0].strip()[-60:]
