@@ -92,15 +92,17 @@ def main():
     tune_note = None
     if args.tune:
         # held-out queries of the workload's recipe (another seed), in the
-        # timed work's shape: a batch as large as the timed one, or one query
-        # for one-at-a-time calls (a one-query sample tunes that path)
-        k = q if args.mode == "batch" else 1
-        hs, ha, hw = make_queries(args.workload, g, count=max(k, 2), held_out=True)
+        # timed work's shape: a batch as large as the timed one, or a few
+        # queries answered one per call
+        k = q if args.mode == "batch" else min(q, 4)
+        form = K.KAIROS_TUNE_BATCH if args.mode == "batch" else K.KAIROS_TUNE_SINGLE
+        hs, ha, hw = make_queries(args.workload, g, count=k, held_out=True)
         cache = os.environ.get("KAIROS_TUNING_CACHE")
         t0 = time.perf_counter()
-        best = K.kairos_autotune(G, hs[:k], ha[:k], hw[:k])
+        best = K.kairos_autotune_form(G, form, hs, ha, hw)
         tune_s = time.perf_counter() - t0
-        tune_note = {"sample": f"{k} held-out queries of the workload's recipe (another seed)",
+        tune_note = {"sample": f"{k} held-out queries of the workload's recipe (another seed), "
+                               + ("as one batch" if args.mode == "batch" else "one per call"),
                      "seconds": round(tune_s, 2), "cache": cache}
         log(f"autotuned on {k} held-out queries in {tune_s:.1f} s: {best}")
 
@@ -195,7 +197,7 @@ def main():
                    **{k: tuning[k] for k in ("block", "batch_layout", "batch_persistent", "single_persistent",
                                              "rounds_per_sync", "tail_limit", "split", "chunk", "pull_alpha",
                                              "pull_beta", "dense_frontier", "arrival_filter", "run_dedupe",
-                                             "sweep_group")}},
+                                             "sweep_group", "binned")}},
         **extra,
     }
     print(json.dumps(line), flush=True)
@@ -224,7 +226,7 @@ B_EDGE, B_ITEM, B_RELAX, B_VERTEX = 8, 16, 4, 8
 
 def path_bytes(prof, traversed, vertex_queries, seconds):
     """Whole-step algorithmic bytes (all kernels) over the timed step time."""
-    b = B_EDGE * traversed + B_ITEM * (prof["items"] + prof.get("tail_items", 0)) \
+    b = B_EDGE * traversed + B_ITEM * (prof["items"] + prof.get("tail_items", 0) + prof.get("binned_items", 0)) \
         + B_RELAX * prof["relaxations"] + B_VERTEX * vertex_queries
     gbs = b / seconds / 1e9 if seconds > 0 else 0.0
     return {"bytes": int(b), "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -234,7 +236,8 @@ def kernel_names(mode, tuning):
     """Kernel names of the push, chunk and tail classes for this run."""
     if mode == "single":
         push = "persist_kernel" if tuning.get("single_persistent") else "push_kernel"
-        return {"push": push, "chunk": "chunk_kernel", "tail": "tail_kernel"}
+        # a binned round is timed as one unit: claim, scans, count, scatter, apply
+        return {"push": push, "chunk": "chunk_kernel", "tail": "tail_kernel", "binned": "binned_round"}
     layout = tuning.get("batch_layout", 2)
     if layout == 2 and tuning.get("batch_persistent"):
         return {"push": "hpersist_kernel", "chunk": "hchunk_kernel"}
@@ -245,9 +248,10 @@ def kernel_names(mode, tuning):
 
 def roofline_from_profile(prof, mode, pairs, workload, tuning):
     names = kernel_names(mode, tuning)
-    classes = [c for c in ("push", "chunk", "tail") if c in names and prof.get(f"launches_{c}", 0) > 0]
-    edges = {"push": prof["edges_scanned"], "chunk": prof["chunk_edges"], "tail": prof.get("tail_edges", 0)}
-    items = {"push": prof["items"], "chunk": 0, "tail": prof.get("tail_items", 0)}
+    classes = [c for c in ("push", "chunk", "tail", "binned") if c in names and prof.get(f"launches_{c}", 0) > 0]
+    edges = {"push": prof["edges_scanned"], "chunk": prof["chunk_edges"], "tail": prof.get("tail_edges", 0),
+             "binned": prof.get("binned_edges", 0)}
+    items = {"push": prof["items"], "chunk": 0, "tail": prof.get("tail_items", 0), "binned": prof.get("binned_items", 0)}
     if names["push"] in ("hpersist_kernel", "persist_kernel") and prof.get("launches_chunk", 0) == 0:
         # one launch runs both phases: its edges are the push and chunk counts
         edges["push"] += edges["chunk"]

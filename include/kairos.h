@@ -291,6 +291,13 @@ typedef struct kairos_tuning {
                                 pair's contacts) issue one atomic per run; on
                                 by default when more than 1/32 of the
                                 out-edges repeat the previous edge's head     */
+    uint32_t binned;         /* single earliest-arrival queries: a round whose
+                                frontier holds at least this many entries is
+                                destination-binned (claims, then candidates
+                                counted and scattered to bins of 2^14 heads,
+                                then applied bin by bin through LDS) instead
+                                of relaxing each edge at its head's word;
+                                0 = never.  Graphs of at most 2^26 vertices. */
 } kairos_tuning;
 
 int kairos_get_tuning(const kairos_graph *g, kairos_tuning *out);
@@ -312,6 +319,15 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in);
 int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
                     const uint32_t *t_omega, kairos_tuning *best);
 
+/* The same search with the objective named: KAIROS_TUNE_SINGLE times the
+ * q sample queries answered one per call (kairos_earliest_arrival),
+ * KAIROS_TUNE_BATCH as one batch.  kairos_autotune is this call with
+ * KAIROS_TUNE_SINGLE for q == 1 and KAIROS_TUNE_BATCH otherwise.  INVALID
+ * for another form. */
+enum { KAIROS_TUNE_SINGLE = 0, KAIROS_TUNE_BATCH = 1 };
+int kairos_autotune_form(kairos_graph *g, int form, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
+                         const uint32_t *t_omega, kairos_tuning *best);
+
 /* ------------------------------------------------------------ profiling --
  * When enabled, every kernel launch on g is bracketed by HIP events on the
  * stream it runs on and its algorithmic work is counted on the device.
@@ -324,7 +340,9 @@ typedef enum kairos_kernel_class {
     KAIROS_K_CHUNK = 4, /* push temporal edge map: split long adjacencies   */
     KAIROS_K_TAIL = 5,  /* push temporal edge map: small frontiers, one
                            workgroup looping over rounds                  */
-    KAIROS_K_COUNT = 6
+    KAIROS_K_BINNED = 6, /* push temporal edge map, destination-binned:
+                           count, scatter and apply of a large round      */
+    KAIROS_K_COUNT = 7
 } kairos_kernel_class;
 
 typedef struct kairos_profile {
@@ -340,6 +358,8 @@ typedef struct kairos_profile {
     uint64_t pull_edges;         /* in-edges read by pull (12 B each)          */
     uint64_t pull_vertices;      /* vertices examined by pull                  */
     uint64_t rounds;             /* frontier rounds                            */
+    uint64_t binned_edges;       /* out-edges claimed by destination-binned rounds */
+    uint64_t binned_items;       /* frontier entries expanded by them          */
 } kairos_profile;
 
 int kairos_profile_enable(kairos_graph *g, int on);

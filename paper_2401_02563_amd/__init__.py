@@ -19,7 +19,7 @@ __all__ = [
     "kairos_graph_build", "kairos_graph_free", "kairos_graph_stats", "kairos_graph_index",
     "kairos_earliest_arrival", "kairos_latest_departure", "kairos_fastest", "kairos_shortest_duration", "kairos_earliest_arrival_noalloc",
     "kairos_earliest_arrival_batch", "kairos_traversed_edges",
-    "kairos_get_tuning", "kairos_set_tuning", "kairos_autotune",
+    "kairos_get_tuning", "kairos_set_tuning", "kairos_autotune", "kairos_autotune_form",
     "kairos_profile_enable", "kairos_profile_read",
     "kairos_server_create", "kairos_server_submit", "kairos_server_poll", "kairos_server_free",
     "kairos_server_stats_read", "kairos_server_set_free_bytes_override", "kairos_status_string",
@@ -42,14 +42,14 @@ class kairos_tuning(ctypes.Structure):
     _fields_ = [(k, _u32) for k in ("block", "chunk", "split", "pull_alpha", "pull_beta",
                                     "rounds_per_sync", "batch_persistent", "sweep_group", "batch_layout",
                                     "tail_limit", "dense_frontier", "arrival_filter", "single_persistent",
-                                    "run_dedupe")]
+                                    "run_dedupe", "binned")]
 
 
 class kairos_profile(ctypes.Structure):
-    _fields_ = [("launches", _u64 * 6), ("ms", ctypes.c_double * 6), ("edges_scanned", _u64),
+    _fields_ = [("launches", _u64 * 7), ("ms", ctypes.c_double * 7), ("edges_scanned", _u64),
                 ("chunk_edges", _u64), ("items", _u64), ("relaxations", _u64), ("relax_attempts", _u64), ("tail_edges", _u64),
                 ("tail_items", _u64), ("pull_edges", _u64),
-                ("pull_vertices", _u64), ("rounds", _u64)]
+                ("pull_vertices", _u64), ("rounds", _u64), ("binned_edges", _u64), ("binned_items", _u64)]
 
 
 class kairos_index_view(ctypes.Structure):
@@ -98,6 +98,7 @@ _sig("kairos_traversed_edges", _i32, _p, _u32, _u32, _p, ctypes.POINTER(_u64))
 _sig("kairos_get_tuning", _i32, _p, ctypes.POINTER(kairos_tuning))
 _sig("kairos_set_tuning", _i32, _p, ctypes.POINTER(kairos_tuning))
 _sig("kairos_autotune", _i32, _p, _u32, _p, _p, _p, ctypes.POINTER(kairos_tuning))
+_sig("kairos_autotune_form", _i32, _p, _i32, _u32, _p, _p, _p, ctypes.POINTER(kairos_tuning))
 _sig("kairos_profile_enable", _i32, _p, _i32)
 _sig("kairos_profile_read", _i32, _p, ctypes.POINTER(kairos_profile))
 _sig("kairos_server_create", _i32, _p, ctypes.POINTER(kairos_server_opts), ctypes.POINTER(_p))
@@ -320,6 +321,20 @@ def kairos_autotune(g: Graph, src, t_alpha, t_omega) -> dict:
     return {k: getattr(t, k) for k, _ in t._fields_}
 
 
+KAIROS_TUNE_SINGLE, KAIROS_TUNE_BATCH = 0, 1
+
+
+def kairos_autotune_form(g: Graph, form: int, src, t_alpha, t_omega) -> dict:
+    s, ps = _host_u32(src)
+    a, pa = _host_u32(t_alpha)
+    w, pw = _host_u32(t_omega)
+    t = kairos_tuning()
+    _sync()
+    _check(_L.kairos_autotune_form(g.handle, int(form), len(s), ps, pa, pw, ctypes.byref(t)),
+           "kairos_autotune_form")
+    return {k: getattr(t, k) for k, _ in t._fields_}
+
+
 def kairos_profile_enable(g: Graph, on: bool = True):
     _check(_L.kairos_profile_enable(g.handle, 1 if on else 0), "kairos_profile_enable")
 
@@ -327,10 +342,10 @@ def kairos_profile_enable(g: Graph, on: bool = True):
 def kairos_profile_read(g: Graph) -> dict:
     p = kairos_profile()
     _check(_L.kairos_profile_read(g.handle, ctypes.byref(p)), "kairos_profile_read")
-    names = ["push", "pull", "init", "sort", "chunk", "tail"]
+    names = ["push", "pull", "init", "sort", "chunk", "tail", "binned"]
     d = {f"launches_{k}": p.launches[i] for i, k in enumerate(names)}
     d.update({f"ms_{k}": p.ms[i] for i, k in enumerate(names)})
-    for k in ("edges_scanned", "chunk_edges", "tail_edges", "tail_items", "items", "relaxations", "relax_attempts", "pull_edges", "pull_vertices", "rounds"):
+    for k in ("edges_scanned", "chunk_edges", "tail_edges", "tail_items", "items", "relaxations", "relax_attempts", "pull_edges", "pull_vertices", "rounds", "binned_edges", "binned_items"):
         d[k] = getattr(p, k)
     return d
 

@@ -372,7 +372,8 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 16 || in->split < 16 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
-        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1 || in->run_dedupe > 1)
+        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1 || in->run_dedupe > 1 ||
+        (in->binned != 0 && in->binned < 256))
         return KAIROS_ERR_INVALID;
     {
         // the reversed graph (if built) runs with the same parameters
@@ -436,8 +437,11 @@ int kairos_profile_read(kairos_graph *g, kairos_profile *out)
     out->pull_edges = g->prof.pull_edges;
     out->pull_vertices = g->prof.pull_verts;
     out->rounds = g->prof.rounds;
+    out->binned_edges = g->prof.bin_edges;
+    out->binned_items = g->prof.bin_items;
     g->prof.edges = g->prof.chunk_edges = g->prof.tail_edges = g->prof.tail_items = g->prof.attempts = g->prof.items = g->prof.relax = g->prof.pull_edges = g->prof.pull_verts = 0;
     g->prof.rounds = 0;
+    g->prof.bin_edges = g->prof.bin_items = 0;
     return KAIROS_OK;
 }
 

@@ -19,7 +19,7 @@
 // the index's shape (n, m, vertices with out-edges, largest out-degree,
 // repeated heads, largest departure) and the sample form (one query or a
 // batch); a later call with the same key takes the stored setting without
-// measuring.  One line per key: the key, then the 14 tuning fields in
+// measuring.  One line per key: the key, then the 15 tuning fields in
 // declaration order.
 #include "internal.h"
 
@@ -42,15 +42,17 @@ double seconds_now()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-int run_sample(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *ta, const uint32_t *tw,
+int run_sample(kairos_graph *g, int form, uint32_t q, const uint32_t *src, const uint32_t *ta, const uint32_t *tw,
                uint32_t *d_single, uint32_t *d_batch, double *secs)
 {
-    // a sample of one query tunes the single-query path, a larger sample the
-    // batched path it will be answered with
+    // the one-query form answers the sample one query per call, the batch
+    // form as one batch
     const double t0 = seconds_now();
-    if (q == 1) {
-        int rc = kairos_earliest_arrival(g, src[0], ta[0], tw[0], d_single);
-        if (rc) return rc;
+    if (form == KAIROS_TUNE_SINGLE) {
+        for (uint32_t i = 0; i < q; ++i) {
+            int rc = kairos_earliest_arrival(g, src[i], ta[i], tw[i], d_single);
+            if (rc) return rc;
+        }
     } else {
         int rc = kairos_earliest_arrival_batch(g, q, src, ta, tw, d_batch);
         if (rc) return rc;
@@ -59,16 +61,16 @@ int run_sample(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t 
     return KAIROS_OK;
 }
 
-int measure(kairos_graph *g, const kairos_tuning &t, uint32_t q, const uint32_t *src, const uint32_t *ta,
+int measure(kairos_graph *g, int form, const kairos_tuning &t, uint32_t q, const uint32_t *src, const uint32_t *ta,
             const uint32_t *tw, uint32_t *d1, uint32_t *db, double *out)
 {
     int rc = kairos_set_tuning(g, &t);
     if (rc) return rc;
     double warm;
-    if ((rc = run_sample(g, q, src, ta, tw, d1, db, &warm))) return rc;
+    if ((rc = run_sample(g, form, q, src, ta, tw, d1, db, &warm))) return rc;
     double v[3];
     for (double &x : v)
-        if ((rc = run_sample(g, q, src, ta, tw, d1, db, &x))) return rc;
+        if ((rc = run_sample(g, form, q, src, ta, tw, d1, db, &x))) return rc;
     std::sort(v, v + 3);
     *out = v[1];
     return KAIROS_OK;
@@ -92,16 +94,17 @@ int measure_sweep(kairos_graph *g, const kairos_tuning &t, uint32_t q, const uin
     return KAIROS_OK;
 }
 
-constexpr int NFIELDS = 14;
+constexpr int NFIELDS = 15;
 uint32_t *field(kairos_tuning &t, int i)
 {
     uint32_t *f[NFIELDS] = {&t.block, &t.chunk, &t.split, &t.pull_alpha, &t.pull_beta, &t.rounds_per_sync,
                             &t.batch_persistent, &t.sweep_group, &t.batch_layout, &t.tail_limit,
-                            &t.dense_frontier, &t.arrival_filter, &t.single_persistent, &t.run_dedupe};
+                            &t.dense_frontier, &t.arrival_filter, &t.single_persistent, &t.run_dedupe,
+                            &t.binned};
     return f[i];
 }
 
-std::string cache_key(kairos_graph *g, uint32_t q)
+std::string cache_key(kairos_graph *g, int form)
 {
     hipDeviceProp_t prop;
     std::string arch = "unknown";
@@ -112,7 +115,8 @@ std::string cache_key(kairos_graph *g, uint32_t q)
     }
     std::ostringstream k;
     k << arch << "/cu" << g->num_cus << "/n" << g->n << "/m" << g->m << "/live" << g->n_live << "/deg"
-      << g->max_out_degree << "/rep" << g->repeat_heads << "/tmax" << g->max_t << (q == 1 ? "/single" : "/batch");
+      << g->max_out_degree << "/rep" << g->repeat_heads << "/tmax" << g->max_t
+      << (form == KAIROS_TUNE_SINGLE ? "/single" : "/batch");
     return k.str();
 }
 
@@ -166,7 +170,15 @@ void cache_store(const char *path, const std::string &key, kairos_tuning t)
 extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src, const uint32_t *t_alpha,
                                const uint32_t *t_omega, kairos_tuning *best_out)
 {
+    return kairos_autotune_form(g, q == 1 ? KAIROS_TUNE_SINGLE : KAIROS_TUNE_BATCH, q, src, t_alpha, t_omega,
+                                best_out);
+}
+
+extern "C" int kairos_autotune_form(kairos_graph *g, int form, uint32_t q, const uint32_t *src,
+                                    const uint32_t *t_alpha, const uint32_t *t_omega, kairos_tuning *best_out)
+{
     if (!g || (q && (!src || !t_alpha || !t_omega))) return KAIROS_ERR_INVALID;
+    if (form != KAIROS_TUNE_SINGLE && form != KAIROS_TUNE_BATCH) return KAIROS_ERR_INVALID;
     for (uint32_t i = 0; i < q; ++i)
         if (src[i] >= g->n || t_alpha[i] > t_omega[i] || t_omega[i] > KAIROS_TMAX) return KAIROS_ERR_RANGE;
     if (q == 0) {
@@ -174,7 +186,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         return KAIROS_OK;
     }
     const char *cache = std::getenv("KAIROS_TUNING_CACHE");
-    const std::string key = cache && *cache ? cache_key(g, q) : std::string();
+    const std::string key = cache && *cache ? cache_key(g, form) : std::string();
     if (!key.empty()) {
         kairos_tuning c{};
         if (cache_lookup(cache, key, &c) && kairos_set_tuning(g, &c) == KAIROS_OK) {
@@ -182,17 +194,20 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
             return KAIROS_OK;
         }
     }
-    const uint32_t qb = (uint32_t)std::min<uint64_t>(q, std::max<uint64_t>(1, 0xFFFFFFFEull / g->n));
+    const uint32_t qb = form == KAIROS_TUNE_SINGLE
+                            ? q
+                            : (uint32_t)std::min<uint64_t>(q, std::max<uint64_t>(1, 0xFFFFFFFEull / g->n));
+    const bool batch = form == KAIROS_TUNE_BATCH;
     uint32_t *d1 = (uint32_t *)dev_alloc((size_t)g->n * 4, nullptr);
-    uint32_t *db = qb > 1 ? (uint32_t *)dev_alloc((size_t)qb * g->n * 4, nullptr) : nullptr;
-    if (!d1 || (qb > 1 && !db)) {
+    uint32_t *db = batch ? (uint32_t *)dev_alloc((size_t)qb * g->n * 4, nullptr) : nullptr;
+    if (!d1 || (batch && !db)) {
         dev_free(d1);
         dev_free(db);
         return KAIROS_ERR_NOMEM;
     }
     kairos_tuning best = g->tuning;
     double best_t = 0;
-    int rc = measure(g, best, qb, src, t_alpha, t_omega, d1, db, &best_t);
+    int rc = measure(g, form, best, qb, src, t_alpha, t_omega, d1, db, &best_t);
     struct Axis {
         uint32_t kairos_tuning::*field;
         std::vector<uint32_t> values;
@@ -211,6 +226,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
         {&kairos_tuning::rounds_per_sync, {1, 2, 4}},
         {&kairos_tuning::pull_alpha, {0, 4, 14}},
         {&kairos_tuning::pull_beta, {8, 24, 64}},
+        {&kairos_tuning::binned, {0, 1u << 14, 1u << 16, 1u << 18, 1u << 20}},
     };
     for (const Axis &ax : axes) {
         if (rc) break;
@@ -220,7 +236,7 @@ extern "C" int kairos_autotune(kairos_graph *g, uint32_t q, const uint32_t *src,
             kairos_tuning t = best;
             t.*(ax.field) = v;
             double secs;
-            if ((rc = measure(g, t, qb, src, t_alpha, t_omega, d1, db, &secs))) break;
+            if ((rc = measure(g, form, t, qb, src, t_alpha, t_omega, d1, db, &secs))) break;
             if (secs < best_t * 0.98) {
                 best_t = secs;
                 best = t;

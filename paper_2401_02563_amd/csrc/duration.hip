@@ -26,6 +26,7 @@
 // over v's in-list.
 
 #include "internal.h"
+#include "scan.h"
 
 #include <algorithm>
 #include <cstring>
@@ -50,9 +51,6 @@ struct SDState {
 namespace {
 
 constexpr int SDT = 256;                  // threads per block
-constexpr int SCAN_PER = 4;               // scan entries per thread
-constexpr int SCAN_BLK = SDT * SCAN_PER;  // scan entries per block
-constexpr int TOPT = 1024;                // threads of the top-level scan
 // counters: frontier sizes of the two parities, relax total
 enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_CNT_WORDS = 4 };
 
@@ -256,75 +254,6 @@ __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t
     }
 }
 
-// Exclusive scan of `count` words, SCAN_BLK per block; block totals to bsum.
-__global__ __launch_bounds__(SDT) void sd_scan_block_kernel(uint32_t *data, uint32_t count, uint32_t *bsum)
-{
-    __shared__ uint32_t s_w[SDT / 64];
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t b0 = blockIdx.x * SCAN_BLK + tid * SCAN_PER;
-    uint32_t v[SCAN_PER];
-    uint32_t s = 0;
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; ++j) {
-        v[j] = b0 + j < count ? data[b0 + j] : 0u;
-        s += v[j];
-    }
-    uint32_t x = s;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    if (lane == 63) s_w[w] = x;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (uint32_t k = 0; k < SDT / 64; ++k) {
-        if (k < w) off += s_w[k];
-        tot += s_w[k];
-    }
-    uint32_t run = off + x - s;
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; ++j) {
-        if (b0 + j < count) data[b0 + j] = run;
-        run += v[j];
-    }
-    if (tid == 0) bsum[blockIdx.x] = tot;
-}
-
-// Exclusive scan of the nb block totals in one block; the grand total to
-// *total.
-__global__ __launch_bounds__(TOPT) void sd_scan_top_kernel(uint32_t *bsum, uint32_t nb, uint32_t *total)
-{
-    __shared__ uint32_t part[TOPT];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (nb + TOPT - 1) / TOPT;
-    const uint32_t beg = min(nb, tid * per), end = min(nb, beg + per);
-    uint32_t s = 0;
-    for (uint32_t i = beg; i < end; ++i) s += bsum[i];
-    part[tid] = s;
-    __syncthreads();
-    for (uint32_t o = 1; o < TOPT; o <<= 1) {
-        const uint32_t y = tid >= o ? part[tid - o] : 0u;
-        __syncthreads();
-        part[tid] += y;
-        __syncthreads();
-    }
-    uint32_t run = part[tid] - s;
-    for (uint32_t i = beg; i < end; ++i) {
-        const uint32_t y = bsum[i];
-        bsum[i] = run;
-        run += y;
-    }
-    if (tid == TOPT - 1) *total = part[TOPT - 1];
-}
-
-__global__ __launch_bounds__(SDT) void sd_scan_add_kernel(uint32_t *data, uint32_t count, const uint32_t *bsum)
-{
-    const uint32_t add = bsum[blockIdx.x];
-    const uint32_t b0 = blockIdx.x * SCAN_BLK;
-    for (uint32_t j = threadIdx.x; j < SCAN_BLK; j += SDT)
-        if (b0 + j < count) data[b0 + j] += add;
-}
-
 // One thread per out-edge of the ranges: candidate D_v(t) + lambda into the
 // head's in-list position.
 __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, const uint32_t *__restrict__ base,
@@ -418,7 +347,7 @@ int sd_state_alloc(kairos_graph *g, SDState **out)
     ok = ok && (s->rng = (uint4 *)dev_alloc(n * sizeof(uint4), nullptr)) != nullptr;
     ok = ok && (s->rstop = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
     ok = ok && (s->base = (uint32_t *)dev_alloc((n + 1) * 4, nullptr)) != nullptr;
-    ok = ok && (s->bsum = (uint32_t *)dev_alloc((n / SCAN_BLK + 2) * 4, nullptr)) != nullptr;
+    ok = ok && (s->bsum = (uint32_t *)dev_alloc(scan_scratch_words(n) * 4, nullptr)) != nullptr;
     ok = ok && (s->cnt = (uint32_t *)dev_alloc(SD_CNT_WORDS * 4, nullptr)) != nullptr;
     if (ok && hipHostMalloc((void **)&s->h_pin, SD_CNT_WORDS * 4, hipHostMallocDefault) != hipSuccess) {
         s->h_pin = nullptr;
@@ -520,10 +449,7 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
             prof_begin(g, st, &ev);
             hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, cap)), dim3(SDT), 0, st, A, s->queue[p],
                                F, s->dlo[p], s->dhi[p], s->rng, s->rstop, s->base, s->cnt + SD_FRONT + q);
-            const uint32_t nb = (F + SCAN_BLK - 1) / SCAN_BLK;
-            hipLaunchKernelGGL(sd_scan_block_kernel, dim3(nb), dim3(SDT), 0, st, s->base, F, s->bsum);
-            hipLaunchKernelGGL(sd_scan_top_kernel, dim3(1), dim3(TOPT), 0, st, s->bsum, nb, s->cnt + SD_TOTAL);
-            if (nb > 1) hipLaunchKernelGGL(sd_scan_add_kernel, dim3(nb), dim3(SDT), 0, st, s->base, F, s->bsum);
+            exclusive_scan(st, s->base, F, s->bsum, s->cnt + SD_TOTAL);
             hipLaunchKernelGGL(sd_relax_kernel, dim3(cap), dim3(SDT), 0, st, A, F, s->base, s->rng, s->rstop,
                                s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q);
             prof_end(g, st, KAIROS_K_PUSH, ev);

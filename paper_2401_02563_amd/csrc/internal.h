@@ -63,6 +63,7 @@ struct Slot {
     // from the host, and the slot's launches are never profiled.
     uint4 *d_stage = nullptr;
     bool fixed = false;
+    void *pb = nullptr;          // buffers of destination-binned rounds (traverse.hip), on first use
     uint32_t stamp_next = 2;     // next round stamp value (0 = never stamped, 1 = spare)
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -85,7 +86,7 @@ enum : int {
 };
 enum : int {
     ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5, ST_ATTEMPTS = 6,
-    ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_WORDS = 16
+    ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_BIN_EDGES = 9, ST_BIN_ITEMS = 10, ST_WORDS = 16
 };
 // The work counters are kept in ST_SHARDS copies (a block adds to copy
 // blockIdx % ST_SHARDS, so concurrent additions hit different addresses),
@@ -109,6 +110,7 @@ struct ProfileAcc {
     uint64_t launches[KAIROS_K_COUNT] = {};
     double ms[KAIROS_K_COUNT] = {};
     uint64_t edges = 0, chunk_edges = 0, tail_edges = 0, tail_items = 0, attempts = 0, items = 0, relax = 0, pull_edges = 0, pull_verts = 0, rounds = 0;
+    uint64_t bin_edges = 0, bin_items = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> free_events;
     std::mutex mu;

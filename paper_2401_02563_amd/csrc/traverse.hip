@@ -33,6 +33,7 @@
 //    edges that a second kernel spreads over the whole GPU.
 
 #include "internal.h"
+#include "scan.h"
 #include "stage.h"
 
 #include <algorithm>
@@ -1077,6 +1078,8 @@ int grid_cap(uint64_t work, int per_block, int cap)
     return (int)g;
 }
 
+#include "binned.h"
+
 int fill(hipStream_t st, uint32_t *p, uint64_t count, uint32_t value)
 {
     if (!count) return KAIROS_OK;
@@ -1293,6 +1296,33 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
             if (prc == KAIROS_OK) continue;
             if (prc != KAIROS_ERR_BUSY) return prc;
             persist = false;  // launch refused: per-round launches from here on
+        }
+        // a large round of a single earliest-arrival query: destination-
+        // binned, then back to the host for the next decision
+        if (!SWEEP && !levels && !pulling && A.nq == 1 && !A.filt && !s->fixed && !tu.pull_alpha && tu.binned &&
+            F >= tu.binned && binned_supported(g)) {
+            if ((rc = binned_alloc(g, s))) return rc;
+            A.round = r;
+            A.stamp_val = next_stamp(s, &rc);
+            if (rc) return rc;
+            A.cur = s->queue[which];
+            A.next = s->queue[which ^ 1];
+            A.dense = 0;
+            if ((rc = binned_round(g, s, A, F))) return rc;
+            ++r;
+            which ^= 1;
+            KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, CNT_WORDS * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            KAIROS_HIP(hipStreamSynchronize(st));
+            F = s->h_pin[CNT_FRONT + r % 3u];
+            if (g->prof.on) {
+                std::lock_guard<std::mutex> lk(g->prof.mu);
+                g->prof.rounds += 1;
+            }
+            if (which == 1 && F > 0) {
+                std::swap(s->queue[0], s->queue[1]);
+                which = 0;
+            }
+            continue;
         }
         for (uint32_t k = 0; k < R; ++k) {
             A.round = r;
@@ -1534,6 +1564,8 @@ void prof_add_stats(kairos_graph *g, const unsigned long long *h)
     g->prof.relax += h[ST_RELAX];
     g->prof.pull_edges += h[ST_PULL_EDGES];
     g->prof.pull_verts += h[ST_PULL_VERTS];
+    g->prof.bin_edges += h[ST_BIN_EDGES];
+    g->prof.bin_items += h[ST_BIN_ITEMS];
 }
 
 // ---------------------------------------------------------------- slots --
@@ -1541,6 +1573,7 @@ void slot_destroy(Slot *s)
 {
     if (!s) return;
     if (s->stream) hipStreamSynchronize(s->stream);
+    binned_free(s);
     dev_free(s->done);
     dev_free(s->queue[0]);
     dev_free(s->queue[1]);
@@ -1950,6 +1983,12 @@ kairos_tuning default_tuning(const kairos_graph *g)
     // on batches of the 10^9-edge bursty graph; on R-MAT graphs, which have
     // almost none, the extra ballot costs up to 1.4%
     t.run_dedupe = g && g->repeat_heads * 32 > g->m ? 1u : 0u;
+    // longer chunks where bursts of one pair's contacts fill long claims:
+    // the 10^9-edge bursty graph (first 16 queries) 3.28 -> 3.10 ms with
+    // 1024 (2048: 3.20, 4096: 3.40); the R-MAT graphs lose 2% with 1024
+    // (scale 24 4.41 -> 4.49 ms, scale 20 0.779 -> 0.796 ms)
+    if (t.run_dedupe) t.chunk = 1024;
+    t.binned = 0;
     return t;
 }
 

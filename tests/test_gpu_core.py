@@ -523,3 +523,63 @@ def test_gappy_single_and_batch(layout, persistent):
                 assert np.array_equal(K.as_u32(one), pf), q
     finally:
         K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("which", ["uniform", "rmat16", "bursty16", "rmat_wide", "gappy"])
+@pytest.mark.parametrize("tuning", [dict(binned=256), dict(binned=256, tail_limit=0),
+                                    dict(binned=4096, tail_limit=0, rounds_per_sync=2)])
+def test_binned_rounds(which, tuning):
+    """Destination-binned rounds (claims, count, scatter, apply through LDS)
+    give the same bits as push rounds, under both succession predicates and
+    with paths; the rounds really ran (binned edges counted)."""
+    from oracle import paths as P
+    g, G, se = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide,
+                "gappy": gappy}[which]()
+    name = {"uniform": "uniform-10k", "rmat16": "rmat20-32m", "bursty16": "bursty22-1b",
+            "rmat_wide": "rmat22-256m", "gappy": "uniform-10k"}[which]
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, **tuning)
+        srcs, ta, tw = make_queries(name, g, count=4)
+        binned = 0
+        for q in range(len(srcs)):
+            s, a, w = int(srcs[q]), int(ta[q]), int(tw[q])
+            print_case("binned", which, tuning, q)
+            K.kairos_profile_enable(G, True)
+            K.kairos_profile_read(G)
+            got = ea_gpu(G, s, a, w)
+            binned += K.kairos_profile_read(G)["binned_edges"]
+            K.kairos_profile_enable(G, False)
+            want = O.earliest_arrival(se, s, a, w)
+            assert np.array_equal(got, want), q
+            assert K.kairos_traversed_edges(G, a, w, torch.from_numpy(got.view(np.int32)).cuda()) == \
+                O.traversed_edges(se, a, w, want)
+            if q == 0:
+                _, sea = P.min_hops(g.n, g.src, g.dst, g.t, g.lam, s, a, w, True)
+                out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+                K.kairos_query(G, K.KAIROS_EARLIEST_ARRIVAL, s, a, w, out, strict=True)
+                assert np.array_equal(K.as_u32(out), sea)
+                pt, pd = (torch.empty(g.n, dtype=torch.int32, device="cuda") for _ in range(2))
+                K.kairos_earliest_arrival_path(G, s, a, w, out, pt, pd)
+                wt, wd = P.ea_predecessors(g.n, g.src, g.dst, g.t, g.lam, s, a, w, want)
+                assert np.array_equal(K.as_u32(pt), wt) and np.array_equal(K.as_u32(pd), wd)
+        if tuning == dict(binned=256, tail_limit=0) and which in ("uniform", "rmat16", "bursty16"):
+            assert binned > 0  # wide windows: large frontiers (the narrow-window graphs may have none)
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+def test_binned_rounds_scale20_full():
+    """All 2^20 vertices (64 bins) with binned rounds from 4096 entries, in
+    the benchmark's one-query-per-call form."""
+    g, G, se = built("rmat20-full", lambda: make_graph("rmat20-32m"))
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, binned=4096)
+        srcs, ta, tw = make_queries("rmat20-32m", g)
+        for q in range(0, 64, 9):
+            print_case("binned full", q)
+            assert np.array_equal(ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q])),
+                                  O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+    finally:
+        K.kairos_set_tuning(G, **old)
