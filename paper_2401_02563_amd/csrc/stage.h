@@ -40,6 +40,9 @@ __device__ __forceinline__ uint64_t lanes_below()
 // one lane it returns after one ballot.
 __device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
 {
+    // most edge groups improve nothing (their arrivals are not below the
+    // heads' words): one ballot settles those
+    if (__ballot(ok) == 0ull) return;
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t kk = ok ? key : ~(uint64_t)lane;
     // shuffles run with every lane active: a shuffle inside a short-circuit

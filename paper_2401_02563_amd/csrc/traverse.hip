@@ -94,6 +94,7 @@ struct TravArgs {
     uint32_t dedupe;         // one atomic per run of lanes into the same slot
     uint32_t n_live;         // vertices from this id on have no out-edges: never enqueued
     uint32_t max_deg;        // largest out-degree
+    uint32_t min_per;        // least frontier entries per block and pass of the push phase
 };
 
 // Per-query parameter word fpar.y: code shift (bits 0-7), code width (bits
@@ -336,11 +337,19 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     // in id order and expand the members (stamped by the previous round), so
     // offsets, claim words and adjacency ranges are read in address order
     const uint32_t span = A.dense ? A.n : F;
-    for (uint32_t base = blockIdx.x * B; base < span; base += gridDim.x * B) {
+    // entries per block and pass: B, or fewer when the frontier would not
+    // fill the grid and adjacencies are long, so that a small frontier is
+    // spread over more blocks and each block relaxes fewer edges (a block
+    // relaxes its entries' short claims itself: 256 entries with 100-edge
+    // claims keep one block busy for a hundred edge groups while others
+    // idle).  Never below A.min_per, about B * 32 / average out-degree:
+    // with short adjacencies every extra block only adds its fixed cost.
+    const uint32_t per = max(min((uint32_t)B, A.min_per), min((uint32_t)B, (span + gridDim.x - 1u) / gridDim.x));
+    for (uint32_t base = blockIdx.x * per; base < span; base += gridDim.x * per) {
         const uint32_t i = base + tid;
         uint32_t lo = 0, len = 0, q = 0, tw = 0, sd = 0, nch = 0;
         uint2 fpq = make_uint2(0u, 0u);
-        if (i < span && (!A.dense || stamp_of(A.av, i) == A.front_stamp)) {
+        if (tid < per && i < span && (!A.dense || stamp_of(A.av, i) == A.front_stamp)) {
             ++n_items;
             const uint32_t item = A.dense ? i : A.cur[i];
             q = item / A.n;
@@ -1130,6 +1139,16 @@ int fill_filter(kairos_graph *g, hipStream_t st, uint8_t *filt, uint64_t nq)
     return fill(st, (uint32_t *)filt, nq * filt_stride(g->n) / 4, 0xFFFFFFFFu);
 }
 
+// About 32 edges per thread of a 256-thread block: 256 entries on the
+// scale-20/24 R-MAT graphs (32 out-edges per vertex), 34 on the bursty graph
+// (240).  Measured on the bursty graph (first 16 queries) 3.03 -> 2.88 ms
+// when small frontiers spread; spreading on the R-MAT graphs cost 2-7%.
+uint32_t min_entries_per_block(const kairos_graph *g)
+{
+    const uint64_t avg = std::max<uint64_t>(1, g->m / std::max<uint32_t>(g->n_live, 1));
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, 256 * 32 / avg));
+}
+
 TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
 {
     TravArgs A{};
@@ -1141,6 +1160,7 @@ TravArgs make_args(kairos_graph *g, Slot *s, uint32_t nq)
     A.st_in = g->st_in;
     A.n_live = g->n_live;
     A.max_deg = g->max_out_degree;
+    A.min_per = min_entries_per_block(g);
     A.qp = s->qp;
     A.n = g->n;
     A.av = s->av;
@@ -2171,6 +2191,7 @@ TravArgs multi_args(kairos_graph *g, MultiState *ms)
     A.st_in = g->st_in;
     A.n_live = g->n_live;
     A.max_deg = g->max_out_degree;
+    A.min_per = min_entries_per_block(g);
     A.qp = ms->qp;
     A.n = g->n;
     A.av = ms->av;
