@@ -71,6 +71,52 @@ __device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
 }
 
 
+// One step of a key-gated inclusive min-scan over the wavefront: mv takes
+// the minimum with the value of the lane CTRL names (a DPP row shift or row
+// broadcast, rows ROWS written) when that lane holds the same key.  Lanes
+// without a source lane get the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void gated_min_step(uint32_t &mv, uint32_t key)
+{
+    const uint32_t ms = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)mv, CTRL, ROWS, 0xF, false);
+    const uint32_t ks = (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, ROWS, 0xF, false);
+    if (ks == key) mv = min(mv, ms);
+}
+
+// dedupe_runs for lanes that all relax edges of one query: the slot is the
+// 32-bit head id.  A run is a maximal stretch of neighbouring lanes that
+// have an edge and the same head; its last lane keeps the least arrival of
+// the run and the run's other lanes drop their edges.  The minimum is a
+// scan gated by key equality (DPP shifts by 1, 2, 4, 8 inside rows of 16
+// lanes, then the last lane of a row to the next row and lane 31 to rows 2
+// and 3): a run is contiguous, so its last lane's window covers the whole
+// run; it may also take in an earlier run into the same head, which only
+// lowers the survivor's value to another arrival of this group for that
+// head.  Every lane of the wavefront must call this.
+__device__ __forceinline__ void dedupe_runs32(bool &ok, uint32_t &a, uint32_t key)
+{
+    const uint64_t m = __ballot(ok);
+    if (m == 0ull) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t dn = __shfl_down(key, 1);
+    const bool ok_dn = lane < 63 && ((m >> (lane + 1)) & 1ull);
+    const bool last = !ok_dn || dn != key;
+    if (__ballot(ok && !last) == 0ull) return;  // no run longer than one lane
+    uint32_t mv = ok ? a : 0xFFFFFFFFu;
+    gated_min_step<0x111, 0xF>(mv, key);  // row_shr:1
+    gated_min_step<0x112, 0xF>(mv, key);  // row_shr:2
+    gated_min_step<0x114, 0xF>(mv, key);  // row_shr:4
+    gated_min_step<0x118, 0xF>(mv, key);  // row_shr:8
+    gated_min_step<0x142, 0xA>(mv, key);  // row_bcast:15
+    gated_min_step<0x143, 0xC>(mv, key);  // row_bcast:31
+    if (ok) {
+        if (last)
+            a = mv;
+        else
+            ok = false;
+    }
+}
+
 // Per-wavefront output buffer of CAP entries in LDS.  `n` is wave-uniform.
 template <int CAP>
 struct Stage {

@@ -279,6 +279,89 @@ __device__ __forceinline__ void relax_group(const TravArgs &A, EdgeGroup &G, uns
     }
 }
 
+// One query's view for relax_group_u: its rows and parameters, all
+// wave-uniform.
+struct QueryRow {
+    unsigned long long *av;  // arrival words of the query
+    uint32_t *fa, *l1;       // sweep rows (SWEEP only)
+    uint32_t *hop;           // level row (temporal BFS) or null
+    uint32_t q, qbase;       // query index; its entries are qbase + v
+    uint32_t tw, sd;
+};
+
+__device__ __forceinline__ QueryRow query_row(const TravArgs &A, uint32_t q, bool sweep)
+{
+    const uint4 p = A.qp[q];
+    const size_t base = (size_t)q * A.n;
+    QueryRow Q;
+    Q.av = A.av + base;
+    Q.fa = sweep ? A.fa + base : nullptr;
+    Q.l1 = sweep ? A.l1 + base : nullptr;
+    Q.hop = A.hop ? A.hop + base : nullptr;
+    Q.q = q;
+    Q.qbase = (uint32_t)base;
+    Q.tw = p.z;
+    Q.sd = p.w;
+    return Q;
+}
+
+// relax_group for a wavefront whose lanes all relax edges of one query and
+// no arrival codes: the query's values are scalars, slots are head ids into
+// its own rows, and runs of equal heads are found on 32-bit keys.  Same
+// steps and results as relax_group.
+template <bool SWEEP>
+__device__ __forceinline__ void relax_group_u(const TravArgs &A, const QueryRow &Q, const uint32_t (&v)[UNR],
+                                              uint32_t (&a)[UNR], bool (&ok)[UNR], unsigned long long (&bal)[UNR],
+                                              uint32_t (&item)[UNR], uint32_t *vol_cnt, unsigned long long &nrelax)
+{
+    uint32_t cur[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) ok[k] = ok[k] && a[k] <= Q.tw;
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) cur[k] = arrival_of(Q.av, ok[k] ? v[k] : 0u);
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        ok[k] = ok[k] && a[k] < cur[k];
+        if (A.dedupe) dedupe_runs32(ok[k], a[k], v[k]);
+    }
+    unsigned long long old[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k)
+        if (ok[k]) old[k] = atomicMin(&Q.av[v[k]], av_word(a[k], A.stamp_val));
+    uint32_t st[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        nrelax += ok[k] ? (1ull << 32) : 0ull;
+        ok[k] = ok[k] && a[k] < (uint32_t)(old[k] >> 32);
+        nrelax += ok[k] ? 1ull : 0ull;
+        if (ok[k]) st[k] = (uint32_t)old[k];
+        if (Q.hop && ok[k] && (uint32_t)(old[k] >> 32) == INF) Q.hop[v[k]] = A.round + 1u;
+    }
+    if (SWEEP && Q.sd != INF) {
+#pragma unroll
+        for (int k = 0; k < UNR; ++k)
+            if (ok[k]) {
+                atomicMin(&Q.fa[v[k]], a[k] - Q.sd);
+                atomicMax(&Q.l1[v[k]], Q.sd + 1u);
+            }
+    }
+    uint32_t vol = 0;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+        const bool push = ok[k] && st[k] != A.stamp_val && v[k] < A.n_live;
+        bal[k] = __ballot(push);
+        item[k] = Q.qbase + v[k];
+        any = any || push;
+        if (push && A.track_volume) vol += A.off[v[k] + 1] - A.off[v[k]];
+    }
+    if (A.qflag && any) A.qflag[Q.q] = A.round + 1u;
+    if (A.track_volume) {
+        for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o);
+        if ((threadIdx.x & 63) == 0 && vol) atomicAdd(vol_cnt, vol);
+    }
+}
+
 // Appends the group's entries to a frontier whose length lives in LDS (the
 // one-workgroup kernel): one LDS atomic per wavefront.
 __device__ __forceinline__ void lds_append(uint32_t *next, uint32_t *s_cnt, const unsigned long long (&bal)[UNR],
@@ -307,10 +390,14 @@ using TStage = Stage<SCAP>;
 // part of its adjacency; short claims are relaxed by the block with a
 // prefix-sum load balance, claims of at least `split` edges are cut into
 // chunks for part 2 (one chunk-list reservation per block and pass).
-template <bool SWEEP, int B>
+template <bool SWEEP, int B, bool UQ>
 __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage &S, unsigned long long &n_edges,
                                            unsigned long long &n_relax, unsigned long long &n_items)
 {
+    // UQ: one query and no arrival codes; every entry is a vertex of query
+    // 0 and edges go through relax_group_u
+    QueryRow Q0;
+    if (UQ) Q0 = query_row(A, 0u, SWEEP);
     __shared__ uint32_t s_pref[B + 1];
     __shared__ uint32_t s_lo[B];
     __shared__ uint32_t s_q[B];
@@ -352,7 +439,7 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
         if (tid < per && i < span && (!A.dense || stamp_of(A.av, i) == A.front_stamp)) {
             ++n_items;
             const uint32_t item = A.dense ? i : A.cur[i];
-            q = item / A.n;
+            q = UQ ? 0u : item / A.n;
             const uint32_t u = item - q * A.n;
             const uint4 p = A.qp[q];
             fpq = A.fpar[q];
@@ -391,10 +478,12 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             s_csum[w] = c;
         }
         s_lo[tid] = lo;
-        s_q[tid] = q;
-        s_tw[tid] = tw;
-        s_sd[tid] = sd;
-        s_fp[tid] = fpq;
+        if (!UQ) {
+            s_q[tid] = q;
+            s_tw[tid] = tw;
+            s_sd[tid] = sd;
+            s_fp[tid] = fpq;
+        }
         __syncthreads();
         uint32_t woff = 0, total = 0, coff = 0, ctotal = 0;
         for (int w2 = 0; w2 < B / 64; ++w2) {
@@ -424,6 +513,52 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
             ser_len = len - covered;
         }
         if (tid == 0) n_edges += total;
+        if (UQ) {
+            for (uint32_t j0 = 0; j0 < total; j0 += B * UNR) {
+                uint32_t v[UNR], a[UNR];
+                bool ok[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const uint32_t j = j0 + k * B + tid;
+                    ok[k] = j < total;
+                    int lo_k = 0, hi_k = B;
+                    while (hi_k - lo_k > 1) {
+                        const int mid = (lo_k + hi_k) >> 1;
+                        if (s_pref[mid] <= j)
+                            lo_k = mid;
+                        else
+                            hi_k = mid;
+                    }
+                    const uint2 dv = A.da[ok[k] ? s_lo[lo_k] + (j - s_pref[lo_k]) : 0u];
+                    v[k] = dv.x;
+                    a[k] = dv.y;
+                }
+                unsigned long long bal[UNR];
+                uint32_t item[UNR];
+                relax_group_u<SWEEP>(A, Q0, v, a, ok, bal, item, vol_cnt, n_relax);
+                stage_append(S, bal, item);
+            }
+            n_edges += ser_len;
+            uint32_t ser_done = 0;
+            while (__ballot(ser_done < ser_len)) {
+                uint32_t v[UNR], a[UNR];
+                bool ok[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    ok[k] = ser_done < ser_len;
+                    const uint2 dv = A.da[ok[k] ? ser_lo + ser_done : 0u];
+                    if (ok[k]) ++ser_done;
+                    v[k] = dv.x;
+                    a[k] = dv.y;
+                }
+                unsigned long long bal[UNR];
+                uint32_t item[UNR];
+                relax_group_u<SWEEP>(A, Q0, v, a, ok, bal, item, vol_cnt, n_relax);
+                stage_append(S, bal, item);
+            }
+            __syncthreads();
+            continue;
+        }
         for (uint32_t j0 = 0; j0 < total; j0 += B * UNR) {
             EdgeGroup G;
 #pragma unroll
@@ -482,13 +617,13 @@ __device__ __forceinline__ void push_phase(const TravArgs &A, uint32_t F, TStage
     }
 }
 
-template <bool SWEEP, int B>
+template <bool SWEEP, int B, bool UQ>
 __global__ __launch_bounds__(B) void push_kernel(TravArgs A)
 {
     __shared__ uint32_t s_stage[B / 64][SCAP];
     TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0, n_items = 0;
-    push_phase<SWEEP, B>(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
+    push_phase<SWEEP, B, UQ>(A, A.cnt[CNT_FRONT + A.round % 3u], S, n_edges, n_relax, n_items);
     stage_flush_block<SCAP, B / 64>(S);
     unsigned long long v[4] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_items, n_edges};
     const int slot[4] = {ST_RELAX, ST_ATTEMPTS, ST_ITEMS, ST_EDGES};
@@ -497,7 +632,7 @@ __global__ __launch_bounds__(B) void push_kernel(TravArgs A)
 
 // Push round, part 2: every wave takes whole chunks (grid-stride over the
 // chunk list) and relaxes their edges UNR per lane at a time.
-template <bool SWEEP, int B>
+template <bool SWEEP, int B, bool UQ>
 __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsigned long long &n_edges,
                                             unsigned long long &n_relax)
 {
@@ -507,6 +642,34 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (B / 64);
     for (uint32_t c = blockIdx.x * (B / 64) + (threadIdx.x >> 6); c < C; c += waves) {
+        if (UQ) {
+            // the chunk's query, start and length are the same for the
+            // whole wavefront: scalars
+            const uint4 chv = A.chunks[c];
+            const uint32_t cq = __builtin_amdgcn_readfirstlane(chv.x);
+            const uint32_t c0 = __builtin_amdgcn_readfirstlane(chv.y);
+            const uint32_t cz = __builtin_amdgcn_readfirstlane(chv.z);
+            const QueryRow Q = query_row(A, cq, SWEEP);
+            const uint2 *rec = A.da + c0;
+            if (lane == 0) n_edges += cz;
+            for (uint32_t k0 = 0; k0 < cz; k0 += 64 * UNR) {
+                uint32_t v[UNR], a[UNR];
+                bool ok[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const uint32_t off = k0 + k * 64 + lane;
+                    ok[k] = off < cz;
+                    const uint2 dv = rec[ok[k] ? off : 0u];
+                    v[k] = dv.x;
+                    a[k] = dv.y;
+                }
+                unsigned long long bal[UNR];
+                uint32_t item[UNR];
+                relax_group_u<SWEEP>(A, Q, v, a, ok, bal, item, vol_cnt, n_relax);
+                stage_append(S, bal, item);
+            }
+            continue;
+        }
         const uint4 ch = A.chunks[c];
         const uint4 p = A.qp[ch.x];
         const uint2 fpq = A.fpar[ch.x];
@@ -534,13 +697,13 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
     }
 }
 
-template <bool SWEEP, int B>
+template <bool SWEEP, int B, bool UQ>
 __global__ __launch_bounds__(B) void chunk_kernel(TravArgs A)
 {
     __shared__ uint32_t s_stage[B / 64][SCAP];
     TStage S{s_stage[threadIdx.x >> 6], 0u, A.next, &A.cnt[CNT_FRONT + (A.round + 1u) % 3u]};
     unsigned long long n_edges = 0, n_relax = 0;
-    chunk_phase<SWEEP, B>(A, S, n_edges, n_relax);
+    chunk_phase<SWEEP, B, UQ>(A, S, n_edges, n_relax);
     stage_flush_block<SCAP, B / 64>(S);
     unsigned long long v[3] = {n_relax & 0xFFFFFFFFull, n_relax >> 32, n_edges};
     const int slot[3] = {ST_RELAX, ST_ATTEMPTS, ST_CHUNK_EDGES};
@@ -585,10 +748,10 @@ __global__ __launch_bounds__(TB) void persist_kernel(TravArgs A, uint32_t which0
         B.next = odd ? q0 : q1;
         B.dense = (A.nq == 1 && dense_div && (uint64_t)F * dense_div >= A.n) ? 1u : 0u;
         TStage S{s_stage[threadIdx.x >> 6], 0u, B.next, &A.cnt[CNT_FRONT + (r + 1u) % 3u]};
-        push_phase<SWEEP, TB>(B, F, S, n_edges, n_relax, n_items);
+        push_phase<SWEEP, TB, false>(B, F, S, n_edges, n_relax, n_items);
         stage_flush_block<SCAP, TB / 64>(S);
         grid_barrier(bar, spin_limit);
-        chunk_phase<SWEEP, TB>(B, S, n_cedges, n_relax);
+        chunk_phase<SWEEP, TB, false>(B, S, n_cedges, n_relax);
         stage_flush_block<SCAP, TB / 64>(S);
         grid_barrier(bar, spin_limit);
         ++r;
@@ -1372,21 +1535,39 @@ int run_rounds(kairos_graph *g, Slot *s, TravArgs A, uint32_t first_front, uint3
                 const int bs = wide ? 512 : TB;
                 const int sg = wide ? std::max(1, spec_grid / 2) : spec_grid;
                 const int cg = wide ? std::max(1, chunk_grid / 2) : chunk_grid;
-                const int pg = A.dense ? grid_cap(g->n, bs, sg) : (k == 0 ? grid_cap(F, bs, sg) : sg);
+                // one query without arrival codes: the push kernel relaxes
+                // through the query-uniform path, whose lighter register use
+                // would let twice the blocks share a CU; half the grid keeps
+                // the number in flight where the general kernel has it (more
+                // of them only contend for the same memory)
+                const bool up = A.nq == 1 && A.filt == nullptr;
+                const int sgp = up ? std::max(1, sg / 2) : sg;
+                const int pg = A.dense ? grid_cap(g->n, bs, sgp) : (k == 0 ? grid_cap(F, bs, sgp) : sgp);
                 if (levels)
                     hipLaunchKernelGGL(snapshot_kernel, dim3(k == 0 ? grid_cap(F, 256, spec_grid) : chunk_grid),
                                        dim3(256), 0, st, A);
                 prof_begin(g, st, &ev);
-                if (wide)
-                    hipLaunchKernelGGL((push_kernel<SWEEP, 512>), dim3(pg), dim3(512), 0, st, A);
+                if (wide && up)
+                    hipLaunchKernelGGL((push_kernel<SWEEP, 512, true>), dim3(pg), dim3(512), 0, st, A);
+                else if (wide)
+                    hipLaunchKernelGGL((push_kernel<SWEEP, 512, false>), dim3(pg), dim3(512), 0, st, A);
+                else if (up)
+                    hipLaunchKernelGGL((push_kernel<SWEEP, TB, true>), dim3(pg), dim3(TB), 0, st, A);
                 else
-                    hipLaunchKernelGGL((push_kernel<SWEEP, TB>), dim3(pg), dim3(TB), 0, st, A);
+                    hipLaunchKernelGGL((push_kernel<SWEEP, TB, false>), dim3(pg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_PUSH, ev);
                 prof_begin(g, st, &ev);
-                if (wide)
-                    hipLaunchKernelGGL((chunk_kernel<SWEEP, 512>), dim3(cg), dim3(512), 0, st, A);
+                // without arrival codes the chunk kernel takes the
+                // query-uniform relaxation (one query per chunk)
+                const bool uq = A.filt == nullptr;
+                if (wide && uq)
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, 512, true>), dim3(cg), dim3(512), 0, st, A);
+                else if (wide)
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, 512, false>), dim3(cg), dim3(512), 0, st, A);
+                else if (uq)
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, TB, true>), dim3(cg), dim3(TB), 0, st, A);
                 else
-                    hipLaunchKernelGGL((chunk_kernel<SWEEP, TB>), dim3(cg), dim3(TB), 0, st, A);
+                    hipLaunchKernelGGL((chunk_kernel<SWEEP, TB, false>), dim3(cg), dim3(TB), 0, st, A);
                 prof_end(g, st, KAIROS_K_CHUNK, ev);
             }
             KAIROS_HIP(hipGetLastError());
@@ -2234,10 +2415,10 @@ int multi_push_round(kairos_graph *g, MultiState *ms)
     A.stamp_val = ms->stamp_next++;
     hipEvent_t ev;
     prof_begin(g, ms->stream, &ev);
-    hipLaunchKernelGGL((push_kernel<true, TB>), dim3(std::max(1, g->num_cus * 8)), dim3(TB), 0, ms->stream, A);
+    hipLaunchKernelGGL((push_kernel<true, TB, false>), dim3(std::max(1, g->num_cus * 8)), dim3(TB), 0, ms->stream, A);
     prof_end(g, ms->stream, KAIROS_K_PUSH, ev);
     prof_begin(g, ms->stream, &ev);
-    hipLaunchKernelGGL((chunk_kernel<true, TB>), dim3(std::max(1, g->num_cus * 4)), dim3(TB), 0, ms->stream, A);
+    hipLaunchKernelGGL((chunk_kernel<true, TB, false>), dim3(std::max(1, g->num_cus * 4)), dim3(TB), 0, ms->stream, A);
     prof_end(g, ms->stream, KAIROS_K_CHUNK, ev);
     KAIROS_HIP(hipGetLastError());
     ms->round += 1;
