@@ -309,16 +309,23 @@ __device__ __forceinline__ QueryRow query_row(const TravArgs &A, uint32_t q, boo
 // no arrival codes: the query's values are scalars, slots are head ids into
 // its own rows, and runs of equal heads are found on 32-bit keys.  Same
 // steps and results as relax_group.
-template <bool SWEEP>
-__device__ __forceinline__ void relax_group_u(const TravArgs &A, const QueryRow &Q, const uint32_t (&v)[UNR],
-                                              uint32_t (&a)[UNR], bool (&ok)[UNR], unsigned long long (&bal)[UNR],
-                                              uint32_t (&item)[UNR], uint32_t *vol_cnt, unsigned long long &nrelax)
+// Stage 1: the window test and the heads' arrival reads.
+__device__ __forceinline__ void relax_load_u(const QueryRow &Q, const uint32_t (&v)[UNR], const uint32_t (&a)[UNR],
+                                             bool (&ok)[UNR], uint32_t (&cur)[UNR])
 {
-    uint32_t cur[UNR];
 #pragma unroll
     for (int k = 0; k < UNR; ++k) ok[k] = ok[k] && a[k] <= Q.tw;
 #pragma unroll
     for (int k = 0; k < UNR; ++k) cur[k] = arrival_of(Q.av, ok[k] ? v[k] : 0u);
+}
+
+// Stage 2: everything after the arrival reads.
+template <bool SWEEP>
+__device__ __forceinline__ void relax_apply_u(const TravArgs &A, const QueryRow &Q, const uint32_t (&v)[UNR],
+                                              uint32_t (&a)[UNR], bool (&ok)[UNR], const uint32_t (&cur)[UNR],
+                                              unsigned long long (&bal)[UNR], uint32_t (&item)[UNR],
+                                              uint32_t *vol_cnt, unsigned long long &nrelax)
+{
 #pragma unroll
     for (int k = 0; k < UNR; ++k) {
         ok[k] = ok[k] && a[k] < cur[k];
@@ -360,6 +367,16 @@ __device__ __forceinline__ void relax_group_u(const TravArgs &A, const QueryRow 
         for (int o = 32; o > 0; o >>= 1) vol += __shfl_xor(vol, o);
         if ((threadIdx.x & 63) == 0 && vol) atomicAdd(vol_cnt, vol);
     }
+}
+
+template <bool SWEEP>
+__device__ __forceinline__ void relax_group_u(const TravArgs &A, const QueryRow &Q, const uint32_t (&v)[UNR],
+                                              uint32_t (&a)[UNR], bool (&ok)[UNR], unsigned long long (&bal)[UNR],
+                                              uint32_t (&item)[UNR], uint32_t *vol_cnt, unsigned long long &nrelax)
+{
+    uint32_t cur[UNR];
+    relax_load_u(Q, v, a, ok, cur);
+    relax_apply_u<SWEEP>(A, Q, v, a, ok, cur, bal, item, vol_cnt, nrelax);
 }
 
 // Appends the group's entries to a frontier whose length lives in LDS (the
@@ -652,20 +669,38 @@ __device__ __forceinline__ void chunk_phase(const TravArgs &A, TStage &S, unsign
             const QueryRow Q = query_row(A, cq, SWEEP);
             const uint2 *rec = A.da + c0;
             if (lane == 0) n_edges += cz;
+            // the next group's records are requested while this group's
+            // arrival reads are in flight
+            uint2 r[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; ++k) {
+                const uint32_t off = k * 64 + lane;
+                r[k] = rec[off < cz ? off : 0u];
+            }
             for (uint32_t k0 = 0; k0 < cz; k0 += 64 * UNR) {
-                uint32_t v[UNR], a[UNR];
+                uint32_t v[UNR], a[UNR], cur[UNR];
                 bool ok[UNR];
 #pragma unroll
                 for (int k = 0; k < UNR; ++k) {
-                    const uint32_t off = k0 + k * 64 + lane;
-                    ok[k] = off < cz;
-                    const uint2 dv = rec[ok[k] ? off : 0u];
-                    v[k] = dv.x;
-                    a[k] = dv.y;
+                    ok[k] = k0 + k * 64 + lane < cz;
+                    v[k] = r[k].x;
+                    a[k] = r[k].y;
+                }
+                relax_load_u(Q, v, a, ok, cur);
+                // issued after all arrival reads (the scheduler may not mix
+                // them in: the in-order load counter would then make the
+                // arrival waits cover these too), and unconditional (past
+                // the end: the chunk's first record) for the same reason
+                __builtin_amdgcn_sched_barrier(0);
+                const uint32_t k1 = k0 + 64 * UNR;
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const uint32_t off = k1 + k * 64 + lane;
+                    r[k] = rec[off < cz ? off : 0u];
                 }
                 unsigned long long bal[UNR];
                 uint32_t item[UNR];
-                relax_group_u<SWEEP>(A, Q, v, a, ok, bal, item, vol_cnt, n_relax);
+                relax_apply_u<SWEEP>(A, Q, v, a, ok, cur, bal, item, vol_cnt, n_relax);
                 stage_append(S, bal, item);
             }
             continue;
