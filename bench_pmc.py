@@ -32,7 +32,8 @@ import sys
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["paper_2401_02563_amd/csrc/traverse.hip", "paper_2401_02563_amd/csrc/batch.hip",
                   "paper_2401_02563_amd/csrc/build.hip", "paper_2401_02563_amd/csrc/stage.h",
-                  "paper_2401_02563_amd/csrc/binned.h", "paper_2401_02563_amd/csrc/scan.h"]
+                  "paper_2401_02563_amd/csrc/binned.h", "paper_2401_02563_amd/csrc/scan.h",
+                  "paper_2401_02563_amd/csrc/sweep.h"]
 COPY_BYTES = 256 << 20
 # raw rocprofv3 output goes under this directory of the repository
 OUT_ROOT = os.environ.get("KAIROS_PROFILE_DIR", "profile_runs")

@@ -268,7 +268,11 @@ typedef struct kairos_tuning {
                                 once per 64 queries); 1: one thread per query
                                 and vertex, arrivals query-major; 2: vertex-major
                                 arrivals, (vertex, query) pairs dealt densely to
-                                threads                                         */
+                                threads; 3: sweep form -- every edge of a group's
+                                windows once, in departure order, a lane per
+                                query, slab by slab with fix-up passes (suits
+                                groups whose windows overlap; falls back to 2
+                                when a slab will not settle)                    */
     uint32_t tail_limit;     /* frontiers of at most this many entries run in one
                                 workgroup that loops over rounds without host
                                 round trips; 0 disables                          */
@@ -360,6 +364,10 @@ typedef struct kairos_profile {
     uint64_t rounds;             /* frontier rounds                            */
     uint64_t binned_edges;       /* out-edges claimed by destination-binned rounds */
     uint64_t binned_items;       /* frontier entries expanded by them          */
+    uint64_t sweep_slabs;        /* slabs of the batch sweep form (batch_layout 3) */
+    uint64_t sweep_passes;       /* its passes (pass 0 and fix-ups, all slabs)  */
+    uint64_t sweep_fix_edges;    /* out-edges relaxed by its fix-up passes      */
+    uint64_t sweep_fallbacks;    /* batches it handed to the lane-dense rounds  */
 } kairos_profile;
 
 int kairos_profile_enable(kairos_graph *g, int on);

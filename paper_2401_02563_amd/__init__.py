@@ -49,7 +49,8 @@ class kairos_profile(ctypes.Structure):
     _fields_ = [("launches", _u64 * 7), ("ms", ctypes.c_double * 7), ("edges_scanned", _u64),
                 ("chunk_edges", _u64), ("items", _u64), ("relaxations", _u64), ("relax_attempts", _u64), ("tail_edges", _u64),
                 ("tail_items", _u64), ("pull_edges", _u64),
-                ("pull_vertices", _u64), ("rounds", _u64), ("binned_edges", _u64), ("binned_items", _u64)]
+                ("pull_vertices", _u64), ("rounds", _u64), ("binned_edges", _u64), ("binned_items", _u64),
+                ("sweep_slabs", _u64), ("sweep_passes", _u64), ("sweep_fix_edges", _u64), ("sweep_fallbacks", _u64)]
 
 
 class kairos_index_view(ctypes.Structure):
@@ -345,7 +346,8 @@ def kairos_profile_read(g: Graph) -> dict:
     names = ["push", "pull", "init", "sort", "chunk", "tail", "binned"]
     d = {f"launches_{k}": p.launches[i] for i, k in enumerate(names)}
     d.update({f"ms_{k}": p.ms[i] for i, k in enumerate(names)})
-    for k in ("edges_scanned", "chunk_edges", "tail_edges", "tail_items", "items", "relaxations", "relax_attempts", "pull_edges", "pull_vertices", "rounds", "binned_edges", "binned_items"):
+    for k in ("edges_scanned", "chunk_edges", "tail_edges", "tail_items", "items", "relaxations", "relax_attempts", "pull_edges", "pull_vertices", "rounds", "binned_edges", "binned_items",
+              "sweep_slabs", "sweep_passes", "sweep_fix_edges", "sweep_fallbacks"):
         d[k] = getattr(p, k)
     return d
 

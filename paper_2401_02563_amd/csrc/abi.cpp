@@ -60,6 +60,7 @@ static void graph_release(kairos_graph *g)
     if (!g) return;
     graph_release(g->rev);
     release_duration_state(g);
+    dev_free(g->tsorted);
     for (Slot *s : g->free_slots) slot_destroy(s);
     for (Slot *s : g->batch_slots) slot_destroy(s);
     for (VBatch *b : g->vbatches) vbatch_destroy(b);
@@ -321,7 +322,8 @@ int kairos_earliest_arrival_batch(kairos_graph *g, uint32_t q, const uint32_t *s
             VBatch *vb = nullptr;
             int rc = vbatch_acquire(g, (k + 63) / 64, &vb);
             if (rc) return rc;
-            rc = run_vbatch(g, vb, k, src + b, t_alpha + b, t_omega + b, out + b * g->n);
+            rc = g->tuning.batch_layout == 3 ? run_vbatch_sweep(g, vb, k, src + b, t_alpha + b, t_omega + b, out + b * g->n)
+                                             : run_vbatch(g, vb, k, src + b, t_alpha + b, t_omega + b, out + b * g->n);
             if (rc == KAIROS_OK) {
                 vbatch_release(g, vb);
             } else {
@@ -372,7 +374,7 @@ int kairos_set_tuning(kairos_graph *g, const kairos_tuning *in)
     if (!g || !in) return KAIROS_ERR_INVALID;
     if ((in->block != 256 && in->block != 512) || in->chunk < 16 || in->split < 16 ||
         in->rounds_per_sync < 1 || in->rounds_per_sync > 64 || in->sweep_group < 1 || in->sweep_group > 64 ||
-        in->batch_layout > 2 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1 || in->run_dedupe > 1 ||
+        in->batch_layout > 3 || (in->arrival_filter != 0 && in->arrival_filter != 2 && in->arrival_filter != 4 && in->arrival_filter != 8) || in->batch_persistent > 1 || in->single_persistent > 1 || in->run_dedupe > 1 ||
         (in->binned != 0 && in->binned < 256))
         return KAIROS_ERR_INVALID;
     {
@@ -439,6 +441,11 @@ int kairos_profile_read(kairos_graph *g, kairos_profile *out)
     out->rounds = g->prof.rounds;
     out->binned_edges = g->prof.bin_edges;
     out->binned_items = g->prof.bin_items;
+    out->sweep_slabs = g->prof.sw_slabs;
+    out->sweep_passes = g->prof.sw_passes;
+    out->sweep_fix_edges = g->prof.sw_fix;
+    out->sweep_fallbacks = g->prof.sw_fallbacks;
+    g->prof.sw_slabs = g->prof.sw_passes = g->prof.sw_fix = g->prof.sw_fallbacks = 0;
     g->prof.edges = g->prof.chunk_edges = g->prof.tail_edges = g->prof.tail_items = g->prof.attempts = g->prof.items = g->prof.relax = g->prof.pull_edges = g->prof.pull_verts = 0;
     g->prof.rounds = 0;
     g->prof.bin_edges = g->prof.bin_items = 0;

@@ -214,7 +214,7 @@ extern "C" int kairos_autotune_form(kairos_graph *g, int form, uint32_t q, const
     };
     const std::vector<Axis> axes = {
         {&kairos_tuning::block, {256, 512}},
-        {&kairos_tuning::batch_layout, {0, 1, 2}},
+        {&kairos_tuning::batch_layout, {0, 1, 2, 3}},
         {&kairos_tuning::split, {64, 128, 256, 1024}},
         {&kairos_tuning::chunk, {128, 256, 512, 2048}},
         {&kairos_tuning::tail_limit, {0, 1024, 4096, 16384}},

@@ -21,9 +21,14 @@
 // once per group instead of once per query and the arrival reads coalesce,
 // which is where batching pays (the paper runs its 100 sources one after the
 // other, §6.1).
+//
+// The sweep form (batch_layout 3, sweep.h) reads every edge of a group's
+// windows once in departure order instead of following frontiers; it pays
+// where the group's windows overlap and the graph is large.
 
 #include "internal.h"
 #include "stage.h"
+#include "sweep.h"
 
 #include <algorithm>
 #include <cstdlib>
@@ -714,6 +719,10 @@ static int vbatch_alloc(kairos_graph *g, uint32_t groups, VBatch **out)
                            (g->m / std::max<uint32_t>(g->tuning.chunk, 64) +
                             g->m / std::max<uint32_t>(g->tuning.split, 64) + 1);
     b->chunk_cap = std::min<uint64_t>((uint64_t)groups * per_g, 1ull << 26);
+    // the sweep form's fix-up chunks of one pass: at most a slab's edges in
+    // chunks of SW_C plus one partial chunk per listed vertex
+    if (g->tuning.batch_layout == 3)
+        b->chunk_cap = std::max<uint64_t>(b->chunk_cap, std::min<uint64_t>(SWEEP_SLAB / SW_C + g->n + 64, 1ull << 26));
     b->range_cap = std::min<uint64_t>((uint64_t)groups * (g->m / std::max<uint32_t>(g->tuning.split, 64) + 1),
                                       1ull << 22);
     if (const char *cap = std::getenv("KAIROS_TEST_CHUNK_CAP")) {
@@ -909,6 +918,126 @@ int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, cons
         stats_sum_shards(raw.data(), h);
         prof_add_stats(g, h);
     }
+    return KAIROS_OK;
+}
+
+// The graph's departure-ordered edge records, built on first use.
+static int ensure_time_order(kairos_graph *g, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g->ts_mu);
+    if (g->tsorted || g->m == 0) return KAIROS_OK;
+    uint4 *ts = nullptr;
+    int rc = build_time_order(g, st, &ts);
+    if (rc == KAIROS_OK) g->tsorted = ts;
+    return rc;
+}
+
+// One group of the sweep form in one cooperative launch.  KAIROS_ERR_BUSY:
+// the launch was refused, or the group needs the lane-dense rounds (a
+// fix-up list overflowed or a slab would not settle); its rows are then
+// rewritten by the caller's fallback.
+static int sweep_group(kairos_graph *g, VBatch *b, uint32_t gi, uint32_t q0, uint32_t nq, hipStream_t st)
+{
+    const size_t n = g->n;
+    uint32_t *arr = b->arr + (size_t)gi * n * 64;
+    // the group's claim area (64 n words) holds the stamps (n words) and,
+    // 8-byte aligned after them, the per-vertex pass notes (2 n words)
+    uint32_t *stamp = b->done + (size_t)gi * n * 64;
+    unsigned long long *low = (unsigned long long *)(stamp + (n + 1) / 2 * 2);
+    int rc;
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    if ((rc = bfill(st, arr, n * 64, INF))) return rc;
+    if ((rc = bfill(st, stamp, n, 0u))) return rc;
+    if ((rc = bfill(st, (uint32_t *)low, 2 * n, 0xFFFFFFFFu))) return rc;
+    hipLaunchKernelGGL(sweep_init_kernel, dim3(1), dim3(64), 0, st, b->qw + (size_t)gi * 64, arr, b->h_q, q0, nq);
+    KAIROS_HIP(hipMemsetAsync(b->cnt, 0, 64 * 4, st));
+    KAIROS_HIP(hipMemsetAsync(b->bar, 0, BAR_WORDS * 4, st));
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel, SW_TB, 0) != hipSuccess || occ < 1) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    SwArgs S{};
+    S.E = g->tsorted;
+    S.m = g->m;
+    S.off = g->off_out;
+    S.tt = g->t_out;
+    S.da = g->da_out;
+    S.arr = arr;
+    S.qw = b->qw + (size_t)gi * 64;
+    S.stamp = stamp;
+    S.low = low;
+    S.list0 = b->queue[0];
+    S.list1 = b->queue[1];
+    S.chunks = b->chunks;
+    S.chunk_cap = (uint32_t)std::min<uint64_t>(b->chunk_cap, 0xFFFFFFF0u);
+    S.cnt = b->cnt;
+    S.bar = b->bar;
+    S.spin_limit = 1u << 24;  // about 4 s of polling: far beyond one phase
+    // slabs of about n / 4 records (2^14 .. 2^22, never more than n: a pass
+    // lists up to one head per record and a list holds n).  Larger slabs
+    // mean fewer pass-0 phases but longer chains inside a slab, i.e. more
+    // fix-up passes, each a few dependent memory round trips and two grid
+    // barriers; on the scale-24 graph (64 queries) n / 16, n / 8, n / 4 and
+    // n / 2 took 239, 207, 199 and 217 ms.
+    S.slab = std::min<uint32_t>(SWEEP_SLAB, std::max<uint32_t>(std::min<uint32_t>(1u << 14, g->n), g->n / 4));
+    S.max_passes = 1u << 12;
+    S.list_cap = (uint32_t)std::min<uint64_t>((uint64_t)b->groups * n + 64, 0xFFFFFFF0u);
+    const int grid = g->num_cus * std::min(occ, 4);
+    void *args[] = {&S};
+    prof_begin(g, st, &ev);
+    const hipError_t e = hipLaunchCooperativeKernel((const void *)sweep_kernel, dim3(grid), dim3(SW_TB), args, 0, st);
+    prof_end(g, st, KAIROS_K_PUSH, ev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return KAIROS_ERR_BUSY;
+    }
+    KAIROS_HIP(hipMemcpyAsync(b->h_pin, b->cnt, 64, hipMemcpyDeviceToHost, st));
+    KAIROS_HIP(hipStreamSynchronize(st));
+    if (b->h_pin[SWC_ABORT]) return KAIROS_ERR_DEVICE;
+    if (g->prof.on) {
+        std::lock_guard<std::mutex> lk(g->prof.mu);
+        g->prof.rounds += b->h_pin[SWC_PASSES];
+        g->prof.sw_slabs += b->h_pin[SWC_SLABS];
+        g->prof.sw_passes += b->h_pin[SWC_PASSES];
+        g->prof.sw_fix += b->h_pin[SWC_FIXEDGES];
+    }
+    return b->h_pin[SWC_OVER] ? KAIROS_ERR_BUSY : KAIROS_OK;
+}
+
+int run_vbatch_sweep(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, const uint32_t *ta,
+                     const uint32_t *tw, uint32_t *out)
+{
+    hipStream_t st = b->stream;
+    if (q > (size_t)b->groups * 64) return KAIROS_ERR_INVALID;
+    int rc = ensure_time_order(g, st);
+    if (rc) return rc;
+    const uint32_t groups = (q + 63) / 64;
+    uint4 *staging = b->h_q;
+    for (uint32_t i = 0; i < q; ++i) staging[i] = make_uint4(g->h_perm[src[i]], ta[i], tw[i], 0);
+    for (uint32_t gi = 0; gi < groups; ++gi) {
+        rc = sweep_group(g, b, gi, gi * 64, std::min<uint32_t>(64, q - gi * 64), st);
+        // a group the sweep could not settle, or a refused launch: the
+        // lane-dense rounds answer the whole batch (they rewrite every row)
+        if (rc == KAIROS_ERR_BUSY) {
+            if (g->prof.on) {
+                std::lock_guard<std::mutex> lk(g->prof.mu);
+                g->prof.sw_fallbacks += 1;
+            }
+            return run_vbatch(g, b, q, src, ta, tw, out);
+        }
+        if (rc) return rc;
+    }
+    hipEvent_t ev;
+    prof_begin(g, st, &ev);
+    hipLaunchKernelGGL(btranspose_kernel, dim3(gridc((uint64_t)((g->n + 63) / 64) * groups, 1, 16384)), dim3(256), 0,
+                       st, b->arr, out, g->perm, g->n, q, groups);
+    prof_end(g, st, KAIROS_K_INIT, ev);
+    KAIROS_HIP(hipGetLastError());
+    KAIROS_HIP(hipStreamSynchronize(st));
     return KAIROS_OK;
 }
 

@@ -634,4 +634,56 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
     return rc;
 }
 
+namespace {
+
+// Records {tail, head, t, a} of the out-index in its order, one wavefront
+// per tail.
+__global__ void out_records_kernel(const uint32_t *__restrict__ off_out, const uint32_t *__restrict__ t_out,
+                                   const uint2 *__restrict__ da_out, uint32_t n_live, uint4 *__restrict__ rec)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t u = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); u < n_live; u += waves)
+        for (uint32_t f = off_out[u] + lane; f < off_out[u + 1]; f += 64) {
+            const uint2 va = da_out[f];
+            rec[f] = make_uint4(u, va.x, t_out[f], va.y);
+        }
+}
+
+}  // namespace
+
+int build_time_order(kairos_graph *g, hipStream_t st, uint4 **out)
+{
+    const uint64_t m = g->m;
+    *out = nullptr;
+    if (m == 0) return KAIROS_OK;
+    uint64_t scratch = 0;
+    uint4 *a = (uint4 *)dev_alloc(sizeof(uint4) * m, nullptr);
+    uint4 *b = (uint4 *)dev_alloc(sizeof(uint4) * m, &scratch);
+    const uint64_t tiles = (m + STILE - 1) / STILE;
+    const uint32_t nblocks = (uint32_t)std::min<uint64_t>(tiles, 1024);
+    uint32_t *hist = (uint32_t *)dev_alloc(sizeof(uint32_t) * 256 * (size_t)nblocks + 64, &scratch);
+    int rc = a && b && hist ? KAIROS_OK : KAIROS_ERR_NOMEM;
+    if (rc == KAIROS_OK) {
+        hipLaunchKernelGGL(out_records_kernel, dim3(grid_for(g->n_live, 4, 16384)), dim3(256), 0, st, g->off_out,
+                           g->t_out, g->da_out, g->n_live, a);
+        if (hipGetLastError() != hipSuccess) rc = KAIROS_ERR_DEVICE;
+    }
+    if (rc == KAIROS_OK) {
+        // stable by departure; the out-index order breaks ties (tail, a, head)
+        std::vector<Pass> ps;
+        add_field(ps, F_T, bits_for(g->max_t), 0);
+        rc = run_passes(g, a, b, m, ps, hist, st);  // leaves the sorted records in `a`
+    }
+    if (hipStreamSynchronize(st) != hipSuccess && rc == KAIROS_OK) rc = KAIROS_ERR_DEVICE;
+    dev_free(b);
+    dev_free(hist);
+    if (rc != KAIROS_OK) {
+        dev_free(a);
+        return rc;
+    }
+    *out = a;
+    return KAIROS_OK;
+}
+
 }  // namespace kairos

@@ -111,6 +111,7 @@ struct ProfileAcc {
     double ms[KAIROS_K_COUNT] = {};
     uint64_t edges = 0, chunk_edges = 0, tail_edges = 0, tail_items = 0, attempts = 0, items = 0, relax = 0, pull_edges = 0, pull_verts = 0, rounds = 0;
     uint64_t bin_edges = 0, bin_items = 0;
+    uint64_t sw_slabs = 0, sw_passes = 0, sw_fix = 0, sw_fallbacks = 0;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> free_events;
     std::mutex mu;
@@ -159,6 +160,10 @@ struct kairos_graph {
     uint64_t o2i_bytes = 0;
     std::mutex sd_mu;
     std::vector<kairos::SDState *> sd_states;
+    // every edge {tail, head, t, a} (internal ids) in departure order, for
+    // the sweep form of batches (built on its first use)
+    uint4 *tsorted = nullptr;
+    std::mutex ts_mu;
 };
 
 namespace kairos {
@@ -166,6 +171,9 @@ namespace kairos {
 // build.hip
 int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const uint32_t *t,
                 const uint32_t *lam, hipStream_t st);
+// The graph's edges {tail, head, t, a} sorted by departure (stable on the
+// out-index order), in a new device array of m records (*out, null for m = 0).
+int build_time_order(kairos_graph *g, hipStream_t st, uint4 **out);
 
 // traverse.hip
 int slot_acquire(kairos_graph *g, uint32_t qcap, bool sweep, Slot **out);
@@ -204,6 +212,10 @@ void vbatch_release(kairos_graph *g, VBatch *b);
 void vbatch_destroy(VBatch *b);
 int run_vbatch(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, const uint32_t *ta,
                const uint32_t *tw, uint32_t *out);
+// The sweep form (batch_layout 3): every edge of the groups' windows in
+// departure order, one wavefront per edge and a lane per query.
+int run_vbatch_sweep(kairos_graph *g, VBatch *b, uint32_t q, const uint32_t *src, const uint32_t *ta,
+                     const uint32_t *tw, uint32_t *out);
 
 // Device state of a multi-slot round loop driven by the server (query
 // slots q in [0, qcap), query-major arrays of qcap*n words).

@@ -118,12 +118,15 @@ __device__ __forceinline__ void dedupe_runs32(bool &ok, uint32_t &a, uint32_t ke
 }
 
 // Per-wavefront output buffer of CAP entries in LDS.  `n` is wave-uniform.
+// Entries past `cap` in the global array are counted but not written (the
+// reader sees a length above cap and treats it as an overflow).
 template <int CAP>
 struct Stage {
     uint32_t *buf;       // this wavefront's CAP entries
     uint32_t n;          // entries held
     uint32_t *next;      // global frontier array
     uint32_t *next_cnt;  // its length counter
+    uint32_t cap = 0xFFFFFFFFu;
 };
 
 // Writes the buffer out at a range reserved with one atomicAdd.
@@ -136,7 +139,8 @@ __device__ __forceinline__ void stage_flush_wave(Stage<CAP> &S)
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(S.next_cnt, S.n);
     base = __shfl(base, 0);
-    for (uint32_t j = lane; j < S.n; j += 64) S.next[base + j] = S.buf[j];
+    for (uint32_t j = lane; j < S.n; j += 64)
+        if (base + j < S.cap) S.next[base + j] = S.buf[j];
     wave_sync();
     S.n = 0;
 }
@@ -182,7 +186,8 @@ __device__ __forceinline__ void stage_flush_block(Stage<CAP> &S)
     __syncthreads();
     uint32_t off = s_base;
     for (uint32_t i = 0; i < w; ++i) off += s_n[i];
-    for (uint32_t j = lane; j < S.n; j += 64) S.next[off + j] = S.buf[j];
+    for (uint32_t j = lane; j < S.n; j += 64)
+        if (off + j < S.cap) S.next[off + j] = S.buf[j];
     S.n = 0;
 }
 

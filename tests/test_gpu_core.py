@@ -284,7 +284,7 @@ def test_batch_rows_equal_single(which):
         assert np.array_equal(rows[q], O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
 
 
-@pytest.mark.parametrize("layout,persistent,dedupe", [(1, 0, 1), (2, 0, 1), (2, 1, 1), (2, 1, 0), (0, 0, 1)])
+@pytest.mark.parametrize("layout,persistent,dedupe", [(1, 0, 1), (2, 0, 1), (2, 1, 1), (2, 1, 0), (0, 0, 1), (3, 0, 1)])
 def test_batch_bursty_runs(layout, persistent, dedupe):
     """Bursty pairs put runs of edges into one head next to each other: the
     batch kernels with and without one atomic per run agree with the oracle."""
@@ -350,7 +350,7 @@ def test_build_rejects_bad_edges():
     G.free()
 
 
-@pytest.mark.parametrize("layout,persistent", [(0, 0), (1, 0), (2, 0), (2, 1)])
+@pytest.mark.parametrize("layout,persistent", [(0, 0), (1, 0), (2, 0), (2, 1), (3, 0)])
 def test_batch_layouts_ragged_groups(layout, persistent):
     """100 queries = one full and one ragged group of 64 lanes."""
     g, G, se = rmat16()
@@ -420,7 +420,7 @@ def test_chunk_list_overflow_paths():
             assert np.array_equal(ea_gpu(G, int(srcs[qi]), int(ta[qi]), int(tw[qi])),
                                   O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi]))
         out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
-        for layout in (0, 1, 2):
+        for layout in (0, 1, 2, 3):
             K.kairos_set_tuning(G, batch_layout=layout)
             K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
             rows = K.as_u32(out).reshape(len(srcs), g.n)
@@ -493,7 +493,7 @@ def test_dense_frontier_walk(dense):
         K.kairos_set_tuning(G, **old)
 
 
-@pytest.mark.parametrize("layout,persistent", [(1, 0), (2, 0), (2, 1), (0, 0)])
+@pytest.mark.parametrize("layout,persistent", [(1, 0), (2, 0), (2, 1), (0, 0), (3, 0)])
 def test_gappy_single_and_batch(layout, persistent):
     """Vertices without out-edges are never enqueued and vertices without
     in-edges sit in one block of ids: every query kind and batch layout still
@@ -581,5 +581,59 @@ def test_binned_rounds_scale20_full():
             print_case("binned full", q)
             assert np.array_equal(ea_gpu(G, int(srcs[q]), int(ta[q]), int(tw[q])),
                                   O.earliest_arrival(se, srcs[q], ta[q], tw[q])), q
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("which,count", [("uniform", 16), ("uniform", 130), ("rmat16", 64), ("bursty16", 40),
+                                         ("rmat_wide", 100)])
+def test_batch_sweep_form(which, count):
+    """The sweep form (every edge of the group's windows in departure order,
+    a lane per query, slabs fixed up by stamped passes) gives every row of
+    the batch bit for bit, on full and ragged groups, first-half and
+    log-uniform windows, duplicate sources; repeated calls reuse its state."""
+    g, G, se = {"uniform": uniform, "rmat16": rmat16, "bursty16": bursty16, "rmat_wide": rmat_wide}[which]()
+    name = {"uniform": "uniform-10k", "rmat16": "rmat20-32m", "bursty16": "bursty22-1b",
+            "rmat_wide": "rmat22-256m"}[which]
+    srcs, ta, tw = make_queries(name, g, count=count)
+    srcs[1] = srcs[0]  # a duplicate source with its own window
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, batch_layout=3)
+        out = torch.full((count * g.n,), 5, dtype=torch.int32, device="cuda")
+        for rep in range(2):
+            print_case("sweep batch", which, count, rep)
+            K.kairos_profile_enable(G, True)
+            K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+            prof = K.kairos_profile_read(G)
+            K.kairos_profile_enable(G, False)
+            # the sweep itself answered (no hand-over to the lane-dense rounds)
+            assert prof["sweep_slabs"] > 0 and prof["sweep_fallbacks"] == 0, prof
+            rows = K.as_u32(out).reshape(count, g.n)
+            for qi in range(count):
+                assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), (rep, qi)
+    finally:
+        K.kairos_set_tuning(G, **old)
+
+
+def test_batch_sweep_form_small_slabs_settle():
+    """Many fix-up passes: on the scale-16 R-MAT graph every slab of the
+    sweep form holds 2^20 records, i.e. the whole window in one slab, so
+    its chains are settled by fix-up passes alone (the profile shows more
+    passes than slabs) and the rows stay exact."""
+    g, G, se = rmat16()
+    srcs, ta, tw = make_queries("rmat20-32m", g, count=64)
+    old = K.kairos_get_tuning(G)
+    try:
+        K.kairos_set_tuning(G, batch_layout=3)
+        out = torch.empty(64 * g.n, dtype=torch.int32, device="cuda")
+        K.kairos_profile_enable(G, True)
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        prof = K.kairos_profile_read(G)
+        K.kairos_profile_enable(G, False)
+        assert prof["sweep_fallbacks"] == 0 and prof["sweep_passes"] > 2 * prof["sweep_slabs"], prof
+        rows = K.as_u32(out).reshape(64, g.n)
+        for qi in range(0, 64, 7):
+            assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
     finally:
         K.kairos_set_tuning(G, **old)
