@@ -239,6 +239,9 @@ def kernel_names(mode, tuning):
         # a binned round is timed as one unit: claim, scans, count, scatter, apply
         return {"push": push, "chunk": "chunk_kernel", "tail": "tail_kernel", "binned": "binned_round"}
     layout = tuning.get("batch_layout", 2)
+    if layout == 3:
+        # the sweep form: one cooperative launch per 64-query group
+        return {"push": "sweep_kernel"}
     if layout == 2 and tuning.get("batch_persistent"):
         return {"push": "hpersist_kernel", "chunk": "hchunk_kernel"}
     return {0: {"push": "bpush_kernel", "chunk": "bchunk_kernel"},
@@ -252,6 +255,10 @@ def roofline_from_profile(prof, mode, pairs, workload, tuning):
     edges = {"push": prof["edges_scanned"], "chunk": prof["chunk_edges"], "tail": prof.get("tail_edges", 0),
              "binned": prof.get("binned_edges", 0)}
     items = {"push": prof["items"], "chunk": 0, "tail": prof.get("tail_items", 0), "binned": prof.get("binned_items", 0)}
+    if names["push"] == "sweep_kernel":
+        # the sweep relaxes every edge of the groups' windows; it keeps no
+        # per-query counts, so its share is the whole traversal
+        edges["push"], items["push"] = max(1, pairs), 0
     if names["push"] in ("hpersist_kernel", "persist_kernel") and prof.get("launches_chunk", 0) == 0:
         # one launch runs both phases: its edges are the push and chunk counts
         edges["push"] += edges["chunk"]
