@@ -10,7 +10,9 @@
   departure / fastest / shortest duration of one query against the
   oracle's profile scans.
 * rmat22-256m (256-query batch) and rmat24-512m (single queries): eight rows
-  each by the EA certificate, two of them also against the oracle's scan.
+  each by the EA certificate, two of them also against the oracle's scan;
+  the scale-24 batch of 64 also in the sweep form, whose rows must equal
+  the checked single-query rows.
 
 The certificate (source at t_alpha, a witness edge for every reached
 vertex, no usable edge arriving earlier) is exact and needs no sorted copy
@@ -100,17 +102,20 @@ def _spread(k, count):
     return sorted(set(np.linspace(0, k - 1, count).round().astype(int).tolist()))
 
 
-@pytest.mark.parametrize("name,kind,cert_rows,scan_rows,sweep_rows", [
-    ("bursty22-1b", "single", 5, 2, 1),
-    ("rmat24-512m", "single", 8, 2, 0),
-    ("rmat22-256m", "batch", 8, 2, 0)])
-def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
+@pytest.mark.parametrize("name,kind,cert_rows,scan_rows,sweep_rows,sweep_form", [
+    ("bursty22-1b", "single", 5, 2, 1, False),
+    ("rmat24-512m", "single", 8, 2, 0, True),
+    ("rmat22-256m", "batch", 8, 2, 0, False)])
+def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows, sweep_form):
     """Earliest arrival at full size in the launch configuration the
     benchmark times (one query per call, or the whole batch in one call):
     `cert_rows` rows by the exact certificate, the first and the middle of
     them (`scan_rows`) also element by element against the oracle's scan
     with their traversed-edge counts; latest departure / fastest / shortest
-    duration of `sweep_rows` queries against the oracle's profile scans."""
+    duration of `sweep_rows` queries against the oracle's profile scans.
+    With `sweep_form`, the whole batch also runs in the sweep form (the
+    form the autotuner picks for it) and those rows must equal the checked
+    one-query rows bit for bit."""
     _C.clear()
     print(f"case: generating {name}", flush=True)
     g = make_graph(name)
@@ -138,6 +143,21 @@ def test_large_full_size(name, kind, cert_rows, scan_rows, sweep_rows):
             got[q] = K.as_u32(one)
             if q in scan:
                 counts[q] = K.kairos_traversed_edges(G, int(ta[q]), int(tw[q]), one)
+    if sweep_form:
+        print(f"case: {name} batch of {len(srcs)} in the sweep form", flush=True)
+        old = K.kairos_get_tuning(G)
+        K.kairos_set_tuning(G, batch_layout=3)
+        out = torch.empty(len(srcs) * g.n, dtype=torch.int32, device="cuda")
+        K.kairos_profile_enable(G, True)
+        K.kairos_earliest_arrival_batch(G, srcs, ta, tw, out)
+        prof = K.kairos_profile_read(G)
+        K.kairos_profile_enable(G, False)
+        K.kairos_set_tuning(G, **old)
+        assert prof["sweep_slabs"] > 0 and prof["sweep_fallbacks"] == 0, prof
+        view = out.view(len(srcs), g.n)
+        for q in rows:
+            assert np.array_equal(K.as_u32(view[q]), got[q]), q
+        del out, view
     sweeps = {}
     for q in range(1, 1 + sweep_rows):
         print(f"case: {name} latest departure / fastest of query {q}", flush=True)
