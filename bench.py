@@ -375,7 +375,10 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
     queries per rate.  The server first answers `warmup` other queries
     (closed loop, growing its slot pool).  Latency runs from the query's
     arrival time to its completion; queries wait on the client side while
-    all `pool` output buffers are in flight."""
+    all `pool` output buffers are in flight.  A sample of the served results
+    (every 500th query and the first of each kind) is copied out on
+    completion and compared, after the timed run, with the same queries
+    answered alone; a difference fails the run."""
     from workloads import make_queries, poisson_arrivals
     from workloads.configs import make_kinds
     total = count + warmup
@@ -399,6 +402,12 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
         arr = poisson_arrivals(rate, count, 105 + rate)
         free = list(range(pool))
         inflight = {}
+        sample_at = set(range(0, count, 500))
+        for kd in range(3):
+            hits = np.nonzero(kinds[warmup:] == kd)[0]
+            if len(hits):
+                sample_at.add(int(hits[0]))
+        samples = []
         lat = np.empty(count)
         done = 0
         i = 0
@@ -410,10 +419,12 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
                 b = free.pop()
                 q = warmup + i
                 tk = K.kairos_server_submit(srv, int(kinds[q]), int(srcs[q]), int(ta[q]), int(tw[q]), outs[b])
-                inflight[tk] = (b, arr[i])
+                inflight[tk] = (b, arr[i], i)
                 i += 1
             for c in K.kairos_server_poll(srv, 4096):
-                b, a = inflight.pop(c["ticket"])
+                b, a, idx = inflight.pop(c["ticket"])
+                if idx in sample_at:
+                    samples.append((warmup + idx, outs[b].clone()))
                 free.append(b)
                 lat[done] = (c["t_done_ns"] - start) * 1e-9 - a
                 last = max(last, c["t_done_ns"])
@@ -432,8 +443,14 @@ def serve_sweep(K, torch, G, g, name, rates=(1000, 2000, 5000, 10000, 20000, 500
             fns[kinds[q]](G, int(srcs[q]), int(ta[q]), int(tw[q]), outs[0])
             clock += time.perf_counter() - t
             fifo_lat.append(clock - arr[j])
+        # served results against the same queries alone (untimed)
+        for q, got in samples:
+            fns[kinds[q]](G, int(srcs[q]), int(ta[q]), int(tw[q]), outs[0])
+            if not torch.equal(got, outs[0]):
+                raise RuntimeError(f"served result of query {q} (kind {int(kinds[q])}) differs from the query alone")
         fl = np.array(fifo_lat) if fifo_lat else np.zeros(1)
         res.append({"rate": rate, "queries": count, "warmup": warmup, "served_qps": count / wall,
+                    "checked_against_alone": len(samples),
                     "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                     "fifo_qps": float(n_fifo / clock) if clock > 0 else None,
                     "fifo_p50_ms": float(np.percentile(fl, 50) * 1e3) if n_fifo else None,
