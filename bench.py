@@ -56,7 +56,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve", action="store_true", help="also run the serving sweep")
-    ap.add_argument("--extras", action="store_true", help="also time LD/F and one-at-a-time EA")
+    ap.add_argument("--extras", action="store_true", default=True,
+                    help="also time the batch against one query per call, LD/F, paths, BFS (the default)")
+    ap.add_argument("--no-extras", dest="extras", action="store_false", help="skip those timings")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
     return ap.parse_args()
 

@@ -65,7 +65,9 @@ def run(argv):
     env = dict(os.environ, TMPDIR="/tmp", KAIROS_CALIBRATION_COPY="1")
     with open(os.path.join(out, "args.json"), "w") as f:
         json.dump(argv, f)  # the summary quotes the exact command
-    bench = [sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu", *argv]
+    # the timed earliest-arrival step only: the extra timings would mix other
+    # query kinds into the per-kernel averages
+    bench = [sys.executable, os.path.join(ROOT, "bench.py"), "--no-cpu", "--no-extras", *argv]
     passes = [("trace", ["--kernel-trace", "--stats"]), ("fetch", ["--pmc", "FETCH_SIZE"]),
               ("write", ["--pmc", "WRITE_SIZE"])]
     exits = {}
@@ -146,7 +148,7 @@ def summarize(outdir, workload="bursty22-1b", mode="single"):
     argv = ["--workload", workload, "--mode", mode, "--steps", "3", "--warmup", "1"]
     if os.path.exists(os.path.join(outdir, "args.json")):
         argv = json.load(open(os.path.join(outdir, "args.json")))
-    b = " ".join(["--no-cpu", *argv])
+    b = " ".join(["--no-cpu", "--no-extras", *argv])
     lines = [f"# rocprofv3 summary: bench.py workload {workload}, mode {mode}",
              "",
              "commands (from the repository root, on the GPU host; raw output under",
