@@ -31,46 +31,6 @@ __device__ __forceinline__ uint64_t lanes_below()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Lanes of a wavefront that hold edges into the same (query, vertex) slot
-// in a row -- a burst of one tail's adjacency -- need one atomic between
-// them: a segmented minimum over each run leaves the run's least arrival in
-// its last lane and drops the others' edges (none of them can beat it).
-// `key` is the slot; a lane without an edge is a run of its own.  Every lane
-// of the wavefront must call this (it shuffles); without runs longer than
-// one lane it returns after one ballot.
-__device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
-{
-    // most edge groups improve nothing (their arrivals are not below the
-    // heads' words): one ballot settles those
-    if (__ballot(ok) == 0ull) return;
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t kk = ok ? key : ~(uint64_t)lane;
-    // shuffles run with every lane active: a shuffle inside a short-circuit
-    // (lane == 0 || ...) would read a lane switched off for it
-    const uint64_t up = __shfl_up(kk, 1);
-    const uint64_t dn = __shfl_down(kk, 1);
-    const bool head = lane == 0 || up != kk;
-    if (__ballot(!head) == 0ull) return;
-    uint32_t mv = ok ? a : 0xFFFFFFFFu;
-    int f = head ? 1 : 0;  // the scan has reached the run's first lane
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t mo = __shfl_up(mv, o);
-        const int fo = __shfl_up(f, o);
-        if (lane >= (uint32_t)o && !f) {
-            mv = min(mv, mo);
-            f = fo;
-        }
-    }
-    const bool last = lane == 63 || dn != kk;
-    if (ok) {
-        if (last)
-            a = mv;
-        else
-            ok = false;
-    }
-}
-
-
 // One step of a key-gated inclusive min-scan over the wavefront: mv takes
 // the minimum with the value of the lane CTRL names (a DPP row shift or row
 // broadcast, rows ROWS written) when that lane holds the same key.  Lanes
@@ -81,6 +41,53 @@ __device__ __forceinline__ void gated_min_step(uint32_t &mv, uint32_t key)
     const uint32_t ms = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)mv, CTRL, ROWS, 0xF, false);
     const uint32_t ks = (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, CTRL, ROWS, 0xF, false);
     if (ks == key) mv = min(mv, ms);
+}
+
+// gated_min_step with a 64-bit key given as two halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void gated_min_step2(uint32_t &mv, uint32_t klo, uint32_t khi)
+{
+    const uint32_t ms = (uint32_t)__builtin_amdgcn_update_dpp((int)0xFFFFFFFF, (int)mv, CTRL, ROWS, 0xF, false);
+    const uint32_t sl = (uint32_t)__builtin_amdgcn_update_dpp((int)klo, (int)klo, CTRL, ROWS, 0xF, false);
+    const uint32_t sh = (uint32_t)__builtin_amdgcn_update_dpp((int)khi, (int)khi, CTRL, ROWS, 0xF, false);
+    if (sl == klo && sh == khi) mv = min(mv, ms);
+}
+
+// Lanes of a wavefront that hold edges into the same (query, vertex) slot
+// in a row -- a burst of one tail's adjacency -- need one atomic between
+// them: a segmented minimum over each run leaves the run's least arrival in
+// its last lane and drops the others' edges (none of them can beat it).
+// `key` is the slot; a lane without an edge is a run of its own.  The
+// minimum is the key-gated DPP scan of dedupe_runs32 below on the two
+// halves of the key (a window may also take in an earlier run into the same
+// slot, which only lowers the survivor to another of this group's arrivals
+// for it).  Every lane of the wavefront must call this; without runs
+// longer than one lane it returns after two ballots.
+__device__ __forceinline__ void dedupe_runs(bool &ok, uint32_t &a, uint64_t key)
+{
+    // most edge groups improve nothing (their arrivals are not below the
+    // heads' words): one ballot settles those
+    const uint64_t m = __ballot(ok);
+    if (m == 0ull) return;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t klo = (uint32_t)key, khi = (uint32_t)(key >> 32);
+    const uint32_t dlo = __shfl_down(klo, 1), dhi = __shfl_down(khi, 1);
+    const bool ok_dn = lane < 63 && ((m >> (lane + 1)) & 1ull);
+    const bool last = !ok_dn || dlo != klo || dhi != khi;
+    if (__ballot(ok && !last) == 0ull) return;  // no run longer than one lane
+    uint32_t mv = ok ? a : 0xFFFFFFFFu;
+    gated_min_step2<0x111, 0xF>(mv, klo, khi);  // row_shr:1
+    gated_min_step2<0x112, 0xF>(mv, klo, khi);  // row_shr:2
+    gated_min_step2<0x114, 0xF>(mv, klo, khi);  // row_shr:4
+    gated_min_step2<0x118, 0xF>(mv, klo, khi);  // row_shr:8
+    gated_min_step2<0x142, 0xA>(mv, klo, khi);  // row_bcast:15
+    gated_min_step2<0x143, 0xC>(mv, klo, khi);  // row_bcast:31
+    if (ok) {
+        if (last)
+            a = mv;
+        else
+            ok = false;
+    }
 }
 
 // dedupe_runs for lanes that all relax edges of one query: the slot is the
