@@ -275,18 +275,24 @@ __device__ __forceinline__ uint32_t nth_set_bit(unsigned long long m, uint32_t j
 // Relax HU edges per lane: arrival-row reads, atomic minima and head-mask ORs
 // are each issued together.  Heads whose mask was empty go to the next
 // frontier through the wavefront's staging buffer.
-__device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, unsigned long long &n_relax)
+// Stage 1 of hrelax: the window test and the heads' arrival reads
+// (unconditional loads from valid addresses, so nothing forces a wait
+// between the HU requests).
+__device__ __forceinline__ void hrelax_load(const BArgs &A, HGroup &H, size_t (&idx)[HU], uint32_t (&cur)[HU])
 {
-    // unconditional loads from valid addresses, predicated atomics without
-    // default values: nothing forces a wait between the HU requests
-    size_t idx[HU];
-    uint32_t cur[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
         H.ok[k] = H.ok[k] && H.a[k] <= H.tw[k];
         idx[k] = ((size_t)H.row[k] + H.v[k]) * 64 + H.bit[k];
         cur[k] = A.arr[H.ok[k] ? idx[k] : 0];
     }
+}
+
+// Stage 2: run dedupe, atomic minima, head-mask ORs and staging
+// (predicated atomics without default values).
+__device__ __forceinline__ void hrelax_apply(const BArgs &A, HGroup &H, const size_t (&idx)[HU],
+                                             const uint32_t (&cur)[HU], BStage &S, unsigned long long &n_relax)
+{
     uint32_t old[HU];
 #pragma unroll
     for (int k = 0; k < HU; ++k) {
@@ -312,6 +318,14 @@ __device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, uns
         head[k] = H.row[k] + H.v[k];
     }
     stage_append(S, bal, head);
+}
+
+__device__ __forceinline__ void hrelax(const BArgs &A, HGroup &H, BStage &S, unsigned long long &n_relax)
+{
+    size_t idx[HU];
+    uint32_t cur[HU];
+    hrelax_load(A, H, idx, cur);
+    hrelax_apply(A, H, idx, cur, S, n_relax);
 }
 
 // Expansion of one round's F frontier entries by the whole grid (every
@@ -519,20 +533,39 @@ __device__ __forceinline__ void hchunk_phase(const BArgs &A, BStage &S, unsigned
         const uint32_t g = ch.x / A.n;
         const uint32_t tw = A.qw[(size_t)g * 64 + ch.y].y;
         if (lane == 0) n_edges += ch.w;
+        // a chunk is one (query, vertex) pair's: the next group's records
+        // are requested while this group's arrival reads are in flight
+        uint2 r[HU];
+#pragma unroll
+        for (int k = 0; k < HU; ++k) {
+            const uint32_t off = k * 64 + lane;
+            r[k] = A.da[ch.z + (off < ch.w ? off : 0u)];
+        }
         for (uint32_t k0 = 0; k0 < ch.w; k0 += 64 * HU) {
             HGroup H;
 #pragma unroll
             for (int k = 0; k < HU; ++k) {
-                const uint32_t off = k0 + k * 64 + lane;
-                H.ok[k] = off < ch.w;
-                const uint2 dv = A.da[H.ok[k] ? ch.z + off : 0u];
-                H.v[k] = dv.x;
-                H.a[k] = dv.y;
+                H.ok[k] = k0 + k * 64 + lane < ch.w;
+                H.v[k] = r[k].x;
+                H.a[k] = r[k].y;
                 H.row[k] = g * A.n;
                 H.bit[k] = ch.y;
                 H.tw[k] = tw;
             }
-            hrelax(A, H, S, n_relax);
+            size_t idx[HU];
+            uint32_t cur[HU];
+            hrelax_load(A, H, idx, cur);
+            // after all arrival reads, unconditional (past the end: the
+            // chunk's first record), so the waits for those reads do not
+            // cover these
+            __builtin_amdgcn_sched_barrier(0);
+            const uint32_t k1 = k0 + 64 * HU;
+#pragma unroll
+            for (int k = 0; k < HU; ++k) {
+                const uint32_t off = k1 + k * 64 + lane;
+                r[k] = A.da[ch.z + (off < ch.w ? off : 0u)];
+            }
+            hrelax_apply(A, H, idx, cur, S, n_relax);
         }
     }
 }
