@@ -2,10 +2,10 @@
 //
 // The group's 64 queries share one pass over the graph's edges in departure
 // order, as the one-pass scan of §7's temporal-paths reference takes them
-// for one query: a wavefront holds one edge at a time and lane q relaxes it
-// for query q against the arrival rows of its tail and head (64 words of 4
-// bytes each, so a row is two cache lines read by one instruction).  Edge
-// records are read once for the whole group instead of once per query.
+// for one query: a wavefront holds a few edges at a time and lane q relaxes
+// each for query q against the arrival rows of its tail and head (64 words
+// of 4 bytes each, so a row is two cache lines read by one instruction).
+// Edge records are read once for the whole group instead of once per query.
 //
 // The edges of the group's range [lo, hi) (departures in [min t_alpha,
 // max t_omega)) are cut into slabs of `slab` consecutive records, taken in
@@ -13,12 +13,13 @@
 // later slab can enable an edge of an earlier one, and a slab relaxed to a
 // fixpoint stays final.  Inside a slab every edge is relaxed at once (pass
 // 0), which can miss an edge whose tail is lowered by another edge of the
-// same slab.  Every vertex lowered in a pass is listed (a stamp per vertex
-// lists it once), and the next pass re-relaxes, through the out-index, the
-// listed vertices' out-edges departing inside the slab's time range, for
-// all lanes; passes repeat until one lowers nothing.  Edges departing at the
-// slab's last time may belong to the next slab: relaxing them early with a
-// real arrival is harmless.
+// same slab.  Every vertex lowered in a pass is listed, with a note of the
+// least arrival the pass wrote into its row, and the next pass re-relaxes,
+// through the out-index, each listed vertex's out-edges that depart from
+// that arrival to the slab's last departure, for all lanes (a vertex listed
+// twice is expanded once); passes repeat until one lowers nothing.  Edges
+// departing at the slab's last time may belong to the next slab: relaxing
+// them early with a real arrival is harmless.
 //
 // One cooperative launch runs all slabs and passes of a group, with grid
 // barriers between phases; every block reads the same counters after a
@@ -65,19 +66,6 @@ struct SwArgs {
     uint32_t max_passes;
     uint32_t list_cap;       // entries each list holds; a longer list is an overflow
 };
-
-__device__ __forceinline__ uint32_t sw_lower_bound(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi,
-                                                   uint32_t key)
-{
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
 
 // [lo, hi): the records departing in [min t_alpha, max t_omega) of the
 // group (an edge departing at t_omega or later arrives after it).
@@ -185,10 +173,11 @@ __device__ __forceinline__ void sweep_pass0(const SwArgs &S, uint64_t s0, uint64
 // Fix-up expansion: lane per listed vertex; chunks of its out-edges that
 // depart in [max(a, t_lo), t_hi], a the least arrival the listing pass
 // wrote into the vertex's row (earlier departures cannot use any arrival
-// that pass wrote, and arrivals written before it were expanded already).  A vertex listed
-// more than once is expanded once: the stamp names the last expansion that
-// took it (a plain read and write; two lanes racing on one vertex only
-// expand it twice, which repeats work and changes no result).
+// that pass wrote, and arrivals written before it were expanded already).
+// A vertex listed more than once is expanded once: the stamp names the
+// last expansion that took it (a plain read and write; two lanes racing on
+// one vertex only expand it twice, which repeats work and changes no
+// result).
 __device__ __forceinline__ void sweep_expand(const SwArgs &S, const uint32_t *list, uint32_t L, uint32_t t_lo,
                                              uint32_t t_hi, uint32_t pid, uint32_t listed_by, uint32_t *chunk_cnt)
 {
