@@ -60,6 +60,8 @@ def parse():
                     help="also time the batch against one query per call, LD/F, paths, BFS (the default)")
     ap.add_argument("--no-extras", dest="extras", action="store_false", help="skip those timings")
     ap.add_argument("--tune", action="store_true", help="autotune before timing")
+    ap.add_argument("--layout", type=int, choices=[0, 1, 2, 3], default=None,
+                    help="batch layout to time (3: the sweep form); default: the library's")
     return ap.parse_args()
 
 
@@ -92,6 +94,8 @@ def main():
     one = torch.empty(g.n, dtype=torch.int32, device="cuda")
 
     tune_note = None
+    if args.layout is not None:
+        K.kairos_set_tuning(G, batch_layout=args.layout)
     if args.tune:
         # held-out queries of the workload's recipe (another seed), in the
         # timed work's shape: a batch as large as the timed one, or a few
@@ -195,7 +199,7 @@ def main():
         "traversed_edges_per_step": etrav_total, "numerator": numerator,
         "rounds_per_step": prof["rounds"] / args.steps,
         "roofline": roofline, "cpu_baseline": cpu,
-        "tuning": {"source": "autotuner" if args.tune else "defaults", **({"tuned": tune_note} if tune_note else {}),
+        "tuning": {"source": "autotuner" if args.tune else ("layout given" if args.layout is not None else "defaults"), **({"tuned": tune_note} if tune_note else {}),
                    **{k: tuning[k] for k in ("block", "batch_layout", "batch_persistent", "single_persistent",
                                              "rounds_per_sync", "tail_limit", "split", "chunk", "pull_alpha",
                                              "pull_beta", "dense_frontier", "arrival_filter", "run_dedupe",
