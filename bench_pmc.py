@@ -30,6 +30,8 @@ import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# the kernels the profiled workloads run (the small-graph kernel of tiny.hip
+# serves graphs of at most 10,240 vertices, none of them)
 KERNEL_SOURCES = ["paper_2401_02563_amd/csrc/traverse.hip", "paper_2401_02563_amd/csrc/batch.hip",
                   "paper_2401_02563_amd/csrc/build.hip", "paper_2401_02563_amd/csrc/stage.h",
                   "paper_2401_02563_amd/csrc/binned.h", "paper_2401_02563_amd/csrc/scan.h",

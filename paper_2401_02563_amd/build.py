@@ -16,7 +16,8 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KAIROS_ARCH", "gfx950")
 
-SOURCES = ["build.hip", "traverse.hip", "batch.hip", "duration.hip", "noalloc.hip", "abi.cpp", "server.cpp", "autotune.cpp"]
+SOURCES = ["build.hip", "traverse.hip", "batch.hip", "duration.hip", "noalloc.hip", "tiny.hip", "abi.cpp", "server.cpp",
+           "autotune.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-result", "-Wno-unused-command-line-argument",

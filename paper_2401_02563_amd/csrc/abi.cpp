@@ -205,7 +205,11 @@ static int single_query(kairos_graph *g, int kind, uint32_t src, uint32_t ta, ui
     Slot *s = nullptr;
     if ((rc = slot_acquire(g, 1, kind == 1 || kind == 2, &s))) return rc;
     switch (kind) {
-    case 0: rc = run_earliest_arrival(g, s, src, ta, tw, out, strict); break;
+    case 0:
+        // small graphs: the whole query in one workgroup with its state in LDS
+        rc = tiny_eligible(g) ? run_tiny_earliest_arrival(g, s, src, ta, tw, out, strict)
+                              : run_earliest_arrival(g, s, src, ta, tw, out, strict);
+        break;
     case 3: rc = run_earliest_arrival_path(g, s, src, ta, tw, out, out2, out3); break;
     case 4: rc = run_temporal_bfs(g, s, src, ta, tw, out, strict); break;
     default: rc = run_sweep(g, s, kind, src, ta, tw, out, strict); break;

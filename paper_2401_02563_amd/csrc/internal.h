@@ -86,7 +86,9 @@ enum : int {
 };
 enum : int {
     ST_EDGES = 0, ST_ITEMS = 1, ST_RELAX = 2, ST_PULL_EDGES = 3, ST_PULL_VERTS = 4, ST_CHUNK_EDGES = 5, ST_ATTEMPTS = 6,
-    ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_BIN_EDGES = 9, ST_BIN_ITEMS = 10, ST_WORDS = 16
+    ST_TAIL_EDGES = 7, ST_TAIL_ITEMS = 8, ST_BIN_EDGES = 9, ST_BIN_ITEMS = 10,
+    ST_ROUNDS = 11,  // rounds run inside a kernel (the small-graph kernel)
+    ST_WORDS = 16
 };
 // The work counters are kept in ST_SHARDS copies (a block adds to copy
 // blockIdx % ST_SHARDS, so concurrent additions hit different addresses),
@@ -174,6 +176,13 @@ int build_index(kairos_graph *g, const uint32_t *src, const uint32_t *dst, const
 // The graph's edges {tail, head, t, a} sorted by departure (stable on the
 // out-index order), in a new device array of m records (*out, null for m = 0).
 int build_time_order(kairos_graph *g, hipStream_t st, uint4 **out);
+
+// tiny.hip: one earliest-arrival query in one workgroup with its state in
+// LDS, for graphs of at most TINY_N vertices (12 bytes of LDS per vertex)
+constexpr uint32_t TINY_N = 10240;
+bool tiny_eligible(const kairos_graph *g);
+int run_tiny_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t ta, uint32_t tw, uint32_t *out,
+                              bool strict);
 
 // traverse.hip
 int slot_acquire(kairos_graph *g, uint32_t qcap, bool sweep, Slot **out);

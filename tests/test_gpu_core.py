@@ -637,3 +637,43 @@ def test_batch_sweep_form_small_slabs_settle():
             assert np.array_equal(rows[qi], O.earliest_arrival(se, srcs[qi], ta[qi], tw[qi])), qi
     finally:
         K.kairos_set_tuning(G, **old)
+
+
+@pytest.mark.parametrize("n", [10240, 10241])
+def test_small_graph_kernel(n):
+    """Graphs of at most 10,240 vertices answer a single earliest-arrival
+    query in one workgroup with the query state in LDS (one launch, no
+    push / chunk rounds); one vertex more takes the general rounds.  Both
+    give the oracle's rows, with and without "Strictly succeeds", and the
+    LDS kernel equals the general one-workgroup rounds (tail_limit 0 turns
+    it off) on the same graph."""
+    from workloads.gen import uniform_graph
+    g = uniform_graph(n, 6 * n, 77, 0, 20000, 1, 10)
+    G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (g.src, g.dst, g.t, g.lam)], g.n)
+    se = O.sort_by_departure(g.n, g.src, g.dst, g.t, g.lam)
+    rng = np.random.default_rng(n)
+    srcs = rng.integers(0, n, 6)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    old = K.kairos_get_tuning(G)
+    try:
+        for i, s in enumerate(srcs.tolist()):
+            a, w = int(rng.integers(0, 5000)), int(rng.integers(10000, 20001))
+            print_case("small graph kernel", n, s, a, w)
+            K.kairos_profile_enable(G, True)
+            K.kairos_earliest_arrival(G, s, a, w, out)
+            prof = K.kairos_profile_read(G)
+            K.kairos_profile_enable(G, False)
+            got = K.as_u32(out).copy()
+            assert np.array_equal(got, O.earliest_arrival(se, s, a, w)), (s, a, w)
+            if n <= 10240:
+                assert prof["launches_tail"] == 1 and prof["launches_push"] == 0, prof
+            K.kairos_set_tuning(G, tail_limit=0)
+            assert np.array_equal(ea_gpu(G, s, a, w), got)
+            K.kairos_set_tuning(G, **old)
+            strict = K.as_u32(K.kairos_query(G, 0, s, a, w, out, strict=True)).copy()
+            K.kairos_set_tuning(G, tail_limit=0)
+            assert np.array_equal(K.as_u32(K.kairos_query(G, 0, s, a, w, out, strict=True)), strict)
+            K.kairos_set_tuning(G, **old)
+    finally:
+        K.kairos_set_tuning(G, **old)
+        G.free()
