@@ -202,6 +202,8 @@ int run_tiny_earliest_arrival(kairos_graph *g, Slot *s, uint32_t src, uint32_t t
         KAIROS_HIP(hipMemsetAsync(s->stats, 0, raw.size() * 8, st));
         stats_sum_shards(raw.data(), h);
         prof_add_stats(g, h);
+        std::lock_guard<std::mutex> lk(g->prof.mu);
+        g->prof.rounds += h[ST_ROUNDS];
     }
     return KAIROS_OK;
 }

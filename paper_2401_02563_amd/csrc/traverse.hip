@@ -1802,7 +1802,6 @@ void prof_add_stats(kairos_graph *g, const unsigned long long *h)
     g->prof.pull_verts += h[ST_PULL_VERTS];
     g->prof.bin_edges += h[ST_BIN_EDGES];
     g->prof.bin_items += h[ST_BIN_ITEMS];
-    g->prof.rounds += h[ST_ROUNDS];
 }
 
 // ---------------------------------------------------------------- slots --
