@@ -14,16 +14,20 @@
 //
 // Label-correcting rounds.  A relaxation that lowers pm at position k of w's
 // in-list widens w's dirty range [lo, hi] for the next round and enqueues w
-// once.  Expanding v redoes the prefix minimum from lo; past hi the stored
-// values are the previous prefix minima, so the scan stops at the first
-// position past hi whose value does not change, `stop`.  D_v changed exactly
-// on departures in [a_lo, a_stop), so only v's out-edges departing in that
-// interval are relaxed again.  Every value is the duration of a real path
-// and values only decrease, so a stale read costs work, never a wrong
-// result.  The source's D is 0 from t_alpha on: its usable out-edges are
+// once.  Expanding v redoes the prefix minimum over [lo, hi]; with C its
+// value at hi, the new value at k > hi is min(C, pm[k]), because an expanded
+// list is non-increasing and nothing past hi was lowered since.  So the
+// values past hi change exactly up to `stop`, the first position past hi
+// holding at most C (a binary search), and there they all become C.  D_v
+// changed exactly on departures in [a_lo, a_stop), so only v's out-edges
+// departing in that interval are relaxed again.  Dirty ranges longer than
+// SD_BIG are expanded by a whole workgroup instead of a wavefront.  Every
+// value is the duration of a real path and values only decrease, so a stale
+// read costs work, never a wrong result.  The source's D is 0 from t_alpha on: its usable out-edges are
 // relaxed once at the start with their own lambda, and it is never expanded.
-// When no vertex is left to expand, the result for v is the minimum of pm
-// over v's in-list.
+// When no vertex is left to expand, every vertex with out-edges has a
+// non-increasing list, whose minimum is its last label; the others (never
+// expanded) take the minimum over the list.
 
 #include "internal.h"
 #include "scan.h"
@@ -39,6 +43,7 @@ struct SDState {
     uint32_t *dhi[2] = {nullptr, nullptr};          // n each: dirty range end (inclusive)
     uint32_t *queue[2] = {nullptr, nullptr};        // n each: frontier vertices
     uint4 *rng = nullptr;                           // n: {v, first out-edge, count, lo}
+    uint32_t *big = nullptr;                        // n: frontier indices whose dirty range a workgroup expands
     uint32_t *rstop = nullptr;                      // n: first in-position past the change
     uint32_t *base = nullptr;                       // n + 1: out-edge counts, then their exclusive scan
     uint32_t *bsum = nullptr;                       // block sums of the scan
@@ -51,8 +56,11 @@ struct SDState {
 namespace {
 
 constexpr int SDT = 256;                  // threads per block
-// counters: frontier sizes of the two parities, relax total
-enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_CNT_WORDS = 4 };
+constexpr int SDB = 1024;                 // threads of a workgroup expanding one long dirty range
+constexpr int SDB_PER = 8;                // positions per thread per tile of that scan
+constexpr uint32_t SD_BIG = 4096;         // dirty ranges longer than this go to a workgroup
+// counters: frontier sizes of the two parities, relax total, long ranges
+enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_BIG_CNT = 3, SD_CNT_WORDS = 4 };
 
 struct SDArgs {
     const uint32_t *off_out, *t_out;
@@ -88,6 +96,37 @@ __device__ __forceinline__ uint32_t upper_bound_t(const uint32_t *__restrict__ a
             hi = mid;
     }
     return lo;
+}
+
+// First position in [lo, hi) of a non-increasing run whose value is at most
+// key (hi when none).
+__device__ __forceinline__ uint32_t first_at_most(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t key)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= key)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Out-edges of v departing in [a_p, a_stop) ([a_p + 1, a_stop + 1) under
+// strict succession) and before t_omega: {first, count}.
+__device__ __forceinline__ uint2 changed_out_range(const SDArgs &A, uint32_t v, uint32_t p, uint32_t stop,
+                                                   uint32_t end)
+{
+    const uint32_t ob = A.off_out[v], oe = A.off_out[v + 1];
+    const uint32_t lo = lower_bound_t(A.t_out, ob, oe, A.a_in[p] + A.strict);
+    uint32_t hi_out;
+    if (stop < end) {
+        const uint32_t khi = min(A.a_in[stop] + A.strict, A.tw);
+        hi_out = lower_bound_t(A.t_out, lo, oe, khi);
+    } else {
+        hi_out = A.tw > A.max_t ? oe : lower_bound_t(A.t_out, lo, oe, A.tw);
+    }
+    return make_uint2(lo, hi_out > lo ? hi_out - lo : 0u);
 }
 
 __device__ __forceinline__ uint64_t below_mask()
@@ -187,12 +226,15 @@ __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, u
     }
 }
 
-// One wavefront per frontier vertex v: prefix minimum of pm over v's
-// in-list from its dirty start until it stops changing past the dirty end,
-// then the range of v's out-edges whose candidate can have changed.
+// One wavefront per frontier vertex v: prefix minimum of pm over v's dirty
+// range, then the values past it up to `stop` set to the range's last
+// minimum, then the range of v's out-edges whose candidate can have changed.
+// A dirty range longer than SD_BIG is left whole to sd_expand_big_kernel:
+// its index goes to `big` and rng[i] carries {v, hi, 0, lo}.
 __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur, uint32_t F,
                                                         uint32_t *dlo, uint32_t *dhi, uint4 *rng, uint32_t *rstop,
-                                                        uint32_t *lens, uint32_t *cnt_next)
+                                                        uint32_t *lens, uint32_t *cnt_next, uint32_t *big,
+                                                        uint32_t *big_cnt)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
     const uint32_t lane = threadIdx.x & 63;
@@ -210,46 +252,103 @@ __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t
         }
         p = __shfl(p, 0);
         hi = __shfl(hi, 0);
+        if (hi - p >= SD_BIG) {
+            if (lane == 0) {
+                rng[i] = make_uint4(v, hi, 0u, p);
+                big[atomicAdd(big_cnt, 1u)] = i;
+            }
+            continue;
+        }
         const uint32_t end = A.off_in[v + 1];
         uint32_t carry = p > A.off_in[v] ? A.pm[p - 1] : INF;
-        uint32_t stop = end;
-        for (uint32_t k0 = p; k0 < end; k0 += 64) {
+        for (uint32_t k0 = p; k0 <= hi; k0 += 64) {
             const uint32_t k = k0 + lane;
-            const uint32_t old = k < end ? A.pm[k] : INF;
+            const uint32_t old = k <= hi ? A.pm[k] : INF;
             uint32_t x = old;
             for (int o = 1; o < 64; o <<= 1) {
                 const uint32_t y = __shfl_up(x, o);
                 if (lane >= (uint32_t)o) x = min(x, y);
             }
             x = min(x, carry);
-            // past the dirty end an unchanged value means every later one
-            // is unchanged too
-            const unsigned long long same = __ballot(k < end && k > hi && x == old);
-            const uint32_t first = same ? (uint32_t)__ffsll((long long)same) - 1u : 64u;
-            if (k < end && lane < first && x != old) A.pm[k] = x;
-            if (same) {
-                stop = k0 + first;
-                break;
-            }
+            if (k <= hi && x != old) A.pm[k] = x;
             carry = __shfl(x, 63);
         }
-        // out-edges departing in [a_p, a_stop) ([a_p + 1, a_stop + 1) under
-        // strict succession), and before t_omega
-        const uint32_t ob = A.off_out[v], oe = A.off_out[v + 1];
-        const uint32_t klo = A.a_in[p] + A.strict;
-        const uint32_t lo = lower_bound_t(A.t_out, ob, oe, klo);
-        uint32_t hi_out;
-        if (stop < end) {
-            const uint32_t khi = min(A.a_in[stop] + A.strict, A.tw);
-            hi_out = lower_bound_t(A.t_out, lo, oe, khi);
-        } else {
-            hi_out = A.tw > A.max_t ? oe : lower_bound_t(A.t_out, lo, oe, A.tw);
-        }
+        const uint32_t stop = first_at_most(A.pm, hi + 1, end, carry);
+        for (uint32_t k = hi + 1 + lane; k < stop; k += 64) A.pm[k] = carry;
+        const uint2 oc = changed_out_range(A, v, p, stop, end);
         if (lane == 0) {
-            const uint32_t len = hi_out > lo ? hi_out - lo : 0u;
-            rng[i] = make_uint4(v, lo, len, p);
+            rng[i] = make_uint4(v, oc.x, oc.y, p);
             rstop[i] = stop;
-            lens[i] = len;
+            lens[i] = oc.y;
+        }
+    }
+}
+
+// One workgroup per long dirty range (listed by sd_expand_kernel): the same
+// expansion, the prefix minimum taken tile by tile (SDB * SDB_PER positions
+// through LDS, a run of SDB_PER per thread, a block scan of the runs' minima).
+__global__ __launch_bounds__(SDB) void sd_expand_big_kernel(SDArgs A, const uint32_t *__restrict__ big,
+                                                            const uint32_t *__restrict__ big_cnt, uint4 *rng,
+                                                            uint32_t *rstop, uint32_t *lens)
+{
+    constexpr uint32_t TILE = SDB * SDB_PER;
+    __shared__ uint32_t s_old[TILE];
+    __shared__ uint32_t s_new[TILE];
+    __shared__ uint32_t s_w[SDB / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t nb = *big_cnt;
+    for (uint32_t j = blockIdx.x; j < nb; j += gridDim.x) {
+        const uint32_t i = big[j];
+        const uint4 r = rng[i];
+        const uint32_t v = r.x, hi = r.y, p = r.w;
+        const uint32_t end = A.off_in[v + 1];
+        uint32_t carry = p > A.off_in[v] ? A.pm[p - 1] : INF;
+        for (uint32_t k0 = p; k0 <= hi; k0 += TILE) {
+            const uint32_t cnt = min(TILE, hi + 1 - k0);
+            for (uint32_t q = tid; q < TILE; q += SDB) s_old[q] = q < cnt ? A.pm[k0 + q] : INF;
+            __syncthreads();
+            uint32_t run[SDB_PER];
+            uint32_t m = INF;
+#pragma unroll
+            for (int c = 0; c < SDB_PER; ++c) {
+                run[c] = s_old[tid * SDB_PER + c];
+                m = min(m, run[c]);
+            }
+            // inclusive min-scan of the runs' minima over the wavefront
+            uint32_t x = m;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= (uint32_t)o) x = min(x, y);
+            }
+            if (lane == 63) s_w[w] = x;
+            uint32_t ex = __shfl_up(x, 1);
+            if (lane == 0) ex = INF;
+            __syncthreads();
+            uint32_t pre = carry, tot = carry;
+            for (uint32_t w2 = 0; w2 < SDB / 64; ++w2) {
+                if (w2 < w) pre = min(pre, s_w[w2]);
+                tot = min(tot, s_w[w2]);
+            }
+            pre = min(pre, ex);
+#pragma unroll
+            for (int c = 0; c < SDB_PER; ++c) {
+                pre = min(pre, run[c]);
+                s_new[tid * SDB_PER + c] = pre;
+            }
+            __syncthreads();
+            for (uint32_t q = tid; q < cnt; q += SDB)
+                if (s_new[q] != s_old[q]) A.pm[k0 + q] = s_new[q];
+            carry = tot;
+            __syncthreads();  // the next tile reuses s_old, s_new and s_w
+        }
+        const uint32_t stop = first_at_most(A.pm, hi + 1, end, carry);
+        __syncthreads();  // every wavefront has searched before any fills
+        for (uint32_t k = hi + 1 + tid; k < stop; k += SDB) A.pm[k] = carry;
+        const uint2 oc = changed_out_range(A, v, p, stop, end);
+        if (tid == 0) {
+            rng[i] = make_uint4(v, oc.x, oc.y, p);
+            rstop[i] = stop;
+            lens[i] = oc.y;
         }
     }
 }
@@ -260,8 +359,11 @@ __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, con
                                                        const uint4 *__restrict__ rng,
                                                        const uint32_t *__restrict__ rstop,
                                                        const uint32_t *__restrict__ total_p, uint32_t *dlo,
-                                                       uint32_t *dhi, uint32_t *next, uint32_t *cnt)
+                                                       uint32_t *dhi, uint32_t *next, uint32_t *cnt,
+                                                       uint32_t *big_cnt)
 {
+    // the long-range list is consumed; the next round's expansion refills it
+    if (blockIdx.x == 0 && threadIdx.x == 0) *big_cnt = 0u;
     const uint32_t total = *total_p;
     for (uint32_t j0 = blockIdx.x * SDT; j0 < total; j0 += gridDim.x * SDT) {
         const uint32_t j = j0 + threadIdx.x;
@@ -288,23 +390,44 @@ __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, con
 }
 
 // out[c] for caller vertex c: 0 at the source, else the least label over
-// its in-list (INF when none).  One wavefront per vertex.
+// its in-list (INF when none): the last label of an expanded (non-increasing)
+// list, i.e. of every vertex with out-edges; a minimum over the list for the
+// others, by the lane itself for short lists and by the whole wavefront for
+// lists longer than 32.
 __global__ __launch_bounds__(SDT) void sd_output_kernel(const uint32_t *__restrict__ off_in,
                                                         const uint32_t *__restrict__ pm,
-                                                        const uint32_t *__restrict__ perm, uint32_t n, uint32_t src,
-                                                        uint32_t *__restrict__ out)
+                                                        const uint32_t *__restrict__ perm, uint32_t n,
+                                                        uint32_t n_live, uint32_t src, uint32_t *__restrict__ out)
 {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t waves = gridDim.x * (SDT / 64);
-    for (uint32_t c = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); c < n; c += waves) {
-        const uint32_t v = perm[c];
-        uint32_t x = INF;
-        if (v != src)
-            for (uint32_t k = off_in[v] + lane; k < off_in[v + 1]; k += 64) x = min(x, pm[k]);
-        else
-            x = 0u;
-        for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor(x, o));
-        if (lane == 0) out[c] = x;
+    const uint32_t stride = gridDim.x * SDT;
+    for (uint32_t c0 = blockIdx.x * SDT + (threadIdx.x & ~63u); c0 < n; c0 += stride) {
+        const uint32_t c = c0 + lane;
+        uint32_t x = INF, b = 0, e = 0;
+        bool scan = false;
+        if (c < n) {
+            const uint32_t v = perm[c];
+            b = off_in[v];
+            e = off_in[v + 1];
+            if (v == src) {
+                x = 0u;
+            } else if (v < n_live) {
+                if (e > b) x = pm[e - 1];
+            } else if (e - b <= 32) {
+                for (uint32_t k = b; k < e; ++k) x = min(x, pm[k]);
+            } else {
+                scan = true;
+            }
+        }
+        for (unsigned long long m = __ballot(scan); m; m &= m - 1) {
+            const int l = __ffsll((long long)m) - 1;
+            const uint32_t bl = __shfl(b, l), el = __shfl(e, l);
+            uint32_t y = INF;
+            for (uint32_t k = bl + lane; k < el; k += 64) y = min(y, pm[k]);
+            for (int o = 32; o > 0; o >>= 1) y = min(y, (uint32_t)__shfl_xor(y, o));
+            if (lane == (uint32_t)l) x = y;
+        }
+        if (c < n) out[c] = x;
     }
 }
 
@@ -325,6 +448,7 @@ void sd_state_free(SDState *s)
         dev_free(s->queue[k]);
     }
     dev_free(s->rng);
+    dev_free(s->big);
     dev_free(s->rstop);
     dev_free(s->base);
     dev_free(s->bsum);
@@ -345,6 +469,7 @@ int sd_state_alloc(kairos_graph *g, SDState **out)
         ok = ok && (s->queue[k] = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
     }
     ok = ok && (s->rng = (uint4 *)dev_alloc(n * sizeof(uint4), nullptr)) != nullptr;
+    ok = ok && (s->big = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
     ok = ok && (s->rstop = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
     ok = ok && (s->base = (uint32_t *)dev_alloc((n + 1) * 4, nullptr)) != nullptr;
     ok = ok && (s->bsum = (uint32_t *)dev_alloc(scan_scratch_words(n) * 4, nullptr)) != nullptr;
@@ -444,14 +569,19 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         KAIROS_HIP(hipStreamSynchronize(st));
         uint32_t F = s->h_pin[SD_FRONT];
         uint32_t r = 0;
+        const uint32_t big_grid = (uint32_t)g->num_cus * 2;  // two 1024-thread workgroups per CU
         while (F > 0) {
             const uint32_t p = r & 1u, q = p ^ 1u;
             prof_begin(g, st, &ev);
             hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, cap)), dim3(SDT), 0, st, A, s->queue[p],
-                               F, s->dlo[p], s->dhi[p], s->rng, s->rstop, s->base, s->cnt + SD_FRONT + q);
+                               F, s->dlo[p], s->dhi[p], s->rng, s->rstop, s->base, s->cnt + SD_FRONT + q, s->big,
+                               s->cnt + SD_BIG_CNT);
+            hipLaunchKernelGGL(sd_expand_big_kernel, dim3(std::min<uint32_t>(F, big_grid)), dim3(SDB), 0, st, A,
+                               s->big, s->cnt + SD_BIG_CNT, s->rng, s->rstop, s->base);
             exclusive_scan(st, s->base, F, s->bsum, s->cnt + SD_TOTAL);
             hipLaunchKernelGGL(sd_relax_kernel, dim3(cap), dim3(SDT), 0, st, A, F, s->base, s->rng, s->rstop,
-                               s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q);
+                               s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q,
+                               s->cnt + SD_BIG_CNT);
             prof_end(g, st, KAIROS_K_PUSH, ev);
             KAIROS_HIP(hipGetLastError());
             KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, SD_CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
@@ -466,8 +596,8 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         }
     }
     prof_begin(g, st, &ev);
-    hipLaunchKernelGGL(sd_output_kernel, dim3(grid_for(n, SDT / 64, cap * 4)), dim3(SDT), 0, st, g->off_in, s->pm,
-                       g->perm, n, src_i, out);
+    hipLaunchKernelGGL(sd_output_kernel, dim3(grid_for(n, SDT, cap * 4)), dim3(SDT), 0, st, g->off_in, s->pm,
+                       g->perm, n, g->n_live, src_i, out);
     prof_end(g, st, KAIROS_K_INIT, ev);
     KAIROS_HIP(hipGetLastError());
     return KAIROS_OK;

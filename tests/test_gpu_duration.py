@@ -150,3 +150,40 @@ def test_full_size_scale20_queries():
         got = sd(G, s, a, w)
         assert np.array_equal(got, O.shortest_duration(se, s, a, w)), q
         assert int((got != INF).sum()) > 10000
+
+
+def _hub_graph(T=12000, seed=5):
+    """A hub h whose in-list is lowered across T positions in one round (a
+    dirty range longer than one wavefront expands, spanning two tiles of the
+    workgroup expansion), later in-edges that the first expansion fills, an
+    early arrival of small total that refills the whole list, and a sink
+    without out-edges with more than 32 in-edges."""
+    rng = np.random.default_rng(seed)
+    s, y, w1, c1, h, z = 0, 1, 2, 3, 4, 5
+    u = 6 + np.arange(T)                    # reached from s in round 0
+    up = 6 + T + np.arange(64)              # reached two rounds later
+    x = 6 + T + 64 + np.arange(32)          # the hub's successors
+    n = int(x[-1]) + 1
+    E = []
+    E += [(s, int(u[i]), 10 + i, int(rng.integers(1, 1000))) for i in range(T)]
+    times = rng.permutation(T)
+    E += [(int(u[i]), h, 20000 + int(times[i]), int(rng.integers(1, 50))) for i in range(T)]
+    E += [(int(u[i]), z, 20000 + i, int(rng.integers(1, 50))) for i in range(100)]
+    E += [(s, y, 1, 1), (y, w1, 2, 1), (w1, h, 3, 1)]           # early, total 3
+    E += [(s, c1, 5, 2)] + [(c1, int(up[k]), 6 + k, 3) for k in range(64)]
+    E += [(int(up[k]), h, 50000 + k, int(rng.integers(1, 9))) for k in range(64)]
+    E += [(h, int(x[j]), int(t), int(rng.integers(1, 20))) for j in range(32) for t in (4 + j, 30000 + 97 * j, 60000 + j)]
+    src, dst, t, lam = (np.array([e[k] for e in E], dtype=np.uint32) for k in range(4))
+    return Graph(n, src, dst, t, lam, dict(kind="hub", seed=seed))
+
+
+@pytest.mark.parametrize("strict", [False, True])
+def test_long_dirty_ranges_and_sinks(strict):
+    """Dirty ranges expanded by a workgroup, long fills past the dirty end,
+    and the minimum over a long in-list of a vertex without out-edges."""
+    g, G, se = built("hub", _hub_graph)
+    for s, a, w in ((0, 0, 70000), (0, 0, 40000), (0, 2, 70000), (0, 9, 25000)):
+        print("case: hub", s, a, w, strict, flush=True)
+        got = sd(G, s, a, w, strict)
+        assert np.array_equal(got, O.shortest_duration(se, s, a, w, strict=strict)), (s, a, w)
+    assert int((sd(G, 0, 0, 70000, strict) != INF).sum()) > 12000
