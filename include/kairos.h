@@ -210,9 +210,10 @@ int kairos_earliest_arrival_noalloc(kairos_graph *g, uint32_t src, uint32_t t_al
  * lambda over its edges, of a time-respecting path from src to v within
  * [t_alpha, t_omega]; 0 for src, INF if v is unreachable.  Waiting at a
  * vertex costs nothing, so this differs from fastest (arrival minus
- * departure).  The first call builds, once per graph, a map from each
- * out-edge to the position of the same edge in the in-index (4 bytes per
- * edge, counted by kairos_graph_stats); each query also takes 4 bytes per
+ * departure).  The first call builds, once per graph, two maps from each
+ * out-edge into the in-index: the position of the same edge, and that of the
+ * last in-edge of its tail arriving by its departure (8 bytes per edge in
+ * all, counted by kairos_graph_stats); each query also takes 4 bytes per
  * edge of scratch state, pooled per graph.  KAIROS_STRICT in kairos_query
  * applies "Strictly succeeds" between consecutive edges.
  *   out: device, n uint32.  Errors: INVALID, RANGE, NOMEM, DEVICE. */
@@ -352,9 +353,11 @@ typedef enum kairos_kernel_class {
 typedef struct kairos_profile {
     uint64_t launches[KAIROS_K_COUNT];
     double ms[KAIROS_K_COUNT];   /* summed event time                          */
-    uint64_t edges_scanned;      /* out-edges read by the push kernel (8 B each) */
+    uint64_t edges_scanned;      /* out-edges read by the push kernel (8 B each);
+                                    shortest duration: out-edges relaxed        */
     uint64_t chunk_edges;        /* out-edges read by the chunk kernel (8 B each) */
-    uint64_t items;              /* frontier entries expanded by push          */
+    uint64_t items;              /* frontier entries expanded by push (shortest
+                                    duration: vertices expanded)                */
     uint64_t relaxations;        /* successful atomic minimum updates          */
     uint64_t relax_attempts;     /* atomic minimum updates issued              */
     uint64_t tail_edges;         /* out-edges read by the small-frontier kernel */

@@ -139,7 +139,7 @@ int kairos_graph_stats(const kairos_graph *g, uint32_t *n, uint64_t *m, uint64_t
     if (!g) return KAIROS_ERR_INVALID;
     if (n) *n = g->n;
     if (m) *m = g->m;
-    if (device_bytes) *device_bytes = g->index_bytes + (g->rev ? g->rev->index_bytes : 0) + g->o2i_bytes;
+    if (device_bytes) *device_bytes = g->index_bytes + (g->rev ? g->rev->index_bytes : 0) + g->sd_map_bytes;
     return KAIROS_OK;
 }
 

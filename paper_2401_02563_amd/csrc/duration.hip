@@ -10,7 +10,10 @@
 // minimum pm[k] over that order equals D_v(a_k).  An out-edge f = (v, w, t,
 // lambda) has the candidate D_v(t) + lambda, read at the last in-edge of v
 // arriving by t (before t under "Strictly succeeds"), and lowers pm at f's
-// own position in w's in-list (o2i[f]).
+// own position in w's in-list (o2i[f]).  Both positions depend on the graph
+// alone: o2i[f] and o2k[f] (the last in-edge of v arriving by t; the strict
+// case steps back over in-edges arriving exactly at t) are built once per
+// graph.
 //
 // Label-correcting rounds.  A relaxation that lowers pm at position k of w's
 // in-list widens w's dirty range [lo, hi] for the next round and enqueues w
@@ -31,6 +34,7 @@
 
 #include "internal.h"
 #include "scan.h"
+#include "stage.h"
 
 #include <algorithm>
 #include <cstring>
@@ -44,7 +48,6 @@ struct SDState {
     uint32_t *queue[2] = {nullptr, nullptr};        // n each: frontier vertices
     uint4 *rng = nullptr;                           // n: {v, first out-edge, count, lo}
     uint32_t *big = nullptr;                        // n: frontier indices whose dirty range a workgroup expands
-    uint32_t *rstop = nullptr;                      // n: first in-position past the change
     uint32_t *base = nullptr;                       // n + 1: out-edge counts, then their exclusive scan
     uint32_t *bsum = nullptr;                       // block sums of the scan
     uint32_t *cnt = nullptr;                        // SD_CNT_WORDS counters
@@ -59,6 +62,8 @@ constexpr int SDT = 256;                  // threads per block
 constexpr int SDB = 1024;                 // threads of a workgroup expanding one long dirty range
 constexpr int SDB_PER = 8;                // positions per thread per tile of that scan
 constexpr uint32_t SD_BIG = 4096;         // dirty ranges longer than this go to a workgroup
+constexpr int SD_SCAP = 512;              // staged frontier entries per wavefront
+using SDStage = Stage<SD_SCAP>;
 // counters: frontier sizes of the two parities, relax total, long ranges
 enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_BIG_CNT = 3, SD_CNT_WORDS = 4 };
 
@@ -66,7 +71,7 @@ struct SDArgs {
     const uint32_t *off_out, *t_out;
     const uint2 *da_out;
     const uint32_t *off_in, *a_in;
-    const uint32_t *o2i;
+    const uint32_t *o2i, *o2k;
     uint32_t *pm;
     uint32_t n, n_live, max_t, src, ta, tw, strict;
 };
@@ -129,36 +134,36 @@ __device__ __forceinline__ uint2 changed_out_range(const SDArgs &A, uint32_t v, 
     return make_uint2(lo, hi_out > lo ? hi_out - lo : 0u);
 }
 
-__device__ __forceinline__ uint64_t below_mask()
-{
-    const uint32_t lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
 __global__ __launch_bounds__(SDT) void sd_fill_kernel(uint32_t *p, uint64_t count, uint32_t value)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * SDT + threadIdx.x; i < count; i += (uint64_t)gridDim.x * SDT)
         p[i] = value;
 }
 
-// o2i[f] = position in the in-index of the first in-edge equal to out-edge
-// f in (tail, head, t, a).  Edges equal in all four are interchangeable for
-// every label here, so they may share one position.  One wavefront per tail.
+// o2i[f] = position in the in-index of out-edge f: copies of one edge
+// (equal in tail, head, t and a) sit next to each other in both indexes,
+// and the d-th copy in the out-index takes the d-th in the in-index, so
+// every in-index position belongs to exactly one out-edge.  o2k[f] =
+// position of the last in-edge of f's tail arriving by f's departure (the
+// list's start minus one when none).  One wavefront per tail.
 __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ off_out,
                                                   const uint32_t *__restrict__ t_out,
                                                   const uint2 *__restrict__ da_out,
                                                   const uint32_t *__restrict__ off_in,
                                                   const uint32_t *__restrict__ a_in,
                                                   const uint2 *__restrict__ st_in, uint32_t n_live,
-                                                  uint32_t *__restrict__ o2i, uint32_t *err)
+                                                  uint32_t *__restrict__ o2i, uint32_t *__restrict__ o2k,
+                                                  uint32_t *err)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (SDT / 64);
     for (uint32_t u = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); u < n_live; u += waves) {
         const uint32_t e = off_out[u + 1];
+        const uint32_t ib = off_in[u], ie = off_in[u + 1];
         for (uint32_t f = off_out[u] + lane; f < e; f += 64) {
             const uint2 va = da_out[f];
             const uint32_t t = t_out[f];
+            o2k[f] = upper_bound_t(a_in, ib, ie, t) - 1u;
             uint32_t lo = off_in[va.x], hi = off_in[va.x + 1];
             // in-list order: (a, t, tail)
             while (lo < hi) {
@@ -171,6 +176,12 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
                 else
                     hi = mid;
             }
+            // copies of this edge before it in the out-index
+            uint32_t d = 0;
+            while (f - d > off_out[u] && t_out[f - d - 1] == t && da_out[f - d - 1].x == va.x &&
+                   da_out[f - d - 1].y == va.y)
+                ++d;
+            lo += d;
             // the same edge is in the in-index; anything else is an index
             // fault, reported instead of used
             const bool found = lo < off_in[va.x + 1] && a_in[lo] == va.y && st_in[lo].y == t && st_in[lo].x == u;
@@ -182,26 +193,20 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
 
 // Lowers pm[pos] to `cand`; on success widens the head's dirty range and
 // reports whether this is the range's first entry of the round (then the
-// caller enqueues the head).
+// caller enqueues the head).  Position pos belongs to one out-edge, which a
+// round relaxes at most once, so nothing else writes it meanwhile and a
+// plain store suffices.  Within a round dlo only falls and dhi only rises,
+// so a plain read that already covers pos (even a stale one) makes the
+// atomic unnecessary: the many in-edges of a hub lowered in one round would
+// otherwise queue on its two words.
 __device__ __forceinline__ bool sd_lower(uint32_t *pm, uint32_t pos, uint32_t cand, uint32_t *dlo, uint32_t *dhi,
                                          uint32_t w)
 {
     if (cand >= pm[pos]) return false;
-    if (cand >= atomicMin(&pm[pos], cand)) return false;
-    atomicMax(&dhi[w], pos);
+    pm[pos] = cand;
+    if (pos > __hip_atomic_load(&dhi[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&dhi[w], pos);
+    if (pos >= __hip_atomic_load(&dlo[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
     return atomicMin(&dlo[w], pos) == INF;
-}
-
-// Appends w for every lane with `push` set, one atomicAdd per wavefront.
-// Every lane of the wavefront calls it.
-__device__ __forceinline__ void wave_append(bool push, uint32_t w, uint32_t *next, uint32_t *cnt)
-{
-    const unsigned long long b = __ballot(push);
-    if (!b) return;
-    uint32_t base = 0;
-    if ((threadIdx.x & 63) == 0) base = atomicAdd(cnt, (uint32_t)__popcll(b));
-    base = __shfl(base, 0);
-    if (push) next[base + __popcll(b & below_mask())] = w;
 }
 
 // The source's usable out-edges (t >= t_alpha, a <= t_omega), each a path
@@ -209,6 +214,8 @@ __device__ __forceinline__ void wave_append(bool push, uint32_t w, uint32_t *nex
 __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, uint32_t *dhi, uint32_t *next,
                                                       uint32_t *cnt)
 {
+    __shared__ uint32_t s_stage[SDT / 64][SD_SCAP];
+    SDStage S{s_stage[threadIdx.x >> 6], 0u, next, cnt};
     const uint32_t b = A.off_out[A.src], e = A.off_out[A.src + 1];
     const uint32_t lo = lower_bound_t(A.t_out, b, e, A.ta);
     const uint32_t hi = A.tw > A.max_t ? e : lower_bound_t(A.t_out, lo, e, A.tw);
@@ -222,8 +229,11 @@ __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, u
             if (va.y <= A.tw && w != A.src)
                 push = sd_lower(A.pm, A.o2i[f], va.y - A.t_out[f], dlo, dhi, w) && w < A.n_live;
         }
-        wave_append(push, w, next, cnt);
+        const unsigned long long bal[1] = {__ballot(push)};
+        const uint32_t item[1] = {w};
+        stage_append<SD_SCAP, 1>(S, bal, item);
     }
+    stage_flush_block<SD_SCAP, SDT / 64>(S);
 }
 
 // One wavefront per frontier vertex v: prefix minimum of pm over v's dirty
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, u
 // A dirty range longer than SD_BIG is left whole to sd_expand_big_kernel:
 // its index goes to `big` and rng[i] carries {v, hi, 0, lo}.
 __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur, uint32_t F,
-                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng, uint32_t *rstop,
+                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng,
                                                         uint32_t *lens, uint32_t *cnt_next, uint32_t *big,
                                                         uint32_t *big_cnt)
 {
@@ -278,7 +288,6 @@ __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t
         const uint2 oc = changed_out_range(A, v, p, stop, end);
         if (lane == 0) {
             rng[i] = make_uint4(v, oc.x, oc.y, p);
-            rstop[i] = stop;
             lens[i] = oc.y;
         }
     }
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t
 // through LDS, a run of SDB_PER per thread, a block scan of the runs' minima).
 __global__ __launch_bounds__(SDB) void sd_expand_big_kernel(SDArgs A, const uint32_t *__restrict__ big,
                                                             const uint32_t *__restrict__ big_cnt, uint4 *rng,
-                                                            uint32_t *rstop, uint32_t *lens)
+                                                            uint32_t *lens)
 {
     constexpr uint32_t TILE = SDB * SDB_PER;
     __shared__ uint32_t s_old[TILE];
@@ -347,46 +356,65 @@ __global__ __launch_bounds__(SDB) void sd_expand_big_kernel(SDArgs A, const uint
         const uint2 oc = changed_out_range(A, v, p, stop, end);
         if (tid == 0) {
             rng[i] = make_uint4(v, oc.x, oc.y, p);
-            rstop[i] = stop;
             lens[i] = oc.y;
         }
     }
 }
 
 // One thread per out-edge of the ranges: candidate D_v(t) + lambda into the
-// head's in-list position.
+// head's in-list position.  The range holding a wavefront's first edge comes
+// from one search over the scanned range lengths; each lane's range is then
+// found among the next 64 range starts (a search over the lanes), or, past
+// them (runs of empty ranges), by a search of its own.
 __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, const uint32_t *__restrict__ base,
                                                        const uint4 *__restrict__ rng,
-                                                       const uint32_t *__restrict__ rstop,
                                                        const uint32_t *__restrict__ total_p, uint32_t *dlo,
                                                        uint32_t *dhi, uint32_t *next, uint32_t *cnt,
                                                        uint32_t *big_cnt)
 {
     // the long-range list is consumed; the next round's expansion refills it
     if (blockIdx.x == 0 && threadIdx.x == 0) *big_cnt = 0u;
+    __shared__ uint32_t s_stage[SDT / 64][SD_SCAP];
+    SDStage S{s_stage[threadIdx.x >> 6], 0u, next, cnt};
     const uint32_t total = *total_p;
-    for (uint32_t j0 = blockIdx.x * SDT; j0 < total; j0 += gridDim.x * SDT) {
-        const uint32_t j = j0 + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t jw = blockIdx.x * SDT + (threadIdx.x & ~63u); jw < total; jw += gridDim.x * SDT) {
+        const uint32_t j = jw + lane;
+        const uint32_t i0 = upper_bound_t(base, 0, F, jw) - 1u;
+        const uint32_t nb = i0 + 1 + lane < F ? base[i0 + 1 + lane] : INF;
+        // pos = how many of the 64 starts after i0's are <= j (they ascend)
+        uint32_t pos = 0;
+        for (uint32_t step = 32; step > 0; step >>= 1) {
+            const uint32_t y = __shfl(nb, (int)(pos + step - 1));
+            if (y <= j) pos += step;
+        }
+        const uint32_t y63 = __shfl(nb, 63);
+        if (pos == 63 && y63 <= j) pos = 64;
         bool push = false;
         uint32_t w = 0;
         if (j < total) {
-            const uint32_t i = upper_bound_t(base, 0, F, j) - 1u;  // the range holding edge j
+            const uint32_t i = pos < 64 ? i0 + pos : upper_bound_t(base, i0 + 65, F, j) - 1u;
             const uint4 r = rng[i];
             const uint32_t f = r.y + (j - base[i]);
             const uint2 va = A.da_out[f];
             const uint32_t t = A.t_out[f];
             w = va.x;
             if (va.y <= A.tw && w != A.src) {
-                // last in-edge of v arriving by t (before t when strict);
-                // t lies in [a_lo, a_stop) by construction of the range
-                const uint32_t key = t - A.strict;
-                const uint32_t k = upper_bound_t(A.a_in, r.w, rstop[i], key) - 1u;
+                // last in-edge of v arriving by t (before t when strict); the
+                // range's departures lie in [a_lo, a_stop) (+1 when strict),
+                // so that edge lies in [lo, stop)
+                uint32_t k = A.o2k[f];
+                if (A.strict)
+                    while (A.a_in[k] == t) --k;
                 const uint32_t d = A.pm[k];
                 if (d != INF) push = sd_lower(A.pm, A.o2i[f], d + (va.y - t), dlo, dhi, w) && w < A.n_live;
             }
         }
-        wave_append(push, w, next, cnt);
+        const unsigned long long bal[1] = {__ballot(push)};
+        const uint32_t item[1] = {w};
+        stage_append<SD_SCAP, 1>(S, bal, item);
     }
+    stage_flush_block<SD_SCAP, SDT / 64>(S);
 }
 
 // out[c] for caller vertex c: 0 at the source, else the least label over
@@ -449,7 +477,6 @@ void sd_state_free(SDState *s)
     }
     dev_free(s->rng);
     dev_free(s->big);
-    dev_free(s->rstop);
     dev_free(s->base);
     dev_free(s->bsum);
     dev_free(s->cnt);
@@ -470,7 +497,6 @@ int sd_state_alloc(kairos_graph *g, SDState **out)
     }
     ok = ok && (s->rng = (uint4 *)dev_alloc(n * sizeof(uint4), nullptr)) != nullptr;
     ok = ok && (s->big = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
-    ok = ok && (s->rstop = (uint32_t *)dev_alloc(n * 4, nullptr)) != nullptr;
     ok = ok && (s->base = (uint32_t *)dev_alloc((n + 1) * 4, nullptr)) != nullptr;
     ok = ok && (s->bsum = (uint32_t *)dev_alloc(scan_scratch_words(n) * 4, nullptr)) != nullptr;
     ok = ok && (s->cnt = (uint32_t *)dev_alloc(SD_CNT_WORDS * 4, nullptr)) != nullptr;
@@ -495,15 +521,17 @@ int sd_state_alloc(kairos_graph *g, SDState **out)
     return KAIROS_OK;
 }
 
-// The out-edge -> in-edge position map, built once per graph.
+// The out-edge -> in-edge position maps, built once per graph.
 int ensure_o2i(kairos_graph *g, hipStream_t st)
 {
     std::lock_guard<std::mutex> lk(g->sd_mu);
     if (g->o2i) return KAIROS_OK;
     uint32_t *o2i = (uint32_t *)dev_alloc(std::max<uint64_t>(g->m, 1) * 4, nullptr);
+    uint32_t *o2k = (uint32_t *)dev_alloc(std::max<uint64_t>(g->m, 1) * 4, nullptr);
     uint32_t *err = (uint32_t *)dev_alloc(4, nullptr);
-    if (!o2i || !err) {
+    if (!o2i || !o2k || !err) {
         dev_free(o2i);
+        dev_free(o2k);
         dev_free(err);
         return KAIROS_ERR_NOMEM;
     }
@@ -511,18 +539,21 @@ int ensure_o2i(kairos_graph *g, hipStream_t st)
         uint32_t h_err = 0;
         hipLaunchKernelGGL(sd_fill_kernel, dim3(1), dim3(SDT), 0, st, err, (uint64_t)1, 0u);
         hipLaunchKernelGGL(o2i_kernel, dim3(grid_for(g->n_live, SDT / 64, (uint32_t)g->num_cus * 16)), dim3(SDT), 0,
-                           st, g->off_out, g->t_out, g->da_out, g->off_in, g->a_in, g->st_in, g->n_live, o2i, err);
+                           st, g->off_out, g->t_out, g->da_out, g->off_in, g->a_in, g->st_in, g->n_live, o2i, o2k,
+                           err);
         if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, st) !=
                                                     hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess || h_err != 0) {
             dev_free(o2i);
+            dev_free(o2k);
             dev_free(err);
             return KAIROS_ERR_DEVICE;
         }
     }
     dev_free(err);
     g->o2i = o2i;
-    g->o2i_bytes = std::max<uint64_t>(g->m, 1) * 4;
+    g->o2k = o2k;
+    g->sd_map_bytes = std::max<uint64_t>(g->m, 1) * 8;
     return KAIROS_OK;
 }
 
@@ -539,6 +570,7 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
     A.off_in = g->off_in;
     A.a_in = g->a_in;
     A.o2i = g->o2i;
+    A.o2k = g->o2k;
     A.pm = s->pm;
     A.n = n;
     A.n_live = g->n_live;
@@ -569,23 +601,26 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         KAIROS_HIP(hipStreamSynchronize(st));
         uint32_t F = s->h_pin[SD_FRONT];
         uint32_t r = 0;
+        uint64_t items = 0, edges = 0;
         const uint32_t big_grid = (uint32_t)g->num_cus * 2;  // two 1024-thread workgroups per CU
         while (F > 0) {
             const uint32_t p = r & 1u, q = p ^ 1u;
             prof_begin(g, st, &ev);
-            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, cap)), dim3(SDT), 0, st, A, s->queue[p],
-                               F, s->dlo[p], s->dhi[p], s->rng, s->rstop, s->base, s->cnt + SD_FRONT + q, s->big,
+            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, 2 * cap)), dim3(SDT), 0, st, A, s->queue[p],
+                               F, s->dlo[p], s->dhi[p], s->rng, s->base, s->cnt + SD_FRONT + q, s->big,
                                s->cnt + SD_BIG_CNT);
             hipLaunchKernelGGL(sd_expand_big_kernel, dim3(std::min<uint32_t>(F, big_grid)), dim3(SDB), 0, st, A,
-                               s->big, s->cnt + SD_BIG_CNT, s->rng, s->rstop, s->base);
+                               s->big, s->cnt + SD_BIG_CNT, s->rng, s->base);
             exclusive_scan(st, s->base, F, s->bsum, s->cnt + SD_TOTAL);
-            hipLaunchKernelGGL(sd_relax_kernel, dim3(cap), dim3(SDT), 0, st, A, F, s->base, s->rng, s->rstop,
+            hipLaunchKernelGGL(sd_relax_kernel, dim3(2 * cap), dim3(SDT), 0, st, A, F, s->base, s->rng,
                                s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q,
                                s->cnt + SD_BIG_CNT);
             prof_end(g, st, KAIROS_K_PUSH, ev);
             KAIROS_HIP(hipGetLastError());
             KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, SD_CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
             KAIROS_HIP(hipStreamSynchronize(st));
+            items += F;
+            edges += s->h_pin[SD_TOTAL];
             F = s->h_pin[SD_FRONT + q];
             ++r;
             if (F > n) return KAIROS_ERR_DEVICE;  // a vertex is enqueued at most once per round
@@ -593,6 +628,8 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         if (g->prof.on) {
             std::lock_guard<std::mutex> lk(g->prof.mu);
             g->prof.rounds += r;
+            g->prof.items += items;  // vertices expanded
+            g->prof.edges += edges;  // out-edges relaxed
         }
     }
     prof_begin(g, st, &ev);
@@ -634,8 +671,10 @@ void release_duration_state(kairos_graph *g)
     for (SDState *s : g->sd_states) sd_state_free(s);
     g->sd_states.clear();
     dev_free(g->o2i);
+    dev_free(g->o2k);
     g->o2i = nullptr;
-    g->o2i_bytes = 0;
+    g->o2k = nullptr;
+    g->sd_map_bytes = 0;
 }
 
 }  // namespace kairos

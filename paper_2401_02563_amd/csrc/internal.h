@@ -157,9 +157,11 @@ struct kairos_graph {
     kairos_graph *rev = nullptr;
     std::mutex rev_mu;
     // shortest duration: for each out-edge, the in-index position of the
-    // same edge (built on the first such query), and pooled query state
+    // same edge and that of the last in-edge of its tail arriving by its
+    // departure (built on the first such query), and pooled query state
     uint32_t *o2i = nullptr;
-    uint64_t o2i_bytes = 0;
+    uint32_t *o2k = nullptr;
+    uint64_t sd_map_bytes = 0;
     std::mutex sd_mu;
     std::vector<kairos::SDState *> sd_states;
     // every edge {tail, head, t, a} (internal ids) in departure order, for

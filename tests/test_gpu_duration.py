@@ -131,12 +131,13 @@ def test_edge_cases_and_errors():
     with pytest.raises(K.KairosError) as e:
         K.kairos_shortest_duration(G, 0, 11, 10, out)
     assert e.value.status == 2
-    # the out-edge to in-edge map is counted with the index
+    # the two out-edge to in-index maps (4 B per edge each) are counted with
+    # the index
     _, _, bytes_after = K.kairos_graph_stats(G)
     G.free()
     G = K.kairos_graph_build(*[K.to_u32_tensor(x) for x in (src, dst, t, lam)], 4)
     _, _, bytes_before = K.kairos_graph_stats(G)
-    assert bytes_after == bytes_before + 4 * 3
+    assert bytes_after == bytes_before + 8 * 3
     G.free()
 
 
@@ -156,8 +157,8 @@ def _hub_graph(T=12000, seed=5):
     """A hub h whose in-list is lowered across T positions in one round (a
     dirty range longer than one wavefront expands, spanning two tiles of the
     workgroup expansion), later in-edges that the first expansion fills, an
-    early arrival of small total that refills the whole list, and a sink
-    without out-edges with more than 32 in-edges."""
+    early arrival of small total that refills the whole list, a sink without
+    out-edges with more than 32 in-edges, and exact copies of edges."""
     rng = np.random.default_rng(seed)
     s, y, w1, c1, h, z = 0, 1, 2, 3, 4, 5
     u = 6 + np.arange(T)                    # reached from s in round 0
@@ -173,6 +174,8 @@ def _hub_graph(T=12000, seed=5):
     E += [(s, c1, 5, 2)] + [(c1, int(up[k]), 6 + k, 3) for k in range(64)]
     E += [(int(up[k]), h, 50000 + k, int(rng.integers(1, 9))) for k in range(64)]
     E += [(h, int(x[j]), int(t), int(rng.integers(1, 20))) for j in range(32) for t in (4 + j, 30000 + 97 * j, 60000 + j)]
+    # exact copies of edges (each copy keeps a label of its own)
+    E += E[:40] + E[T:T + 40] + [(w1, h, 3, 1)] * 2 + E[-10:]
     src, dst, t, lam = (np.array([e[k] for e in E], dtype=np.uint32) for k in range(4))
     return Graph(n, src, dst, t, lam, dict(kind="hub", seed=seed))
 
