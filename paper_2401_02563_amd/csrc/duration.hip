@@ -23,8 +23,9 @@
 // values past hi change exactly up to `stop`, the first position past hi
 // holding at most C (a binary search), and there they all become C.  D_v
 // changed exactly on departures in [a_lo, a_stop), so only v's out-edges
-// departing in that interval are relaxed again.  Dirty ranges longer than
-// SD_BIG are expanded by a whole workgroup instead of a wavefront.  Every
+// departing in that interval are relaxed again.  A lane expands one
+// vertex; long scans and fills go to its wavefront, and dirty ranges longer
+// than SD_BIG to a whole workgroup.  Every
 // value is the duration of a real path and values only decrease, so a stale
 // read costs work, never a wrong result.  The source's D is 0 from t_alpha on: its usable out-edges are
 // relaxed once at the start with their own lambda, and it is never expanded.
@@ -62,6 +63,8 @@ constexpr int SDT = 256;                  // threads per block
 constexpr int SDB = 1024;                 // threads of a workgroup expanding one long dirty range
 constexpr int SDB_PER = 8;                // positions per thread per tile of that scan
 constexpr uint32_t SD_BIG = 4096;         // dirty ranges longer than this go to a workgroup
+constexpr uint32_t SD_LANE = 8;           // dirty ranges a lane scans by itself (longer: its wavefront)
+constexpr uint32_t SD_LANE_FILL = 16;     // fills a lane writes by itself (longer: its wavefront)
 constexpr int SD_SCAP = 512;              // staged frontier entries per wavefront
 using SDStage = Stage<SD_SCAP>;
 // counters: frontier sizes of the two parities, relax total, long ranges
@@ -236,57 +239,91 @@ __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, u
     stage_flush_block<SD_SCAP, SDT / 64>(S);
 }
 
-// One wavefront per frontier vertex v: prefix minimum of pm over v's dirty
+// One lane per frontier vertex v: prefix minimum of pm over v's dirty
 // range, then the values past it up to `stop` set to the range's last
 // minimum, then the range of v's out-edges whose candidate can have changed.
-// A dirty range longer than SD_BIG is left whole to sd_expand_big_kernel:
-// its index goes to `big` and rng[i] carries {v, hi, 0, lo}.
+// A lane scans at most SD_LANE and fills at most SD_LANE_FILL positions
+// itself; longer scans and fills are taken by the whole wavefront, one
+// vertex at a time.  A dirty range longer than SD_BIG is left whole to
+// sd_expand_big_kernel: its index goes to `big` and rng[i] carries
+// {v, hi, 0, lo}.
 __global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur, uint32_t F,
-                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng,
-                                                        uint32_t *lens, uint32_t *cnt_next, uint32_t *big,
-                                                        uint32_t *big_cnt)
+                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng, uint32_t *lens,
+                                                        uint32_t *cnt_next, uint32_t *big, uint32_t *big_cnt)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t waves = gridDim.x * (SDT / 64);
-    for (uint32_t i = blockIdx.x * (SDT / 64) + (threadIdx.x >> 6); i < F; i += waves) {
-        const uint32_t v = cur[i];
-        // lane 0 reads the dirty range and cleans it for the round after
-        // next (the relaxations of this round write the other parity)
-        uint32_t p = 0, hi = 0;
-        if (lane == 0) {
+    const uint32_t stride = gridDim.x * SDT;
+    for (uint32_t i0 = blockIdx.x * SDT + (threadIdx.x & ~63u); i0 < F; i0 += stride) {
+        const uint32_t i = i0 + lane;
+        const bool act = i < F;
+        // the dirty range, cleaned for the round after next (the
+        // relaxations of this round write the other parity)
+        uint32_t v = 0, p = 0, hi = 0;
+        if (act) {
+            v = cur[i];
             p = dlo[v];
             hi = dhi[v];
             dlo[v] = INF;
             dhi[v] = 0u;
         }
-        p = __shfl(p, 0);
-        hi = __shfl(hi, 0);
-        if (hi - p >= SD_BIG) {
-            if (lane == 0) {
+        const bool isbig = act && hi - p >= SD_BIG;
+        const unsigned long long bb = __ballot(isbig);
+        if (bb) {
+            uint32_t at = 0;
+            if (lane == 0) at = atomicAdd(big_cnt, (uint32_t)__popcll(bb));
+            at = __shfl(at, 0);
+            if (isbig) {
                 rng[i] = make_uint4(v, hi, 0u, p);
-                big[atomicAdd(big_cnt, 1u)] = i;
+                big[at + __popcll(bb & lanes_below())] = i;
             }
-            continue;
         }
-        const uint32_t end = A.off_in[v + 1];
-        uint32_t carry = p > A.off_in[v] ? A.pm[p - 1] : INF;
-        for (uint32_t k0 = p; k0 <= hi; k0 += 64) {
-            const uint32_t k = k0 + lane;
-            const uint32_t old = k <= hi ? A.pm[k] : INF;
-            uint32_t x = old;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(x, o);
-                if (lane >= (uint32_t)o) x = min(x, y);
+        const bool mine = act && !isbig;
+        uint32_t end = 0, carry = INF;
+        if (mine) {
+            end = A.off_in[v + 1];
+            if (p > A.off_in[v]) carry = A.pm[p - 1];
+        }
+        const bool lane_scan = mine && hi - p < SD_LANE;
+        if (lane_scan) {
+            for (uint32_t k = p; k <= hi; ++k) {
+                const uint32_t old = A.pm[k];
+                if (old < carry)
+                    carry = old;
+                else if (old != carry)
+                    A.pm[k] = carry;
             }
-            x = min(x, carry);
-            if (k <= hi && x != old) A.pm[k] = x;
-            carry = __shfl(x, 63);
         }
-        const uint32_t stop = first_at_most(A.pm, hi + 1, end, carry);
-        for (uint32_t k = hi + 1 + lane; k < stop; k += 64) A.pm[k] = carry;
-        const uint2 oc = changed_out_range(A, v, p, stop, end);
-        if (lane == 0) {
+        for (unsigned long long m = __ballot(mine && !lane_scan); m; m &= m - 1) {
+            const int l = __ffsll((long long)m) - 1;
+            const uint32_t pl = __shfl(p, l), hl = __shfl(hi, l);
+            uint32_t c = __shfl(carry, l);
+            for (uint32_t k0 = pl; k0 <= hl; k0 += 64) {
+                const uint32_t k = k0 + lane;
+                const uint32_t old = k <= hl ? A.pm[k] : INF;
+                uint32_t x = old;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t y = __shfl_up(x, o);
+                    if (lane >= (uint32_t)o) x = min(x, y);
+                }
+                x = min(x, c);
+                if (k <= hl && x != old) A.pm[k] = x;
+                c = __shfl(x, 63);
+            }
+            if (lane == (uint32_t)l) carry = c;
+        }
+        uint32_t stop = 0;
+        if (mine) stop = first_at_most(A.pm, hi + 1, end, carry);
+        const bool lane_fill = mine && stop - hi - 1 <= SD_LANE_FILL;
+        if (lane_fill)
+            for (uint32_t k = hi + 1; k < stop; ++k) A.pm[k] = carry;
+        for (unsigned long long m = __ballot(mine && !lane_fill); m; m &= m - 1) {
+            const int l = __ffsll((long long)m) - 1;
+            const uint32_t h1 = __shfl(hi, l) + 1u, sl = __shfl(stop, l), cl = __shfl(carry, l);
+            for (uint32_t k = h1 + lane; k < sl; k += 64) A.pm[k] = cl;
+        }
+        if (mine) {
+            const uint2 oc = changed_out_range(A, v, p, stop, end);
             rng[i] = make_uint4(v, oc.x, oc.y, p);
             lens[i] = oc.y;
         }
@@ -606,7 +643,7 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         while (F > 0) {
             const uint32_t p = r & 1u, q = p ^ 1u;
             prof_begin(g, st, &ev);
-            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT / 64, 2 * cap)), dim3(SDT), 0, st, A, s->queue[p],
+            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT, 2 * cap)), dim3(SDT), 0, st, A, s->queue[p],
                                F, s->dlo[p], s->dhi[p], s->rng, s->base, s->cnt + SD_FRONT + q, s->big,
                                s->cnt + SD_BIG_CNT);
             hipLaunchKernelGGL(sd_expand_big_kernel, dim3(std::min<uint32_t>(F, big_grid)), dim3(SDB), 0, st, A,
