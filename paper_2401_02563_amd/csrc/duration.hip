@@ -107,13 +107,54 @@ __device__ __forceinline__ uint32_t upper_bound_t(const uint32_t *__restrict__ a
 }
 
 // First position in [lo, hi) of a non-increasing run whose value is at most
-// key (hi when none).
+// key (hi when none).  The answer is usually at or just past lo, so the
+// search gallops from lo (steps 1, 2, 4, ...) before bisecting.
 __device__ __forceinline__ uint32_t first_at_most(const uint32_t *a, uint32_t lo, uint32_t hi, uint32_t key)
 {
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (lo >= hi || a[lo] <= key) return lo;
+    uint32_t b, step = 1;
+    for (;;) {  // a[lo] > key; the answer lies in (lo, b]
+        if (step >= hi - lo) {
+            b = hi;
+            break;
+        }
+        b = lo + step;
+        if (a[b] <= key) break;
+        lo = b;
+        step <<= 1;
+    }
+    ++lo;
+    while (lo < b) {
+        const uint32_t mid = lo + ((b - lo) >> 1);
         if (a[mid] <= key)
-            hi = mid;
+            b = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// lower_bound_t galloping from lo, for answers expected near lo.
+__device__ __forceinline__ uint32_t gallop_lower_bound(const uint32_t *__restrict__ a, uint32_t lo, uint32_t hi,
+                                                       uint32_t key)
+{
+    if (lo >= hi || a[lo] >= key) return lo;
+    uint32_t b, step = 1;
+    for (;;) {  // a[lo] < key; the answer lies in (lo, b]
+        if (step >= hi - lo) {
+            b = hi;
+            break;
+        }
+        b = lo + step;
+        if (a[b] >= key) break;
+        lo = b;
+        step <<= 1;
+    }
+    ++lo;
+    while (lo < b) {
+        const uint32_t mid = lo + ((b - lo) >> 1);
+        if (a[mid] >= key)
+            b = mid;
         else
             lo = mid + 1;
     }
@@ -130,9 +171,9 @@ __device__ __forceinline__ uint2 changed_out_range(const SDArgs &A, uint32_t v, 
     uint32_t hi_out;
     if (stop < end) {
         const uint32_t khi = min(A.a_in[stop] + A.strict, A.tw);
-        hi_out = lower_bound_t(A.t_out, lo, oe, khi);
+        hi_out = gallop_lower_bound(A.t_out, lo, oe, khi);
     } else {
-        hi_out = A.tw > A.max_t ? oe : lower_bound_t(A.t_out, lo, oe, A.tw);
+        hi_out = A.tw > A.max_t ? oe : gallop_lower_bound(A.t_out, lo, oe, A.tw);
     }
     return make_uint2(lo, hi_out > lo ? hi_out - lo : 0u);
 }
