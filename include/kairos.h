@@ -251,8 +251,9 @@ typedef struct kairos_tuning {
     uint32_t pull_alpha;     /* pull when frontier out-edges > m / pull_alpha;
                                 0 disables the pull kernel                          */
     uint32_t pull_beta;      /* back to push when frontier < n / pull_beta          */
-    uint32_t rounds_per_sync;/* push rounds queued before the host checks the
-                                frontier (1 = check every round)                    */
+    uint32_t rounds_per_sync;/* push rounds (and shortest-duration rounds)
+                                queued before the host checks the frontier
+                                (1 = check every round)                             */
     uint32_t batch_persistent; /* 1: a lane-dense batch (batch_layout 2) runs all
                                   its rounds in one cooperative launch with grid
                                   barriers and stops on the device; 0: one

@@ -288,10 +288,12 @@ __global__ __launch_bounds__(SDT) void sd_seed_kernel(SDArgs A, uint32_t *dlo, u
 // vertex at a time.  A dirty range longer than SD_BIG is left whole to
 // sd_expand_big_kernel: its index goes to `big` and rng[i] carries
 // {v, hi, 0, lo}.
-__global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur, uint32_t F,
-                                                        uint32_t *dlo, uint32_t *dhi, uint4 *rng, uint32_t *lens,
-                                                        uint32_t *cnt_next, uint32_t *big, uint32_t *big_cnt)
+__global__ __launch_bounds__(SDT) void sd_expand_kernel(SDArgs A, const uint32_t *__restrict__ cur,
+                                                        const uint32_t *F_p, uint32_t *dlo, uint32_t *dhi,
+                                                        uint4 *rng, uint32_t *lens, uint32_t *cnt_next,
+                                                        uint32_t *big, uint32_t *big_cnt)
 {
+    const uint32_t F = min(*F_p, A.n);
     if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_next = 0u;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t stride = gridDim.x * SDT;
@@ -444,7 +446,8 @@ __global__ __launch_bounds__(SDB) void sd_expand_big_kernel(SDArgs A, const uint
 // from one search over the scanned range lengths; each lane's range is then
 // found among the next 64 range starts (a search over the lanes), or, past
 // them (runs of empty ranges), by a search of its own.
-__global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, const uint32_t *__restrict__ base,
+__global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, const uint32_t *__restrict__ F_p,
+                                                       const uint32_t *__restrict__ base,
                                                        const uint4 *__restrict__ rng,
                                                        const uint32_t *__restrict__ total_p, uint32_t *dlo,
                                                        uint32_t *dhi, uint32_t *next, uint32_t *cnt,
@@ -454,6 +457,7 @@ __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, uint32_t F, con
     if (blockIdx.x == 0 && threadIdx.x == 0) *big_cnt = 0u;
     __shared__ uint32_t s_stage[SDT / 64][SD_SCAP];
     SDStage S{s_stage[threadIdx.x >> 6], 0u, next, cnt};
+    const uint32_t F = min(*F_p, A.n);
     const uint32_t total = *total_p;
     const uint32_t lane = threadIdx.x & 63;
     for (uint32_t jw = blockIdx.x * SDT + (threadIdx.x & ~63u); jw < total; jw += gridDim.x * SDT) {
@@ -681,27 +685,33 @@ int run_sd(kairos_graph *g, SDState *s, uint32_t src, uint32_t ta, uint32_t tw, 
         uint32_t r = 0;
         uint64_t items = 0, edges = 0;
         const uint32_t big_grid = (uint32_t)g->num_cus * 2;  // two 1024-thread workgroups per CU
+        const uint32_t egrid = grid_for(n, SDT, 2 * cap);   // a lane per frontier vertex
+        // rounds queued per host check; a round whose frontier is empty
+        // ends at once, and so do the queued ones after it (with work
+        // counters on, every round is checked, for exact counts)
+        const uint32_t R = g->prof.on ? 1u : std::max<uint32_t>(1, g->tuning.rounds_per_sync);
         while (F > 0) {
-            const uint32_t p = r & 1u, q = p ^ 1u;
-            prof_begin(g, st, &ev);
-            hipLaunchKernelGGL(sd_expand_kernel, dim3(grid_for(F, SDT, 2 * cap)), dim3(SDT), 0, st, A, s->queue[p],
-                               F, s->dlo[p], s->dhi[p], s->rng, s->base, s->cnt + SD_FRONT + q, s->big,
-                               s->cnt + SD_BIG_CNT);
-            hipLaunchKernelGGL(sd_expand_big_kernel, dim3(std::min<uint32_t>(F, big_grid)), dim3(SDB), 0, st, A,
-                               s->big, s->cnt + SD_BIG_CNT, s->rng, s->base);
-            exclusive_scan(st, s->base, F, s->bsum, s->cnt + SD_TOTAL);
-            hipLaunchKernelGGL(sd_relax_kernel, dim3(2 * cap), dim3(SDT), 0, st, A, F, s->base, s->rng,
-                               s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q,
-                               s->cnt + SD_BIG_CNT);
-            prof_end(g, st, KAIROS_K_PUSH, ev);
-            KAIROS_HIP(hipGetLastError());
+            if (F > n) return KAIROS_ERR_DEVICE;  // a vertex is enqueued at most once per round
+            items += F;
+            for (uint32_t k = 0; k < R; ++k, ++r) {
+                const uint32_t p = r & 1u, q = p ^ 1u;
+                uint32_t *Fp = s->cnt + SD_FRONT + p;
+                prof_begin(g, st, &ev);
+                hipLaunchKernelGGL(sd_expand_kernel, dim3(egrid), dim3(SDT), 0, st, A, s->queue[p], Fp, s->dlo[p],
+                                   s->dhi[p], s->rng, s->base, s->cnt + SD_FRONT + q, s->big, s->cnt + SD_BIG_CNT);
+                hipLaunchKernelGGL(sd_expand_big_kernel, dim3(big_grid), dim3(SDB), 0, st, A, s->big,
+                                   s->cnt + SD_BIG_CNT, s->rng, s->base);
+                exclusive_scan_dev(st, s->base, n, Fp, s->bsum, s->cnt + SD_TOTAL);
+                hipLaunchKernelGGL(sd_relax_kernel, dim3(2 * cap), dim3(SDT), 0, st, A, Fp, s->base, s->rng,
+                                   s->cnt + SD_TOTAL, s->dlo[q], s->dhi[q], s->queue[q], s->cnt + SD_FRONT + q,
+                                   s->cnt + SD_BIG_CNT);
+                prof_end(g, st, KAIROS_K_PUSH, ev);
+                KAIROS_HIP(hipGetLastError());
+            }
             KAIROS_HIP(hipMemcpyAsync(s->h_pin, s->cnt, SD_CNT_WORDS * 4, hipMemcpyDeviceToHost, st));
             KAIROS_HIP(hipStreamSynchronize(st));
-            items += F;
-            edges += s->h_pin[SD_TOTAL];
-            F = s->h_pin[SD_FRONT + q];
-            ++r;
-            if (F > n) return KAIROS_ERR_DEVICE;  // a vertex is enqueued at most once per round
+            edges += s->h_pin[SD_TOTAL];  // the last queued round's (every round's when R = 1)
+            F = s->h_pin[SD_FRONT + (r & 1u)];
         }
         if (g->prof.on) {
             std::lock_guard<std::mutex> lk(g->prof.mu);

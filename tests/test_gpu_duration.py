@@ -190,3 +190,30 @@ def test_long_dirty_ranges_and_sinks(strict):
         got = sd(G, s, a, w, strict)
         assert np.array_equal(got, O.shortest_duration(se, s, a, w, strict=strict)), (s, a, w)
     assert int((sd(G, 0, 0, 70000, strict) != INF).sum()) > 12000
+
+
+@pytest.mark.parametrize("rps", [1, 3])
+def test_rounds_per_check_and_counters(rps):
+    """Rounds checked one at a time or queued three per host check, with
+    work counters off and on (on: every round is checked), give the same
+    labels."""
+    g, G, se = built("bursty16", lambda: make_graph("bursty22-1b", scale_shift=6))
+    srcs, ta, tw = make_queries("bursty22-1b", g, count=3)
+    old = K.kairos_get_tuning(G)
+    K.kairos_set_tuning(G, rounds_per_sync=rps)
+    try:
+        for i in range(len(srcs)):
+            s, a, w = int(srcs[i]), int(ta[i]), int(tw[i])
+            want = O.shortest_duration(se, s, a, w)
+            print("case: rounds per check", rps, i, flush=True)
+            assert np.array_equal(sd(G, s, a, w), want), i
+            K.kairos_profile_enable(G, True)
+            K.kairos_profile_read(G)
+            got = sd(G, s, a, w)
+            prof = K.kairos_profile_read(G)
+            K.kairos_profile_enable(G, False)
+            assert np.array_equal(got, want), i
+            if int((want != INF).sum()) > 1:
+                assert prof["rounds"] > 0 and prof["items"] > 0 and prof["edges_scanned"] > 0, prof
+    finally:
+        K.kairos_set_tuning(G, **old)
