@@ -66,6 +66,7 @@ constexpr uint32_t SD_BIG = 4096;         // dirty ranges longer than this go to
 constexpr uint32_t SD_LANE = 8;           // dirty ranges a lane scans by itself (longer: its wavefront)
 constexpr uint32_t SD_LANE_FILL = 16;     // fills a lane writes by itself (longer: its wavefront)
 constexpr int SD_SCAP = 512;              // staged frontier entries per wavefront
+constexpr int SD_U = 4;                   // out-edges per lane per pass of the relaxation loop
 using SDStage = Stage<SD_SCAP>;
 // counters: frontier sizes of the two parities, relax total, long ranges
 enum : int { SD_FRONT = 0, SD_TOTAL = 2, SD_BIG_CNT = 3, SD_CNT_WORDS = 4 };
@@ -243,14 +244,19 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
 // so a plain read that already covers pos (even a stale one) makes the
 // atomic unnecessary: the many in-edges of a hub lowered in one round would
 // otherwise queue on its two words.
+__device__ __forceinline__ bool sd_mark(uint32_t *dlo, uint32_t *dhi, uint32_t w, uint32_t pos)
+{
+    if (pos > __hip_atomic_load(&dhi[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&dhi[w], pos);
+    if (pos >= __hip_atomic_load(&dlo[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    return atomicMin(&dlo[w], pos) == INF;
+}
+
 __device__ __forceinline__ bool sd_lower(uint32_t *pm, uint32_t pos, uint32_t cand, uint32_t *dlo, uint32_t *dhi,
                                          uint32_t w)
 {
     if (cand >= pm[pos]) return false;
     pm[pos] = cand;
-    if (pos > __hip_atomic_load(&dhi[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&dhi[w], pos);
-    if (pos >= __hip_atomic_load(&dlo[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    return atomicMin(&dlo[w], pos) == INF;
+    return sd_mark(dlo, dhi, w, pos);
 }
 
 // The source's usable out-edges (t >= t_alpha, a <= t_omega), each a path
@@ -441,11 +447,13 @@ __global__ __launch_bounds__(SDB) void sd_expand_big_kernel(SDArgs A, const uint
     }
 }
 
-// One thread per out-edge of the ranges: candidate D_v(t) + lambda into the
+// One thread per out-edge of the ranges, SD_U of them per lane per pass (a
+// wavefront takes 64 * SD_U consecutive edges and issues each step's loads
+// for all of them before using any): candidate D_v(t) + lambda into the
 // head's in-list position.  The range holding a wavefront's first edge comes
-// from one search over the scanned range lengths; each lane's range is then
+// from one search over the scanned range lengths; each edge's range is then
 // found among the next 64 range starts (a search over the lanes), or, past
-// them (runs of empty ranges), by a search of its own.
+// them (runs of empty or short ranges), by a search of its own.
 __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, const uint32_t *__restrict__ F_p,
                                                        const uint32_t *__restrict__ base,
                                                        const uint4 *__restrict__ rng,
@@ -460,41 +468,79 @@ __global__ __launch_bounds__(SDT) void sd_relax_kernel(SDArgs A, const uint32_t 
     const uint32_t F = min(*F_p, A.n);
     const uint32_t total = *total_p;
     const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t jw = blockIdx.x * SDT + (threadIdx.x & ~63u); jw < total; jw += gridDim.x * SDT) {
-        const uint32_t j = jw + lane;
+    const uint64_t stride = (uint64_t)gridDim.x * SDT * SD_U;
+    for (uint64_t jw64 = (uint64_t)(blockIdx.x * SDT + (threadIdx.x & ~63u)) * SD_U; jw64 < total; jw64 += stride) {
+        const uint32_t jw = (uint32_t)jw64;
         const uint32_t i0 = upper_bound_t(base, 0, F, jw) - 1u;
         const uint32_t nb = i0 + 1 + lane < F ? base[i0 + 1 + lane] : INF;
-        // pos = how many of the 64 starts after i0's are <= j (they ascend)
-        uint32_t pos = 0;
-        for (uint32_t step = 32; step > 0; step >>= 1) {
-            const uint32_t y = __shfl(nb, (int)(pos + step - 1));
-            if (y <= j) pos += step;
-        }
         const uint32_t y63 = __shfl(nb, 63);
-        if (pos == 63 && y63 <= j) pos = 64;
-        bool push = false;
-        uint32_t w = 0;
-        if (j < total) {
-            const uint32_t i = pos < 64 ? i0 + pos : upper_bound_t(base, i0 + 65, F, j) - 1u;
-            const uint4 r = rng[i];
-            const uint32_t f = r.y + (j - base[i]);
-            const uint2 va = A.da_out[f];
-            const uint32_t t = A.t_out[f];
-            w = va.x;
-            if (va.y <= A.tw && w != A.src) {
-                // last in-edge of v arriving by t (before t when strict); the
-                // range's departures lie in [a_lo, a_stop) (+1 when strict),
-                // so that edge lies in [lo, stop)
-                uint32_t k = A.o2k[f];
-                if (A.strict)
-                    while (A.a_in[k] == t) --k;
-                const uint32_t d = A.pm[k];
-                if (d != INF) push = sd_lower(A.pm, A.o2i[f], d + (va.y - t), dlo, dhi, w) && w < A.n_live;
+        uint32_t j[SD_U], ri[SD_U];
+        bool act[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+            j[u] = jw + (uint32_t)u * 64u + lane;
+            act[u] = jw64 + (uint64_t)u * 64u + lane < total;
+            // how many of the 64 starts after i0's are <= j (they ascend)
+            uint32_t pos = 0;
+            for (uint32_t step = 32; step > 0; step >>= 1) {
+                const uint32_t y = __shfl(nb, (int)(pos + step - 1));
+                if (y <= j[u]) pos += step;
+            }
+            if (pos == 63 && y63 <= j[u]) pos = 64;
+            ri[u] = i0 + pos;
+            if (act[u] && pos == 64) ri[u] = upper_bound_t(base, i0 + 65, F, j[u]) - 1u;
+        }
+        uint32_t f[SD_U], rb[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+            f[u] = act[u] ? rng[ri[u]].y : 0u;
+            rb[u] = act[u] ? base[ri[u]] : 0u;
+        }
+        uint2 va[SD_U];
+        uint32_t t[SD_U], k[SD_U], oi[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+            f[u] += j[u] - rb[u];
+            va[u] = make_uint2(0u, 0u);
+            t[u] = k[u] = oi[u] = 0u;
+            if (act[u]) {
+                va[u] = A.da_out[f[u]];
+                t[u] = A.t_out[f[u]];
+                k[u] = A.o2k[f[u]];
+                oi[u] = A.o2i[f[u]];
             }
         }
-        const unsigned long long bal[1] = {__ballot(push)};
-        const uint32_t item[1] = {w};
-        stage_append<SD_SCAP, 1>(S, bal, item);
+        bool ok[SD_U];
+        uint32_t d[SD_U], old[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+            ok[u] = act[u] && va[u].y <= A.tw && va[u].x != A.src;
+            // last in-edge of v arriving by t (before t when strict); the
+            // range's departures lie in [a_lo, a_stop) (+1 when strict), so
+            // that edge lies in [lo, stop)
+            if (ok[u] && A.strict)
+                while (A.a_in[k[u]] == t[u]) --k[u];
+            d[u] = ok[u] ? A.pm[k[u]] : INF;
+            old[u] = ok[u] ? A.pm[oi[u]] : 0u;
+        }
+        // the label at oi has one writer per round (its edge), so a plain
+        // store lowers it
+        uint32_t w[SD_U];
+        unsigned long long bal[SD_U];
+#pragma unroll
+        for (int u = 0; u < SD_U; ++u) {
+            w[u] = va[u].x;
+            bool push = false;
+            if (ok[u] && d[u] != INF) {
+                const uint32_t cand = d[u] + (va[u].y - t[u]);
+                if (cand < old[u]) {
+                    A.pm[oi[u]] = cand;
+                    push = sd_mark(dlo, dhi, w[u], oi[u]) && w[u] < A.n_live;
+                }
+            }
+            bal[u] = __ballot(push);
+        }
+        stage_append<SD_SCAP, SD_U>(S, bal, w);
     }
     stage_flush_block<SD_SCAP, SDT / 64>(S);
 }
