@@ -163,7 +163,9 @@ __device__ __forceinline__ uint32_t gallop_lower_bound(const uint32_t *__restric
 }
 
 // Out-edges of v departing in [a_p, a_stop) ([a_p + 1, a_stop + 1) under
-// strict succession) and before t_omega: {first, count}.
+// strict succession) and before t_omega: {first, count}.  Arrivals are at
+// most TMAX = 2^32 - 2 (the index rejects larger ones), so a + 1 does not
+// wrap.
 __device__ __forceinline__ uint2 changed_out_range(const SDArgs &A, uint32_t v, uint32_t p, uint32_t stop,
                                                    uint32_t end)
 {
@@ -236,14 +238,12 @@ __global__ __launch_bounds__(SDT) void o2i_kernel(const uint32_t *__restrict__ o
     }
 }
 
-// Lowers pm[pos] to `cand`; on success widens the head's dirty range and
-// reports whether this is the range's first entry of the round (then the
-// caller enqueues the head).  Position pos belongs to one out-edge, which a
-// round relaxes at most once, so nothing else writes it meanwhile and a
-// plain store suffices.  Within a round dlo only falls and dhi only rises,
-// so a plain read that already covers pos (even a stale one) makes the
-// atomic unnecessary: the many in-edges of a hub lowered in one round would
-// otherwise queue on its two words.
+// Widens head w's dirty range to cover pos and reports whether this is the
+// range's first entry of the round (then the caller enqueues w).  Within a
+// round dlo only falls and dhi only rises, so a plain read that already
+// covers pos (even a stale one) makes the atomic unnecessary: the many
+// in-edges of a hub lowered in one round would otherwise queue on its two
+// words.
 __device__ __forceinline__ bool sd_mark(uint32_t *dlo, uint32_t *dhi, uint32_t w, uint32_t pos)
 {
     if (pos > __hip_atomic_load(&dhi[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&dhi[w], pos);
@@ -251,6 +251,9 @@ __device__ __forceinline__ bool sd_mark(uint32_t *dlo, uint32_t *dhi, uint32_t w
     return atomicMin(&dlo[w], pos) == INF;
 }
 
+// Lowers pm[pos] to `cand` and, on success, marks it as sd_mark does.
+// Position pos belongs to one out-edge, which a round relaxes at most once,
+// so nothing else writes it meanwhile and a plain store suffices.
 __device__ __forceinline__ bool sd_lower(uint32_t *pm, uint32_t pos, uint32_t cand, uint32_t *dlo, uint32_t *dhi,
                                          uint32_t w)
 {
