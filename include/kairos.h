@@ -214,7 +214,8 @@ int kairos_earliest_arrival_noalloc(kairos_graph *g, uint32_t src, uint32_t t_al
  * out-edge into the in-index: the position of the same edge, and that of the
  * last in-edge of its tail arriving by its departure (8 bytes per edge in
  * all, counted by kairos_graph_stats); each query also takes 4 bytes per
- * edge of scratch state, pooled per graph.  KAIROS_STRICT in kairos_query
+ * edge and 48 bytes per vertex of scratch state, pooled per graph (one set
+ * per concurrent caller).  KAIROS_STRICT in kairos_query
  * applies "Strictly succeeds" between consecutive edges.
  *   out: device, n uint32.  Errors: INVALID, RANGE, NOMEM, DEVICE. */
 int kairos_shortest_duration(kairos_graph *g, uint32_t src, uint32_t t_alpha, uint32_t t_omega,
